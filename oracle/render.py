@@ -1,0 +1,343 @@
+"""Brute-force float64 projection, compositing, loss and gradients (oracle; tests only).
+
+Definitions (AgriGS-SLAM, Sec. III-B and III-C; constants from `RenderSettings`):
+
+Projection of Gaussian i into view b (Sec. III-B):
+    x_c = R_b mu + t_b, z = x_c.z; culled if z < z_near
+    Sigma = R(q) diag(e^{2s}) R(q)^T
+    J = [[fx/z, 0, -fx tx/z^2], [0, fy/z, -fy ty/z^2]], tx = z clamp(x/z, +-1.3 W/(2 fx)), ty alike
+    Sigma' = J R_b Sigma R_b^T J^T + blur I   (top-left 2x2 block of J W Sigma W^T J^T)
+    conic = Sigma'^{-1}; culled if det Sigma' <= 0
+    (u, v) = (fx x/z + cx, fy y/z + cy)
+    o = sigmoid(omega); culled if o < alpha_min
+    rgb = max(0, sum_k Y_k(d) f_k + 1/2), d = unit vector from the camera centre to mu
+
+Compositing at pixel (px, py), centre (px + 0.5, py + 0.5), over *all* surviving Gaussians:
+    power = -1/2 (a dx^2 + c dy^2) - b dx dy with (dx, dy) = (u, v) - centre
+    alpha = min(alpha_max, o e^power); kept if power <= 0 and alpha >= alpha_min
+    kept Gaussians ordered by (float32(z), i); T = 1; for each: T' = T (1 - alpha);
+    if T' < t_min stop (this one excluded); w = alpha T; C += w rgb; D += w z; A += w; T = T'
+    outputs C + T bg, D (expected depth, unnormalised), A, T_final.
+
+Loss (Sec. III-C), summed over views b:
+    w_l1 / (3 n_b) sum_{p in mask} sum_ch |C - C_gt|
+  + lambda_L / |Omega_b| sum_{u in Omega_b} KL(N(D_L(u), sigma_L^2) || N(mu_u, sigma_u^2)),
+    mu_u = D(u), sigma_u = sigma_L (fixed-variance reading).
+
+Gradients: torch float64 autograd through projection and compositing with every discrete
+decision (kept sets, order, stop index, alpha clamp) frozen from the forward pass; the pose
+gradient is with respect to a left perturbation W_b <- Exp(delta_b) W_b, delta = (rho, phi).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .geometry import covariance_3d, se3_exp_torch
+from .settings import RenderSettings
+from .sh import real_sh
+
+DT = torch.float64
+
+
+def kl_normal(m1, s1, m2, s2):
+    """KL( N(m1, s1^2) || N(m2, s2^2) ) for univariate normals (elementwise)."""
+    return torch.log(s2 / s1) + (s1 * s1 + (m1 - m2) ** 2) / (2 * s2 * s2) - 0.5
+
+
+def leaves(scene, requires_grad=True, deltas=None):
+    """float64 copies of the scene's parameters, as autograd leaves.  `deltas` (B, 6) are
+    the pose perturbations at which to evaluate (default 0)."""
+    p = {
+        "means": torch.tensor(scene.means, dtype=DT),
+        "log_scales": torch.tensor(scene.log_scales, dtype=DT),
+        "quats": torch.tensor(scene.quats, dtype=DT),
+        "opacity_logits": torch.tensor(scene.opacity_logits, dtype=DT),
+        "sh": torch.tensor(scene.sh, dtype=DT),
+        "pose_delta": (torch.zeros(len(scene.cameras), 6, dtype=DT) if deltas is None
+                       else torch.tensor(np.asarray(deltas, np.float64))),
+    }
+    for v in p.values():
+        v.requires_grad_(requires_grad)
+    return p
+
+
+def camera_pose(cam, delta):
+    """World->camera (R, t) after the left perturbation Exp(delta) (float64, differentiable)."""
+    R0 = torch.tensor(cam.R, dtype=DT)
+    t0 = torch.tensor(cam.t, dtype=DT)
+    Rd, td = se3_exp_torch(delta)
+    return Rd @ R0, Rd @ t0 + td
+
+
+def project(p, cam, delta, s: RenderSettings, sh_degree: int):
+    """Project Gaussians [g_begin, g_end) of the parameters into camera `cam`.
+
+    Returns a dict of per-Gaussian tensors (differentiable where continuous) and the bool
+    mask `valid` (culling decisions)."""
+    g0, g1 = cam.g_begin, cam.g_end
+    mu = p["means"][g0:g1]
+    R, t = camera_pose(cam, delta)
+    xc = mu @ R.T + t
+    z = xc[:, 2]
+    valid = (z >= s.z_near).detach()
+    zs = torch.where(valid, z, torch.ones_like(z))  # keep culled entries finite
+    x, y = xc[:, 0], xc[:, 1]
+    limx = s.fov_clamp * cam.width / (2.0 * cam.fx)
+    limy = s.fov_clamp * cam.height / (2.0 * cam.fy)
+    tx = torch.clamp(x / zs, -limx, limx) * zs
+    ty = torch.clamp(y / zs, -limy, limy) * zs
+    zero = torch.zeros_like(zs)
+    J = torch.stack([torch.stack([cam.fx / zs, zero, -cam.fx * tx / (zs * zs)], -1),
+                     torch.stack([zero, cam.fy / zs, -cam.fy * ty / (zs * zs)], -1)], -2)
+    Sigma = covariance_3d(p["log_scales"][g0:g1], p["quats"][g0:g1])
+    Sigma_c = R @ Sigma @ R.T
+    S2 = J @ Sigma_c @ J.transpose(-1, -2)
+    S2 = S2 + s.blur * torch.eye(2, dtype=DT)
+    a, b, c = S2[:, 0, 0], S2[:, 0, 1], S2[:, 1, 1]
+    det = a * c - b * b
+    valid = valid & (det > 0).detach()
+    dets = torch.where(valid, det, torch.ones_like(det))
+    conic = torch.stack([c / dets, -b / dets, a / dets], -1)
+    u = cam.fx * x / zs + cam.cx
+    v = cam.fy * y / zs + cam.cy
+    o = torch.sigmoid(p["opacity_logits"][g0:g1])
+    valid = valid & (o >= s.alpha_min).detach()
+    centre = -(R.T @ t)
+    dvec = mu - centre
+    d = dvec / torch.linalg.norm(dvec, dim=-1, keepdim=True)
+    Y = real_sh(sh_degree, d)                       # (n, K)
+    raw = torch.einsum("nk,nkc->nc", Y, p["sh"][g0:g1]) + 0.5
+    rgb = torch.clamp(raw, min=0.0)
+    # footprint bounding half-extents (for the binning reference and diagnostics)
+    with torch.no_grad():
+        lnterm = torch.where(valid, 2.0 * torch.log(255.0 * o.clamp_min(1e-30)), zero)
+        ext = torch.stack([torch.sqrt(lnterm.clamp_min(0) * a), torch.sqrt(lnterm.clamp_min(0) * c)], -1)
+    return {"u": u, "v": v, "conic": conic, "o": o, "rgb": rgb, "z": z, "valid": valid,
+            "cov2d": S2, "ext": ext, "g0": g0}
+
+
+@dataclass
+class Decisions:
+    """Frozen per-pixel compositing decisions for a set of pixels of one view."""
+    idx: np.ndarray        # (P, Kmax) int64 local Gaussian indices in composite order, -1 pad
+    clamped: np.ndarray    # (P, Kmax) bool: alpha took the alpha_max clamp
+    count: np.ndarray      # (P,) number of contributors
+    ambiguous: np.ndarray  # (P,) bool: a decision lies within the FP32-vs-FP64 margin
+    touched: list          # per pixel: local indices processed (contributors + stopper)
+
+
+def composite_decisions(proj, px, py, s: RenderSettings, rel_margin=1e-5, ulps=4,
+                        budget=4_000_000) -> Decisions:
+    """Brute force over every valid Gaussian for each pixel: which Gaussians contribute and
+    in what order.  Also flags pixels whose result depends on a decision that float32
+    rounding could flip (alpha near alpha_min or alpha_max, T' near t_min, near-equal
+    depths among processed Gaussians)."""
+    with torch.no_grad():
+        vidx = torch.nonzero(proj["valid"]).flatten()
+        u = proj["u"][vidx]
+        v = proj["v"][vidx]
+        A, B, C = proj["conic"][vidx].unbind(-1)
+        o = proj["o"][vidx]
+        z64 = proj["z"][vidx].numpy()
+    z32 = z64.astype(np.float32)
+    vidx_np = vidx.numpy()
+    P = len(px)
+    lists, clamps, amb, touched = [], [], np.zeros(P, bool), []
+    nv = max(1, len(vidx_np))
+    chunk = max(1, budget // nv)
+    for c0 in range(0, P, chunk):
+        c1 = min(P, c0 + chunk)
+        cx = torch.tensor(np.asarray(px[c0:c1], np.float64) + 0.5, dtype=DT)[:, None]
+        cy = torch.tensor(np.asarray(py[c0:c1], np.float64) + 0.5, dtype=DT)[:, None]
+        with torch.no_grad():
+            dx = u[None, :] - cx
+            dy = v[None, :] - cy
+            power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+            araw = o * torch.exp(power)
+            alpha = torch.clamp(araw, max=s.alpha_max)
+            keep = (power <= 0) & (alpha >= s.alpha_min)
+            near_min = (power <= 0) & ((araw - s.alpha_min).abs() <= rel_margin * s.alpha_min)
+        keep_np = keep.numpy()
+        alpha_np = alpha.numpy()
+        araw_np = araw.numpy()
+        nearmin_np = near_min.numpy()
+        for r in range(c1 - c0):
+            k = np.nonzero(keep_np[r])[0]
+            order = k[np.lexsort((vidx_np[k], z32[k]))]
+            T = 1.0
+            out, cl, tch = [], [], []
+            ambig = bool(nearmin_np[r].any())
+            for j in order:
+                a = float(alpha_np[r, j])
+                Tn = T * (1.0 - a)
+                tch.append(j)
+                if abs(araw_np[r, j] - s.alpha_max) <= rel_margin * s.alpha_max:
+                    ambig = True
+                if abs(Tn - s.t_min) <= rel_margin * s.t_min:
+                    ambig = True
+                if Tn < s.t_min:
+                    break
+                out.append(j)
+                cl.append(bool(araw_np[r, j] > s.alpha_max))
+                T = Tn
+            if len(tch) > 1:
+                zt = z32[np.array(tch)]
+                gaps = np.diff(zt.astype(np.float64))
+                tol = ulps * np.spacing(np.maximum(np.abs(zt[1:]), np.abs(zt[:-1])))
+                if np.any(np.abs(gaps) <= tol):
+                    ambig = True
+            lists.append(vidx_np[np.array(out, dtype=np.int64)] if out else np.zeros(0, np.int64))
+            clamps.append(np.array(cl, dtype=bool))
+            touched.append(vidx_np[np.array(tch, dtype=np.int64)] if tch else np.zeros(0, np.int64))
+            amb[c0 + r] = ambig
+    kmax = max([len(l) for l in lists] + [1])
+    idx = np.full((P, kmax), -1, np.int64)
+    clamped = np.zeros((P, kmax), bool)
+    count = np.zeros(P, np.int64)
+    for r, (l, cl) in enumerate(zip(lists, clamps)):
+        idx[r, :len(l)] = l
+        clamped[r, :len(l)] = cl
+        count[r] = len(l)
+    return Decisions(idx, clamped, count, amb, touched)
+
+
+def composite_eval(proj, px, py, dec: Decisions, s: RenderSettings):
+    """Differentiable compositing of the frozen per-pixel lists (float64)."""
+    P, kmax = dec.idx.shape
+    idx = torch.tensor(np.where(dec.idx >= 0, dec.idx, 0))
+    m = torch.tensor(dec.idx >= 0)
+    cx = torch.tensor(np.asarray(px, np.float64) + 0.5, dtype=DT)[:, None]
+    cy = torch.tensor(np.asarray(py, np.float64) + 0.5, dtype=DT)[:, None]
+    u = proj["u"][idx]
+    v = proj["v"][idx]
+    con = proj["conic"][idx]
+    dx = u - cx
+    dy = v - cy
+    power = -0.5 * (con[..., 0] * dx * dx + con[..., 2] * dy * dy) - con[..., 1] * dx * dy
+    araw = proj["o"][idx] * torch.exp(power)
+    alpha = torch.where(torch.tensor(dec.clamped), torch.full_like(araw, s.alpha_max), araw)
+    alpha = torch.where(m, alpha, torch.zeros_like(alpha))
+    T_after = torch.cumprod(1.0 - alpha, dim=1)
+    T_before = torch.cat([torch.ones(P, 1, dtype=DT), T_after[:, :-1]], dim=1)
+    w = alpha * T_before
+    T_final = T_after[:, -1]
+    bg = torch.tensor(s.bg, dtype=DT)
+    rgb = (w[..., None] * proj["rgb"][idx]).sum(1) + T_final[:, None] * bg
+    depth = (w * proj["z"][idx]).sum(1)
+    acc = w.sum(1)
+    return rgb, depth, acc, T_final
+
+
+def _pixel_coords(cam, pix):
+    pix = np.asarray(pix, np.int64)
+    return pix % cam.width, pix // cam.width
+
+
+def render(scene, s: RenderSettings = None, pixels=None, p=None):
+    """Forward render.  `pixels`: per view flat pixel indices (y * W + x), or None for full
+    images.  Returns per view dict(rgb (P,3), depth, alpha, T, count, ambiguous, pix)."""
+    s = s or RenderSettings()
+    p = p if p is not None else leaves(scene, requires_grad=False)
+    out = []
+    with torch.no_grad():
+        for b, cam in enumerate(scene.cameras):
+            pix = np.arange(cam.width * cam.height) if pixels is None or pixels[b] is None \
+                else np.asarray(pixels[b], np.int64)
+            px, py = _pixel_coords(cam, pix)
+            proj = project(p, cam, p["pose_delta"][b], s, scene.sh_degree)
+            dec = composite_decisions(proj, px, py, s)
+            rgb, depth, acc, T = composite_eval(proj, px, py, dec, s)
+            out.append({"rgb": rgb.numpy(), "depth": depth.numpy(), "alpha": acc.numpy(),
+                        "T": T.numpy(), "count": dec.count, "ambiguous": dec.ambiguous,
+                        "pix": pix, "proj": proj, "dec": dec})
+    return out
+
+
+def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=None,
+                   w_l1: float = 1.0, lam: float = 1.0, upstream=None, sign_margin=1e-5,
+                   frozen=None, deltas=None):
+    """Loss of Sec. III-C (L1 part + LiDAR KL term) and its float64 gradients.
+
+    masks: per view flat pixel indices where the L1 term applies (None = whole image).
+    lidar: per view dict(pix, depth, sigma) (defaults to scene.lidar); its pixels are
+           always evaluated.
+    upstream: optional per view dict(rgb (3,H,W), depth (H,W), alpha (H,W)) -- then the
+           objective is sum(upstream * outputs) over whole images instead of the loss.
+    frozen: decisions from a previous call (to evaluate the same piecewise-smooth branch).
+    Returns dict(loss, grads{name: np}, pose (B,6), views[...], amb_gauss (N,) bool,
+    decisions).
+    """
+    s = s or RenderSettings()
+    lidar = scene.lidar if lidar is None else lidar
+    gt = scene.gt_rgb if gt is None else gt
+    p = leaves(scene, requires_grad=True, deltas=deltas)
+    total = torch.zeros((), dtype=DT)
+    views = []
+    amb_gauss = np.zeros(scene.n, bool)
+    decisions = []
+    for b, cam in enumerate(scene.cameras):
+        HW = cam.width * cam.height
+        if upstream is not None:
+            eval_pix = np.arange(HW)
+            l1_pix = None
+        else:
+            l1_pix = np.arange(HW) if masks is None or masks[b] is None else np.asarray(masks[b], np.int64)
+            lp = np.asarray(lidar[b]["pix"], np.int64) if lidar and len(lidar[b]["pix"]) else np.zeros(0, np.int64)
+            eval_pix = np.union1d(l1_pix, lp)
+        px, py = _pixel_coords(cam, eval_pix)
+        proj = project(p, cam, p["pose_delta"][b], s, scene.sh_degree)
+        if frozen is not None:
+            dec = frozen[b]
+        else:
+            dec = composite_decisions(proj, px, py, s)
+        decisions.append(dec)
+        rgb, depth, acc, T = composite_eval(proj, px, py, dec, s)
+        pos = {int(q): k for k, q in enumerate(eval_pix)}
+        amb_pix = dec.ambiguous.copy()
+        if upstream is not None:
+            up = upstream[b]
+            g_rgb = torch.tensor(np.asarray(up["rgb"], np.float64).reshape(3, -1).T[eval_pix])
+            g_d = torch.tensor(np.asarray(up["depth"], np.float64).reshape(-1)[eval_pix])
+            g_a = torch.tensor(np.asarray(up["alpha"], np.float64).reshape(-1)[eval_pix])
+            total = total + (g_rgb * rgb).sum() + (g_d * depth).sum() + (g_a * acc).sum()
+        else:
+            sel = torch.tensor([pos[int(q)] for q in l1_pix], dtype=torch.long)
+            if len(l1_pix):
+                tgt = torch.tensor(np.asarray(gt[b], np.float64).reshape(3, -1).T[l1_pix])
+                diff = rgb[sel] - tgt
+                total = total + w_l1 / (3.0 * len(l1_pix)) * diff.abs().sum()
+                close = (diff.detach().abs() < sign_margin).any(1).numpy()
+                amb_pix[sel.numpy()[close]] = True
+            if lidar and len(lidar[b]["pix"]):
+                li = torch.tensor([pos[int(q)] for q in lidar[b]["pix"]], dtype=torch.long)
+                dl = torch.tensor(np.asarray(lidar[b]["depth"], np.float64))
+                sl = torch.tensor(np.asarray(lidar[b]["sigma"], np.float64))
+                mu_u = depth[li]
+                kl = kl_normal(dl, sl, mu_u, sl)
+                total = total + lam / len(li) * kl.sum()
+        for r in np.nonzero(amb_pix)[0]:
+            amb_gauss[cam.g_begin + dec.touched[r]] = True
+        views.append({"rgb": rgb.detach().numpy(), "depth": depth.detach().numpy(),
+                      "alpha": acc.detach().numpy(), "T": T.detach().numpy(),
+                      "count": dec.count, "ambiguous": amb_pix, "pix": eval_pix})
+    total.backward()
+    grads = {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
+             for k, v in p.items()}
+    pose = grads.pop("pose_delta")
+    return {"loss": float(total.detach()), "grads": grads, "pose": pose, "views": views,
+            "amb_gauss": amb_gauss, "decisions": decisions}
+
+
+def frozen_objective(scene, decisions, s: RenderSettings = None, masks=None, lidar=None,
+                     gt=None, w_l1=1.0, lam=1.0, upstream=None, deltas=None):
+    """The same objective as `loss_and_grads` evaluated with given frozen decisions and no
+    gradient (used by finite differences)."""
+    s = s or RenderSettings()
+    with torch.enable_grad():
+        r = loss_and_grads(scene, s, masks, lidar, gt, w_l1, lam, upstream, frozen=decisions,
+                           deltas=deltas)
+    return r["loss"]

@@ -1,0 +1,123 @@
+"""Pins for the oracle's tile-binning reference (the depth-ordered per-tile lists of the
+"standard 3DGS" renderer, Sec. III-B) and for its Adam / se(3) pose update (the joint
+refinement of splats and poses, Sec. III-C)."""
+import math
+
+import numpy as np
+import scipy.linalg
+import torch
+
+from oracle.binning import bin_reference, pixel_rect_f32, tile_grid
+from oracle.geometry import se3_exp, skew
+from oracle.optim import adam_update, pose_update
+from oracle.render import leaves, project, render
+from oracle.settings import RenderSettings
+from paper_2510_26358_amd.scenes import tiny_scene
+
+
+def _random_records(rng, n, W, H):
+    u = rng.uniform(-40, W + 40, n).astype(np.float32)
+    v = rng.uniform(-40, H + 40, n).astype(np.float32)
+    ex = rng.exponential(8.0, n).astype(np.float32)
+    ey = rng.exponential(8.0, n).astype(np.float32)
+    # quantised depths so that exact key ties occur and stability matters
+    z = (np.round(rng.uniform(0.5, 3.0, n) * 8) / 8).astype(np.float32)
+    valid = rng.uniform(size=n) > 0.2
+    return {"u": u, "v": v, "ex": ex, "ey": ey, "z": z, "valid": valid}
+
+
+def test_binning_reference_equals_brute_force_enumeration():
+    rng = np.random.default_rng(71)
+    T = 8
+    views = [(64, 40, 0), (50, 30, 300)]
+    recs = [_random_records(rng, 300, 64, 40), _random_records(rng, 200, 50, 30)]
+    keys, vals, ranges, counts, base = bin_reference(recs, views, T)
+    # brute force: for every tile of every view test whether any pixel of the tile lies in
+    # the footprint rectangle (pixel-level test, then Python's stable sort on the key)
+    items = []
+    tile0 = 0
+    for b, ((W, H, g0), r) in enumerate(zip(views, recs)):
+        ntx, nty = tile_grid(W, H, T)
+        for i in range(len(r["u"])):
+            if not r["valid"][i]:
+                continue
+            u, v, ex, ey = (np.float32(r[k][i]) for k in ("u", "v", "ex", "ey"))
+            xlo = math.floor(float(np.float32(np.float32(u - ex) - np.float32(0.5))))
+            xhi = math.ceil(float(np.float32(np.float32(u + ex) - np.float32(0.5))))
+            ylo = math.floor(float(np.float32(np.float32(v - ey) - np.float32(0.5))))
+            yhi = math.ceil(float(np.float32(np.float32(v + ey) - np.float32(0.5))))
+            for ty in range(nty):
+                for tx in range(ntx):
+                    hit = any(xlo <= px <= xhi and ylo <= py <= yhi
+                              for py in range(ty * T, min(H, ty * T + T))
+                              for px in range(tx * T, min(W, tx * T + T)))
+                    if hit:
+                        zb = int(np.float32(r["z"][i]).view(np.uint32))
+                        items.append((((tile0 + ty * ntx + tx) << 32) | zb, g0 + i))
+        tile0 += ntx * nty
+    items.sort(key=lambda e: e[0])  # Python's sort is stable: ties keep emission order
+    assert len(items) == len(keys)
+    assert [k for k, _ in items] == keys.tolist()
+    assert [g for _, g in items] == vals.tolist()
+    # ranges: every tile's slice holds exactly its keys
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    for t in range(base[-1]):
+        s, e = ranges[t]
+        assert (tiles[s:e] == t).all()
+        assert (e - s) == (tiles == t).sum()
+
+
+def test_every_contributing_pixel_lies_in_its_gaussians_tiles():
+    """The opacity-aware bounding box must cover every pixel where the brute-force
+    compositing keeps the Gaussian (alpha >= 1/255), for each tile size."""
+    sc = tiny_scene()
+    s = RenderSettings()
+    out = render(sc, s)[0]
+    pr = out["proj"]
+    dec = out["dec"]
+    W, H = 128, 96
+    ext = pr["ext"].numpy()
+    x0, y0, x1, y1, ne = pixel_rect_f32(pr["u"].numpy(), pr["v"].numpy(), ext[:, 0], ext[:, 1], W, H)
+    for T in (8, 16, 32):
+        ntx, _ = tile_grid(W, H, T)
+        for p in range(W * H):
+            px, py = p % W, p // W
+            for i in dec.touched[p]:
+                assert ne[i]
+                assert x0[i] // T <= px // T <= x1[i] // T and y0[i] // T <= py // T <= y1[i] // T
+
+
+def test_adam_matches_torch_adam_in_float64():
+    rng = np.random.default_rng(81)
+    p0 = rng.normal(size=50)
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=3e-3, betas=(0.9, 0.999), eps=1e-15)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 8):
+        g = rng.normal(size=50)
+        tp.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = adam_update(p, g, m, v, t, 3e-3)
+        assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-15)
+
+
+def test_pose_update_is_left_retraction_of_the_adam_step():
+    """First Adam step is -lr * g / (|g| + eps) componentwise; the pose becomes
+    expm(hat(delta)) W (matrix exponential of the twist, scipy)."""
+    rng = np.random.default_rng(82)
+    a = 0.3
+    R = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    t = np.array([0.5, -1.0, 2.0])
+    g = rng.normal(size=6)
+    lr = 1e-2
+    R2, t2, m, v = pose_update(R, t, g, np.zeros(6), np.zeros(6), 1, lr)
+    delta = -lr * g / (np.abs(g) + 1e-15)
+    X = np.zeros((4, 4))
+    X[:3, :3] = skew(delta[3:])
+    X[:3, 3] = delta[:3]
+    E = scipy.linalg.expm(X)
+    W = np.eye(4)
+    W[:3, :3], W[:3, 3] = R, t
+    W2 = E @ W
+    assert np.allclose(R2, W2[:3, :3], atol=1e-14) and np.allclose(t2, W2[:3, 3], atol=1e-14)
+    assert np.allclose(se3_exp(delta), E, atol=1e-14)
