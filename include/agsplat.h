@@ -1,0 +1,245 @@
+/*
+ * agsplat -- multi-view differentiable Gaussian-splat rasteriser for MI355X (gfx950).
+ *
+ * C ABI of libagsplat.so.  Plain pointers and sizes only.  "device" pointers are HIP
+ * device memory on the context's GPU; "host" pointers are ordinary process memory.
+ *
+ * What it computes (AgriGS-SLAM, arXiv 2510.26358):
+ *   - Gaussians with mean, covariance from scale and rotation, opacity and SH colour
+ *     (Sec. III-B, per-splat parameter equation and Sigma = R S S^T R^T); opacity is the
+ *     sigmoid of a trainable logit (Sec. III-B, "Pruning");
+ *   - projection to image-space conics Sigma' = J W Sigma W^T J^T (Sec. III-B);
+ *   - one shared Gaussian set rendered into B synchronised views in one batch, each
+ *     view's gradients updating the same parameters (Sec. III-B, multi-view setting);
+ *   - front-to-back alpha compositing of colour, expected depth and alpha per pixel
+ *     ("standard 3DGS", Sec. III-B), the expected depth being the mean of the rendered
+ *     depth distribution of the LiDAR term (Sec. III-C);
+ *   - the loss L1 + lambda_L / |Omega| sum KL(N(D_L, sigma_L^2) || N(mu_u, sigma_u^2))
+ *     (Sec. III-C, photometric and probabilistic depth-consistency terms), and its
+ *     gradients to every Gaussian parameter and to each camera pose (poses refined by
+ *     back-propagating through the projection, Sec. III-C and abstract).
+ *
+ * Fixed readings where the paper is silent are carried in ags_config (cutoffs, tile
+ * size, blur, near plane) and documented there.
+ *
+ * Conventions common to all calls
+ *   - Every function returns 0 (AGS_OK) or a negative AGS_ERR_* code; none aborts or
+ *     prints.  After AGS_ERR_HIP, ags_last_hip_error() returns the hipError_t.
+ *   - Calls that take `stream` (a hipStream_t; NULL = default stream) only enqueue work:
+ *     no allocation, no host synchronisation, so they may be captured into a HIP graph.
+ *   - The caller owns every buffer.  The library never keeps a pointer past a call.
+ *   - Images of all views live in one flat buffer: view b starts at pixel offset
+ *     pix_base[b] = sum_{b'<b} W_b' H_b'; inside a view, pixel (x, y) is y * W + x.
+ *     Colour planes are channel-major per view: view b's rgb is [3][H_b][W_b] starting at
+ *     element 3 * pix_base[b].
+ *   - A "pair" is (view b, Gaussian i) with g_begin[b] <= i < g_end[b]; pairs are numbered
+ *     view-major: pair_base[b] + (i - g_begin[b]), pair_base[b] = sum_{b'<b} (g_end - g_begin).
+ */
+#ifndef AGSPLAT_H
+#define AGSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AGS_ABI_VERSION 1
+#define AGS_MAX_VIEWS 32
+
+enum {
+    AGS_OK = 0,
+    AGS_ERR_INVALID_ARG = -1,   /* null pointer, bad size/shape, unsupported setting */
+    AGS_ERR_WORKSPACE = -2,     /* a buffer is smaller than ags_buffer_sizes requires */
+    AGS_ERR_CAPACITY = -3,      /* intersection capacity known on the host to be too small */
+    AGS_ERR_HIP = -4,           /* a HIP runtime call failed (see ags_last_hip_error) */
+    AGS_ERR_NOT_SUPPORTED = -5  /* valid request this build does not implement */
+};
+
+/* Rendering settings.  The paper defers these to "standard 3DGS"; the defaults of
+ * ags_config_default() are: alpha_min 1/255 (a Gaussian whose alpha is below it is
+ * skipped), alpha_max 0.99 (alpha clamp), t_min 1e-4 (compositing stops before the
+ * transmittance would drop below it; that Gaussian is excluded), blur 0.3 px^2 added to
+ * the diagonal of Sigma', z_near 0.2 (Gaussians closer are culled), fov_clamp 1.3 (x/z
+ * and y/z clamped to +-1.3 half-FOV tangents inside J only), bg = 0, tile 16. */
+typedef struct ags_config {
+    float alpha_min, alpha_max, t_min, blur, z_near, fov_clamp;
+    float bg[3];
+    int tile;          /* tile edge in pixels: 8, 16 or 32 (binning and raster) */
+    int batch;         /* Gaussians staged in LDS per batch: 64, 128, 256 or 512 */
+    int px_per_thread; /* raster pixels per thread: 1, 2 or 4 */
+} ags_config;
+
+/* Camera b, device array element (64 bytes).  World->camera rotation R (row-major) and
+ * translation t: x_cam = R x_world + t.  Pinhole intrinsics; pixel (x, y) has its centre
+ * at (x + 0.5, y + 0.5) and a camera point projects to (fx x/z + cx, fy y/z + cy). */
+typedef struct ags_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+} ags_camera;
+
+/* Static shape of a batch of views (host memory).  Must agree with the device cameras. */
+typedef struct ags_views {
+    int n_views;              /* 1 .. AGS_MAX_VIEWS */
+    const int32_t* width;     /* host [n_views], >= 1 */
+    const int32_t* height;    /* host [n_views], >= 1 */
+    const int32_t* g_begin;   /* host [n_views]: view b sees Gaussians [g_begin, g_end) */
+    const int32_t* g_end;     /* host [n_views], 0 <= g_begin <= g_end <= n */
+} ags_views;
+
+/* Gaussian parameters, structure-of-arrays, device float32.  K = (sh_degree + 1)^2.
+ *   means [3][n], log_scales [3][n] (scale = exp), quats [4][n] (w, x, y, z; any norm),
+ *   opacity_logits [n] (opacity = sigmoid), sh [K][3][n] (coefficient k, channel c of
+ *   Gaussian i at (k * 3 + c) * n + i; real SH, l-major, m = -l..l, Condon-Shortley phase;
+ *   colour = max(0, sum_k Y_k(d) sh_k + 0.5), d the unit direction camera centre -> mean). */
+typedef struct ags_gaussians {
+    int32_t n;
+    int32_t sh_degree;        /* 0 .. 3 */
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} ags_gaussians;
+
+/* Gradients, same layouts as ags_gaussians, plus pose [n_views][6] = dL/d delta_b for the
+ * left perturbation W_b <- Exp(delta_b) W_b, delta = (rho, phi), translation first.
+ * accumulate = 0 overwrites every element; 1 adds to what is there. */
+typedef struct ags_grads {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+    float* pose;
+    int32_t accumulate;
+} ags_grads;
+
+/* Forward outputs (device float32): rgb [3 * P], depth [P] (expected depth: sum of
+ * w_i z_i, unnormalised, z the camera-frame depth of the mean), alpha [P]; P = total pixels. */
+typedef struct ags_fwd_out {
+    float* rgb;
+    float* depth;
+    float* alpha;
+} ags_fwd_out;
+
+/* Upstream gradients dL/d(rgb, depth, alpha) in the output layouts; each may be NULL (0). */
+typedef struct ags_upstream {
+    const float* d_rgb;
+    const float* d_depth;
+    const float* d_alpha;
+} ags_upstream;
+
+/* Fused loss, summed over views b:
+ *   w_l1 / (3 n_b) sum_{p in mask_b} sum_c |rgb - gt_rgb|
+ * + lambda_lidar / |Omega_b| sum_{j in Omega_b} KL(N(D_j, s_j^2) || N(depth(p_j), s_j^2))
+ * (equal variances: (depth - D_j)^2 / (2 s_j^2)).  n_b = l1_count[b] if mask is given,
+ * else W_b H_b; the sign of 0 is 0.  Repeated target pixels simply add their terms. */
+typedef struct ags_loss {
+    const float* gt_rgb;          /* device, rgb layout */
+    const uint8_t* mask;          /* device [P] (1 = pixel enters the L1 term) or NULL */
+    const int64_t* l1_count;      /* host [n_views]; required when mask != NULL */
+    const int32_t* depth_pix;     /* device [n_targets]: pixel index y * W + x in its view */
+    const float* depth_val;       /* device [n_targets]: LiDAR depth D_j (camera z) */
+    const float* depth_sigma;     /* device [n_targets]: s_j > 0 */
+    const int64_t* depth_offsets; /* host [n_views + 1]: targets of view b are
+                                     [depth_offsets[b], depth_offsets[b+1]) */
+    float w_l1;
+    float lambda_lidar;
+} ags_loss;
+
+/* Buffer sizes and the layout of the `saved` buffer (byte offsets), for a batch shape. */
+typedef struct ags_sizes {
+    size_t saved_bytes;      /* state the forward leaves for the backward */
+    size_t fwd_ws_bytes;     /* forward scratch */
+    size_t bwd_ws_bytes;     /* backward scratch */
+    int64_t n_pairs, n_pixels, n_tiles;
+    int32_t tile_bits;       /* bits of the global tile id */
+    /* offsets into `saved` */
+    size_t off_counters;     /* uint32[4]: K (all intersections), V (visible pairs),
+                                overflow flag (K > capacity), K kept (min(K, capacity)) */
+    size_t off_records;      /* float[n_pairs][12]: u, v, conic a, b, c, opacity, z,
+                                ex, ey, r, g, b (written only for visible pairs) */
+    size_t off_pair_count;   /* uint32[n_pairs]: tiles touched (0 = culled / off-screen) */
+    size_t off_tile_pairs;   /* uint32[capacity]: pair ids, grouped by global tile and
+                                ordered by (float32 depth bits, pair id) inside a tile */
+    size_t off_ranges;       /* uint32[n_tiles][2]: [start, end) into tile_pairs */
+    size_t off_t_final;      /* float[P]: final transmittance */
+    size_t off_last;         /* uint32[P]: tile-list entries up to the last contributor */
+    size_t off_tile_keys;    /* (forward workspace) uint32[capacity]: sorted global tile ids */
+} ags_sizes;
+
+typedef struct ags_ctx ags_ctx;
+
+int ags_version(void);
+const char* ags_error_string(int code);
+int ags_last_hip_error(const ags_ctx* ctx);
+void ags_config_default(ags_config* cfg);
+
+/* Create a context on HIP device `device` with a copy of *cfg.  One context per stream
+ * at a time (the context holds timing events).  Errors: INVALID_ARG (bad cfg), HIP. */
+int ags_ctx_create(ags_ctx** out, int device, const ags_config* cfg);
+void ags_ctx_destroy(ags_ctx* ctx);
+int ags_ctx_set_config(ags_ctx* ctx, const ags_config* cfg);
+
+/* Host-only arithmetic: sizes of the buffers fwd/bwd need for this shape and capacity
+ * (maximum number of (tile, Gaussian) intersections).  No device access. */
+int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_gaussians,
+                     int32_t sh_degree, int64_t isect_capacity, ags_sizes* out);
+
+/* Forward render of all views in one batch (projection, binning, depth/tile sort, tile
+ * ranges, compositing).  cams: device [n_views].  saved: device, saved_bytes; ws: device,
+ * fwd_ws_bytes.  If the intersections exceed isect_capacity the overflow counter in
+ * `saved` is set and the outputs are not valid: enlarge the capacity and run again. */
+int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
+                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* out,
+                   void* saved, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward: exactly one of `up` (upstream gradients) or `loss` (fused loss; then
+ * `loss_out`, device float[1] or NULL, receives the loss value) is non-NULL.  `fwd` holds
+ * the outputs of the matching forward (read in loss mode).  saved: from that forward.
+ * ws: device, bwd_ws_bytes.  Gradients per ags_grads. */
+int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
+                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
+                   const void* saved, const ags_upstream* up, const ags_loss* loss,
+                   ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Binning stage alone (for tests and tuning): from projected records (float[n_pairs][12],
+ * the `saved` record layout) and per-pair validity (uint8[n_pairs]), compute pair tile
+ * counts, the depth-ordered per-tile pair lists and the ranges into `saved`. */
+int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians,
+                    const float* records, const uint8_t* valid, int64_t isect_capacity,
+                    void* saved, void* ws, size_t ws_bytes, void* stream);
+
+/* Adam on the Gaussian parameters (in place).  lr per group: means, log_scales, quats,
+ * opacity_logits, sh degree 0, sh degree >= 1.  m, v: device state in the parameter
+ * layouts (zero before the first step).  step: device int32, the 1-based step number. */
+typedef struct ags_adam {
+    float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh0, lr_shrest, lr_pose;
+    float beta1, beta2, eps;
+} ags_adam;
+
+int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* params,
+                  const ags_grads* grads, ags_gaussians* m, ags_gaussians* v,
+                  const int32_t* step, void* stream);
+
+/* Adam on each view's se(3) increment (pose_m, pose_v: device float[n_views][6]), then
+ * the left retraction W_b <- Exp(delta_b) W_b written into cams; if advance_step != 0 the
+ * device step counter is incremented afterwards (end of an optimisation step). */
+int ags_pose_step(ags_ctx* ctx, const ags_adam* hp, ags_camera* cams, int32_t n_views,
+                  const float* pose_grad, float* pose_m, float* pose_v, int32_t* step,
+                  int32_t advance_step, void* stream);
+
+/* Per-stage GPU time of the calls since the last reset (HIP events on the calls' streams;
+ * enabling adds an event pair per kernel launch).  names: host array of n_max C strings. */
+int ags_profile_enable(ags_ctx* ctx, int enable);
+int ags_profile_read(ags_ctx* ctx, int n_max, const char** names, double* total_ms,
+                     int64_t* launches, int* n_out);
+int ags_profile_reset(ags_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AGSPLAT_H */

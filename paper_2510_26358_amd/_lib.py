@@ -1,0 +1,140 @@
+"""ctypes view of libagsplat.so (the C ABI declared in include/agsplat.h).
+
+Argument marshalling only: structures mirror the header field by field.  Loading fails
+loudly when the library has not been built -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libagsplat.so")
+
+AGS_OK = 0
+AGS_ERR_INVALID_ARG = -1
+AGS_ERR_WORKSPACE = -2
+AGS_ERR_CAPACITY = -3
+AGS_ERR_HIP = -4
+AGS_ERR_NOT_SUPPORTED = -5
+AGS_MAX_VIEWS = 32
+
+EXPORTED = [
+    "ags_version", "ags_error_string", "ags_last_hip_error", "ags_config_default",
+    "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
+    "ags_render_fwd", "ags_render_bwd", "ags_bin_records", "ags_adam_step", "ags_pose_step",
+    "ags_profile_enable", "ags_profile_read", "ags_profile_reset",
+]
+
+
+class Config(C.Structure):
+    _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("blur", C.c_float), ("z_near", C.c_float), ("fov_clamp", C.c_float),
+                ("bg", C.c_float * 3), ("tile", C.c_int), ("batch", C.c_int),
+                ("px_per_thread", C.c_int)]
+
+
+class Views(C.Structure):
+    _fields_ = [("n_views", C.c_int), ("width", C.POINTER(C.c_int32)),
+                ("height", C.POINTER(C.c_int32)), ("g_begin", C.POINTER(C.c_int32)),
+                ("g_end", C.POINTER(C.c_int32))]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("means", C.c_void_p),
+                ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("pose", C.c_void_p),
+                ("accumulate", C.c_int32)]
+
+
+class FwdOut(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p)]
+
+
+class Upstream(C.Structure):
+    _fields_ = [("d_rgb", C.c_void_p), ("d_depth", C.c_void_p), ("d_alpha", C.c_void_p)]
+
+
+class Loss(C.Structure):
+    _fields_ = [("gt_rgb", C.c_void_p), ("mask", C.c_void_p),
+                ("l1_count", C.POINTER(C.c_int64)), ("depth_pix", C.c_void_p),
+                ("depth_val", C.c_void_p), ("depth_sigma", C.c_void_p),
+                ("depth_offsets", C.POINTER(C.c_int64)), ("w_l1", C.c_float),
+                ("lambda_lidar", C.c_float)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("saved_bytes", C.c_size_t), ("fwd_ws_bytes", C.c_size_t),
+                ("bwd_ws_bytes", C.c_size_t), ("n_pairs", C.c_int64), ("n_pixels", C.c_int64),
+                ("n_tiles", C.c_int64), ("tile_bits", C.c_int32), ("off_counters", C.c_size_t),
+                ("off_records", C.c_size_t), ("off_pair_count", C.c_size_t),
+                ("off_tile_pairs", C.c_size_t), ("off_ranges", C.c_size_t),
+                ("off_t_final", C.c_size_t), ("off_last", C.c_size_t),
+                ("off_tile_keys", C.c_size_t)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_sh0", C.c_float), ("lr_shrest", C.c_float),
+                ("lr_pose", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libagsplat.so (once).  Raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                          " (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    vp = C.c_void_p
+    lib.ags_version.restype = C.c_int
+    lib.ags_error_string.restype = C.c_char_p
+    lib.ags_error_string.argtypes = [C.c_int]
+    lib.ags_last_hip_error.argtypes = [vp]
+    lib.ags_config_default.argtypes = [P(Config)]
+    lib.ags_config_default.restype = None
+    lib.ags_ctx_create.argtypes = [P(vp), C.c_int, P(Config)]
+    lib.ags_ctx_destroy.argtypes = [vp]
+    lib.ags_ctx_destroy.restype = None
+    lib.ags_ctx_set_config.argtypes = [vp, P(Config)]
+    lib.ags_buffer_sizes.argtypes = [P(Config), P(Views), C.c_int32, C.c_int32, C.c_int64, P(Sizes)]
+    lib.ags_render_fwd.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp, vp,
+                                   C.c_size_t, vp]
+    lib.ags_render_bwd.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp,
+                                   P(Upstream), P(Loss), P(Grads), vp, vp, C.c_size_t, vp]
+    lib.ags_bin_records.argtypes = [vp, P(Views), C.c_int32, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
+    lib.ags_adam_step.argtypes = [vp, P(Adam), P(Gaussians), P(Grads), P(Gaussians), P(Gaussians), vp, vp]
+    lib.ags_pose_step.argtypes = [vp, P(Adam), vp, C.c_int32, vp, vp, vp, vp, C.c_int32, vp]
+    lib.ags_profile_enable.argtypes = [vp, C.c_int]
+    lib.ags_profile_read.argtypes = [vp, C.c_int, P(C.c_char_p), P(C.c_double), P(C.c_int64), P(C.c_int)]
+    lib.ags_profile_reset.argtypes = [vp]
+    for name in EXPORTED:
+        if lib.ags_version and not hasattr(lib, name):
+            raise ImportError(f"libagsplat.so lacks {name}")
+    _lib = lib
+    return lib
+
+
+class AgsError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str = "", ctx=None):
+    if rc != AGS_OK:
+        lib = load()
+        msg = lib.ags_error_string(rc).decode()
+        if rc == AGS_ERR_HIP and ctx is not None:
+            msg += f" (hipError {lib.ags_last_hip_error(ctx)})"
+        raise AgsError(f"{what}: {msg} ({rc})")

@@ -1,0 +1,664 @@
+// C ABI of libagsplat: argument validation, buffer layout and launch sequencing.
+// Kernels live in the other translation units; this file only enqueues them.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace ags;
+
+struct ProfEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
+enum Stage {
+    ST_PROJECT = 0,
+    ST_BINNING,
+    ST_RASTER_FWD,
+    ST_LIDAR,
+    ST_RASTER_BWD,
+    ST_PROJECT_BWD,
+    ST_CLEAR,
+    ST_ADAM,
+    ST_POSE,
+    ST_COUNT
+};
+static const char* kStageNames[ST_COUNT] = {"project_fwd", "binning",     "raster_fwd",
+                                             "lidar_adjoint", "raster_bwd", "project_bwd",
+                                             "clear",       "adam",        "pose_step"};
+
+struct ags_ctx {
+    int device;
+    ags_config cfg;
+    int last_hip;
+    bool prof;
+    std::vector<ProfEvent> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[ST_COUNT];
+    long long launches[ST_COUNT];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    ViewTable vt;
+    long long Q, P, n_tiles, cap;
+    int tile_bits;
+    int depth_grid, tile_grid;
+    // saved
+    size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_t_final, s_last, s_total;
+    // fwd ws
+    size_t f_pair_z, f_vis_off, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_tkeys0, f_tkeys1,
+        f_tvals1, f_hist, f_hist_sums, f_block_sums, f_total;
+    // bwd ws
+    size_t b_grad2d, b_ddepth, b_partials, b_total;
+    long long n_partials;
+};
+
+int check_views(const ags_views* v) {
+    if (!v || v->n_views < 1 || v->n_views > AGS_MAX_VIEWS) return AGS_ERR_INVALID_ARG;
+    if (!v->width || !v->height || !v->g_begin || !v->g_end) return AGS_ERR_INVALID_ARG;
+    return AGS_OK;
+}
+
+int check_config(const ags_config* c) {
+    if (!c) return AGS_ERR_INVALID_ARG;
+    if (c->tile != 8 && c->tile != 16 && c->tile != 32) return AGS_ERR_INVALID_ARG;
+    if (c->batch != 64 && c->batch != 128 && c->batch != 256 && c->batch != 512) return AGS_ERR_INVALID_ARG;
+    if (c->px_per_thread != 1 && c->px_per_thread != 2 && c->px_per_thread != 4) return AGS_ERR_INVALID_ARG;
+    if (!(c->alpha_min > 0.f && c->alpha_min < c->alpha_max && c->alpha_max < 1.f)) return AGS_ERR_INVALID_ARG;
+    if (!(c->t_min > 0.f && c->t_min < 1.f) || !(c->blur >= 0.f) || !(c->z_near > 0.f) ||
+        !(c->fov_clamp > 0.f))
+        return AGS_ERR_INVALID_ARG;
+    return AGS_OK;
+}
+
+int build_layout(const ags_config* cfg, const ags_views* views, int n, long long cap, Layout& L) {
+    int rc = check_views(views);
+    if (rc) return rc;
+    if (n < 0 || cap < 0 || cap > 0x7fffffffLL) return AGS_ERR_INVALID_ARG;
+    memset(&L, 0, sizeof(L));
+    ViewTable& vt = L.vt;
+    vt.n_views = views->n_views;
+    vt.tile = cfg->tile;
+    const int T = cfg->tile;
+    long long pix = 0, pair = 0, tiles = 0;
+    for (int b = 0; b < views->n_views; ++b) {
+        const int W = views->width[b], H = views->height[b];
+        const int g0 = views->g_begin[b], g1 = views->g_end[b];
+        if (W < 1 || H < 1 || W > 65535 || H > 65535) return AGS_ERR_INVALID_ARG;
+        if (g0 < 0 || g1 < g0 || g1 > n) return AGS_ERR_INVALID_ARG;
+        vt.width[b] = W;
+        vt.height[b] = H;
+        vt.g_begin[b] = g0;
+        vt.g_end[b] = g1;
+        vt.ntx[b] = (W + T - 1) / T;
+        vt.nty[b] = (H + T - 1) / T;
+        vt.tile_base[b] = (int)tiles;
+        vt.pix_base[b] = pix;
+        vt.pair_base[b] = pair;
+        tiles += (long long)vt.ntx[b] * vt.nty[b];
+        pix += (long long)W * H;
+        pair += g1 - g0;
+    }
+    vt.tile_base[views->n_views] = (int)tiles;
+    vt.pix_base[views->n_views] = pix;
+    vt.pair_base[views->n_views] = pair;
+    if (tiles > 0x7fffffffLL || pair > 0x7fffffffLL || pix > (1LL << 40)) return AGS_ERR_INVALID_ARG;
+    L.Q = pair;
+    L.P = pix;
+    L.n_tiles = tiles;
+    L.cap = cap;
+    int bits = 0;
+    while ((1LL << bits) < tiles) ++bits;
+    L.tile_bits = bits;
+    L.depth_grid = sort_grid(L.Q);
+    L.tile_grid = sort_grid(L.cap);
+    const long long Qs = L.Q > 0 ? L.Q : 1;
+    const long long caps = L.cap > 0 ? L.cap : 1;
+    size_t o = 0;
+    L.s_counters = o; o = align_up(o + 64);
+    L.s_records = o; o = align_up(o + (size_t)Qs * kRecFloats * 4);
+    L.s_pair_count = o; o = align_up(o + (size_t)Qs * 4);
+    L.s_tile_pairs = o; o = align_up(o + (size_t)caps * 4);
+    L.s_ranges = o; o = align_up(o + (size_t)(tiles > 0 ? tiles : 1) * 8);
+    L.s_t_final = o; o = align_up(o + (size_t)pix * 4);
+    L.s_last = o; o = align_up(o + (size_t)pix * 4);
+    L.s_total = o;
+    o = 0;
+    const int gmax = L.depth_grid > L.tile_grid ? L.depth_grid : L.tile_grid;
+    long long sb = scan_blocks(Qs);
+    long long sb2 = scan_blocks(256LL * gmax);
+    if (sb2 > sb) sb = sb2;
+    L.f_pair_z = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_vis_off = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_dkeys0 = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_dkeys1 = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_dvals0 = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_dvals1 = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_emit_off = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_tkeys0 = o; o = align_up(o + (size_t)caps * 4);
+    L.f_tkeys1 = o; o = align_up(o + (size_t)caps * 4);
+    L.f_tvals1 = o; o = align_up(o + (size_t)caps * 4);
+    L.f_hist = o; o = align_up(o + (size_t)256 * gmax * 4);
+    L.f_hist_sums = o; o = align_up(o + (size_t)sb * 4);
+    L.f_block_sums = o; o = align_up(o + (size_t)sb * 4);
+    L.f_total = o;
+    o = 0;
+    L.n_partials = tiles + lidar_blocks(0);  // raster blocks, then LiDAR blocks
+    L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
+    L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
+    L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
+    L.b_total = o;
+    return AGS_OK;
+}
+
+Settings settings_of(const ags_config& c) {
+    Settings s;
+    s.alpha_min = c.alpha_min;
+    s.alpha_max = c.alpha_max;
+    s.t_min = c.t_min;
+    s.blur = c.blur;
+    s.z_near = c.z_near;
+    s.fov_clamp = c.fov_clamp;
+    s.bg0 = c.bg[0];
+    s.bg1 = c.bg[1];
+    s.bg2 = c.bg[2];
+    return s;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename T>
+const T* at(const void* base, size_t off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Profiling helpers: bracket a group of launches with events when enabled.
+struct Scope {
+    ags_ctx* ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    Scope(ags_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+        if (!ctx->prof) return;
+        a = take();
+        b = take();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    hipEvent_t take() {
+        if (!ctx->pool.empty()) {
+            hipEvent_t e = ctx->pool.back();
+            ctx->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Scope() {
+        if (!ctx->prof || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        ctx->pending.push_back({stage, a, b});
+    }
+};
+
+int hip_status(ags_ctx* ctx) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        if (ctx) ctx->last_hip = (int)e;
+        return AGS_ERR_HIP;
+    }
+    return AGS_OK;
+}
+
+int check_gaussians(const ags_gaussians* g) {
+    if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return AGS_ERR_INVALID_ARG;
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return AGS_ERR_INVALID_ARG;
+    return AGS_OK;
+}
+
+BinArgs bin_args(const Layout& L, void* saved, void* ws) {
+    BinArgs a;
+    a.vt = L.vt;
+    a.records = at<float>(saved, L.s_records);
+    a.pair_count = at<uint32_t>(saved, L.s_pair_count);
+    a.pair_z = at<uint32_t>(ws, L.f_pair_z);
+    a.counters = at<uint32_t>(saved, L.s_counters);
+    a.n_pairs = L.Q;
+    a.capacity = L.cap;
+    a.vis_off = at<uint32_t>(ws, L.f_vis_off);
+    a.depth_keys[0] = at<uint32_t>(ws, L.f_dkeys0);
+    a.depth_keys[1] = at<uint32_t>(ws, L.f_dkeys1);
+    a.depth_vals[0] = at<uint32_t>(ws, L.f_dvals0);
+    a.depth_vals[1] = at<uint32_t>(ws, L.f_dvals1);
+    a.emit_off = at<uint32_t>(ws, L.f_emit_off);
+    a.tile_keys[0] = at<uint32_t>(ws, L.f_tkeys0);
+    a.tile_keys[1] = at<uint32_t>(ws, L.f_tkeys1);
+    a.tile_vals[0] = at<uint32_t>(saved, L.s_tile_pairs);
+    a.tile_vals[1] = at<uint32_t>(ws, L.f_tvals1);
+    a.ranges = at<uint32_t>(saved, L.s_ranges);
+    a.final_vals = a.tile_vals[0];
+    a.tile_bits = L.tile_bits;
+    a.scan_tmp.block_sums = at<uint32_t>(ws, L.f_block_sums);
+    a.sort_tmp.hist = at<uint32_t>(ws, L.f_hist);
+    a.sort_tmp.hist_sums = at<uint32_t>(ws, L.f_hist_sums);
+    a.sort_tmp.grid = L.depth_grid;
+    return a;
+}
+
+// Runs the binning with the depth-sort grid, then the tile-sort grid.
+int run_binning(const Layout& L, BinArgs a, hipStream_t s) {
+    // the two sorts use grids sized for their own maxima; launch_binning uses one grid,
+    // so pick the larger (both fit the histogram buffer)
+    a.sort_tmp.grid = L.depth_grid > L.tile_grid ? L.depth_grid : L.tile_grid;
+    return launch_binning(a, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ags_version(void) { return AGS_ABI_VERSION; }
+
+const char* ags_error_string(int code) {
+    switch (code) {
+        case AGS_OK: return "ok";
+        case AGS_ERR_INVALID_ARG: return "invalid argument";
+        case AGS_ERR_WORKSPACE: return "buffer smaller than required";
+        case AGS_ERR_CAPACITY: return "intersection capacity too small";
+        case AGS_ERR_HIP: return "HIP runtime error";
+        case AGS_ERR_NOT_SUPPORTED: return "not supported";
+        default: return "unknown error";
+    }
+}
+
+int ags_last_hip_error(const ags_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+void ags_config_default(ags_config* c) {
+    if (!c) return;
+    c->alpha_min = 1.f / 255.f;
+    c->alpha_max = 0.99f;
+    c->t_min = 1e-4f;
+    c->blur = 0.3f;
+    c->z_near = 0.2f;
+    c->fov_clamp = 1.3f;
+    c->bg[0] = c->bg[1] = c->bg[2] = 0.f;
+    c->tile = 16;
+    c->batch = 256;
+    c->px_per_thread = 1;
+}
+
+int ags_ctx_create(ags_ctx** out, int device, const ags_config* cfg) {
+    if (!out) return AGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return AGS_ERR_HIP;
+    ags_ctx* c = new (std::nothrow) ags_ctx();
+    if (!c) return AGS_ERR_HIP;
+    c->device = device;
+    c->cfg = *cfg;
+    c->last_hip = 0;
+    c->prof = false;
+    for (int k = 0; k < ST_COUNT; ++k) {
+        c->total_ms[k] = 0.0;
+        c->launches[k] = 0;
+    }
+    *out = c;
+    return AGS_OK;
+}
+
+void ags_ctx_destroy(ags_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& p : ctx->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int ags_ctx_set_config(ags_ctx* ctx, const ags_config* cfg) {
+    if (!ctx) return AGS_ERR_INVALID_ARG;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    ctx->cfg = *cfg;
+    return AGS_OK;
+}
+
+int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_gaussians,
+                     int32_t sh_degree, int64_t isect_capacity, ags_sizes* out) {
+    if (!out || sh_degree < 0 || sh_degree > 3) return AGS_ERR_INVALID_ARG;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    Layout L;
+    rc = build_layout(cfg, views, n_gaussians, isect_capacity, L);
+    if (rc) return rc;
+    out->saved_bytes = L.s_total;
+    out->fwd_ws_bytes = L.f_total;
+    out->bwd_ws_bytes = L.b_total;
+    out->n_pairs = L.Q;
+    out->n_pixels = L.P;
+    out->n_tiles = L.n_tiles;
+    out->tile_bits = L.tile_bits;
+    out->off_counters = L.s_counters;
+    out->off_records = L.s_records;
+    out->off_pair_count = L.s_pair_count;
+    out->off_tile_pairs = L.s_tile_pairs;
+    out->off_ranges = L.s_ranges;
+    out->off_t_final = L.s_t_final;
+    out->off_last = L.s_last;
+    // keys and values ping-pong together and the values end in `saved` (buffer 0 of the
+    // tile sort), so the sorted keys end in the workspace's first key buffer
+    out->off_tile_keys = L.f_tkeys0;
+    return AGS_OK;
+}
+
+int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
+                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* out,
+                   void* saved, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !out || !saved || !ws || !cams) return AGS_ERR_INVALID_ARG;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    Layout L;
+    rc = build_layout(&ctx->cfg, views, g->n, isect_capacity, L);
+    if (rc) return rc;
+    if (ws_bytes < L.f_total) return AGS_ERR_WORKSPACE;
+    if (L.P > 0 && (!out->rgb || !out->depth || !out->alpha)) return AGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    const Settings st = settings_of(ctx->cfg);
+    {
+        Scope sc(ctx, ST_PROJECT, s);
+        ProjectArgs pa;
+        pa.vt = L.vt;
+        pa.st = st;
+        pa.n = g->n;
+        pa.sh_degree = g->sh_degree;
+        pa.means = g->means;
+        pa.log_scales = g->log_scales;
+        pa.quats = g->quats;
+        pa.logits = g->opacity_logits;
+        pa.sh = g->sh;
+        pa.cams = cams;
+        pa.records = at<float>(saved, L.s_records);
+        pa.pair_count = at<uint32_t>(saved, L.s_pair_count);
+        pa.pair_z = at<uint32_t>(ws, L.f_pair_z);
+        launch_project_fwd(pa, s);
+    }
+    {
+        Scope sc(ctx, ST_BINNING, s);
+        run_binning(L, bin_args(L, saved, ws), s);
+    }
+    {
+        Scope sc(ctx, ST_RASTER_FWD, s);
+        RasterArgs ra;
+        ra.vt = L.vt;
+        ra.st = st;
+        ra.records = at<float>(saved, L.s_records);
+        ra.tile_pairs = at<uint32_t>(saved, L.s_tile_pairs);
+        ra.ranges = at<uint32_t>(saved, L.s_ranges);
+        ra.rgb = out->rgb;
+        ra.depth = out->depth;
+        ra.alpha = out->alpha;
+        ra.t_final = at<float>(saved, L.s_t_final);
+        ra.last = at<uint32_t>(saved, L.s_last);
+        rc = launch_raster_fwd(ra, ctx->cfg.tile, ctx->cfg.batch, ctx->cfg.px_per_thread, s);
+        if (rc) return rc;
+    }
+    return hip_status(ctx);
+}
+
+int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, const float* records,
+                    const uint8_t* valid, int64_t isect_capacity, void* saved, void* ws,
+                    size_t ws_bytes, void* stream) {
+    if (!ctx || !saved || !ws || (!records && n_gaussians > 0) || (!valid && n_gaussians > 0))
+        return AGS_ERR_INVALID_ARG;
+    Layout L;
+    int rc = build_layout(&ctx->cfg, views, n_gaussians, isect_capacity, L);
+    if (rc) return rc;
+    if (ws_bytes < L.f_total) return AGS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    Scope sc(ctx, ST_BINNING, s);
+    if (L.Q > 0)
+        (void)hipMemcpyAsync(at<float>(saved, L.s_records), records, (size_t)L.Q * kRecFloats * 4,
+                             hipMemcpyDeviceToDevice, s);
+    launch_count_from_records(L.vt, records, valid, L.Q, at<uint32_t>(saved, L.s_pair_count),
+                              at<uint32_t>(ws, L.f_pair_z), s);
+    run_binning(L, bin_args(L, saved, ws), s);
+    return hip_status(ctx);
+}
+
+int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
+                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
+                   const void* saved, const ags_upstream* up, const ags_loss* loss,
+                   ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !saved || !ws || !cams || !grads) return AGS_ERR_INVALID_ARG;
+    if ((up == nullptr) == (loss == nullptr)) return AGS_ERR_INVALID_ARG;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    Layout L;
+    rc = build_layout(&ctx->cfg, views, g->n, isect_capacity, L);
+    if (rc) return rc;
+    if (ws_bytes < L.b_total) return AGS_ERR_WORKSPACE;
+    if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                     !grads->sh))
+        return AGS_ERR_INVALID_ARG;
+    if (!grads->pose) return AGS_ERR_INVALID_ARG;
+    long long n_targets = 0;
+    if (loss) {
+        if (!fwd || !fwd->rgb || !fwd->depth || !loss->gt_rgb) return AGS_ERR_INVALID_ARG;
+        if (loss->mask && !loss->l1_count) return AGS_ERR_INVALID_ARG;
+        if (loss->depth_offsets) {
+            if (loss->depth_offsets[0] != 0) return AGS_ERR_INVALID_ARG;
+            for (int b = 0; b < views->n_views; ++b)
+                if (loss->depth_offsets[b + 1] < loss->depth_offsets[b]) return AGS_ERR_INVALID_ARG;
+            n_targets = loss->depth_offsets[views->n_views];
+            if (n_targets > 0 && (!loss->depth_pix || !loss->depth_val || !loss->depth_sigma))
+                return AGS_ERR_INVALID_ARG;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    const Settings st = settings_of(ctx->cfg);
+    float* grad2d = at<float>(ws, L.b_grad2d);
+    float* ddepth = at<float>(ws, L.b_ddepth);
+    float* partials = at<float>(ws, L.b_partials);
+    {
+        Scope sc(ctx, ST_CLEAR, s);
+        launch_fill_f32(grad2d, 0.f, L.Q * kGrad2dStride, s);
+        if (!grads->accumulate) launch_fill_f32(grads->pose, 0.f, 6LL * views->n_views, s);
+        if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
+        if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, L.n_partials - L.n_tiles, s);
+    }
+    RasterBwdArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.vt = L.vt;
+    ra.st = st;
+    ra.records = at<float>(saved, L.s_records);
+    ra.tile_pairs = at<uint32_t>(saved, L.s_tile_pairs);
+    ra.ranges = at<uint32_t>(saved, L.s_ranges);
+    ra.t_final = at<float>(saved, L.s_t_final);
+    ra.last = at<uint32_t>(saved, L.s_last);
+    ra.grad2d = grad2d;
+    if (loss) {
+        ra.loss_mode = 1;
+        ra.rgb = fwd->rgb;
+        ra.gt_rgb = loss->gt_rgb;
+        ra.mask = loss->mask;
+        for (int b = 0; b < views->n_views; ++b) {
+            const double nb = loss->mask ? (double)loss->l1_count[b]
+                                         : (double)views->width[b] * (double)views->height[b];
+            ra.l1_scale[b] = nb > 0 ? (float)(loss->w_l1 / (3.0 * nb)) : 0.f;
+        }
+        ra.loss_partials = partials;
+        ra.d_depth = n_targets > 0 ? ddepth : nullptr;
+        if (n_targets > 0) {
+            Scope sc(ctx, ST_LIDAR, s);
+            LidarArgs la;
+            memset(&la, 0, sizeof(la));
+            la.vt = L.vt;
+            la.depth = fwd->depth;
+            la.pix = loss->depth_pix;
+            la.val = loss->depth_val;
+            la.sigma = loss->depth_sigma;
+            la.n_targets = n_targets;
+            for (int b = 0; b <= views->n_views; ++b) la.target_off[b] = loss->depth_offsets[b];
+            for (int b = 0; b < views->n_views; ++b) {
+                const long long nb = loss->depth_offsets[b + 1] - loss->depth_offsets[b];
+                la.scale[b] = nb > 0 ? (float)(loss->lambda_lidar / (double)nb) : 0.f;
+            }
+            la.d_depth = ddepth;
+            la.loss_partials = partials + L.n_tiles;  // one slot per LiDAR block
+            launch_lidar_adjoint(la, s);
+        }
+    } else {
+        ra.loss_mode = 0;
+        ra.d_rgb = up->d_rgb;
+        ra.d_depth = up->d_depth;
+        ra.d_alpha = up->d_alpha;
+    }
+    {
+        Scope sc(ctx, ST_RASTER_BWD, s);
+        rc = launch_raster_bwd(ra, ctx->cfg.tile, ctx->cfg.batch, ctx->cfg.px_per_thread, s);
+        if (rc) return rc;
+    }
+    {
+        Scope sc(ctx, ST_PROJECT_BWD, s);
+        ProjectBwdArgs pa;
+        pa.vt = L.vt;
+        pa.st = st;
+        pa.n = g->n;
+        pa.sh_degree = g->sh_degree;
+        pa.means = g->means;
+        pa.log_scales = g->log_scales;
+        pa.quats = g->quats;
+        pa.logits = g->opacity_logits;
+        pa.sh = g->sh;
+        pa.cams = cams;
+        pa.pair_count = at<uint32_t>(saved, L.s_pair_count);
+        pa.grad2d = grad2d;
+        pa.g_means = grads->means;
+        pa.g_log_scales = grads->log_scales;
+        pa.g_quats = grads->quats;
+        pa.g_logits = grads->opacity_logits;
+        pa.g_sh = grads->sh;
+        pa.g_pose = grads->pose;
+        pa.accumulate = grads->accumulate;
+        launch_project_bwd(pa, s);
+    }
+    if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);
+    return hip_status(ctx);
+}
+
+int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* p, const ags_grads* gr,
+                  ags_gaussians* m, ags_gaussians* v, const int32_t* step, void* stream) {
+    if (!ctx || !hp || !p || !gr || !m || !v || !step) return AGS_ERR_INVALID_ARG;
+    if (check_gaussians(p) || check_gaussians(m) || check_gaussians(v)) return AGS_ERR_INVALID_ARG;
+    if (m->n != p->n || v->n != p->n || m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+        return AGS_ERR_INVALID_ARG;
+    if (p->n > 0 && (!gr->means || !gr->log_scales || !gr->quats || !gr->opacity_logits || !gr->sh))
+        return AGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    AdamArgs a;
+    a.n = p->n;
+    a.sh_k = (p->sh_degree + 1) * (p->sh_degree + 1);
+    float* pp[5] = {p->means, p->log_scales, p->quats, p->opacity_logits, p->sh};
+    const float* gg[5] = {gr->means, gr->log_scales, gr->quats, gr->opacity_logits, gr->sh};
+    float* mm[5] = {m->means, m->log_scales, m->quats, m->opacity_logits, m->sh};
+    float* vv[5] = {v->means, v->log_scales, v->quats, v->opacity_logits, v->sh};
+    for (int k = 0; k < 5; ++k) {
+        a.p[k] = pp[k];
+        a.g[k] = gg[k];
+        a.m[k] = mm[k];
+        a.v[k] = vv[k];
+    }
+    a.lr[0] = hp->lr_means;
+    a.lr[1] = hp->lr_log_scales;
+    a.lr[2] = hp->lr_quats;
+    a.lr[3] = hp->lr_opacity;
+    a.lr[4] = hp->lr_sh0;
+    a.lr[5] = hp->lr_shrest;
+    a.beta1 = hp->beta1;
+    a.beta2 = hp->beta2;
+    a.eps = hp->eps;
+    a.step = step;
+    Scope sc(ctx, ST_ADAM, s);
+    launch_adam(a, s);
+    return hip_status(ctx);
+}
+
+int ags_pose_step(ags_ctx* ctx, const ags_adam* hp, ags_camera* cams, int32_t n_views,
+                  const float* pose_grad, float* pose_m, float* pose_v, int32_t* step,
+                  int32_t advance_step, void* stream) {
+    if (!ctx || !hp || !cams || !pose_grad || !pose_m || !pose_v || !step) return AGS_ERR_INVALID_ARG;
+    if (n_views < 1 || n_views > AGS_MAX_VIEWS) return AGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    Scope sc(ctx, ST_POSE, s);
+    launch_pose_step(cams, n_views, pose_grad, pose_m, pose_v, step, advance_step, hp->lr_pose, hp->beta1,
+                     hp->beta2, hp->eps, s);
+    return hip_status(ctx);
+}
+
+int ags_profile_enable(ags_ctx* ctx, int enable) {
+    if (!ctx) return AGS_ERR_INVALID_ARG;
+    ctx->prof = enable != 0;
+    return AGS_OK;
+}
+
+static int drain(ags_ctx* ctx) {
+    for (auto& p : ctx->pending) {
+        if (hipEventSynchronize(p.b) != hipSuccess) return hip_status(ctx);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->total_ms[p.stage] += ms;
+            ctx->launches[p.stage] += 1;
+        }
+        ctx->pool.push_back(p.a);
+        ctx->pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+    return AGS_OK;
+}
+
+int ags_profile_read(ags_ctx* ctx, int n_max, const char** names, double* total_ms, int64_t* launches,
+                     int* n_out) {
+    if (!ctx || !n_out) return AGS_ERR_INVALID_ARG;
+    int rc = drain(ctx);
+    if (rc) return rc;
+    int n = ST_COUNT < n_max ? ST_COUNT : n_max;
+    for (int k = 0; k < n; ++k) {
+        if (names) names[k] = kStageNames[k];
+        if (total_ms) total_ms[k] = ctx->total_ms[k];
+        if (launches) launches[k] = ctx->launches[k];
+    }
+    *n_out = n;
+    return AGS_OK;
+}
+
+int ags_profile_reset(ags_ctx* ctx) {
+    if (!ctx) return AGS_ERR_INVALID_ARG;
+    int rc = drain(ctx);
+    for (int k = 0; k < ST_COUNT; ++k) {
+        ctx->total_ms[k] = 0.0;
+        ctx->launches[k] = 0;
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+// Internal declarations shared by the HIP translation units of libagsplat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/agsplat.h"
+
+namespace ags {
+
+constexpr int kMaxViews = AGS_MAX_VIEWS;
+constexpr int kRecFloats = 12;       // projected record: u v a b c o z ex ey r g b
+constexpr int kGrad2d = 10;          // per-pair 2D adjoint: u v a b c o r g b z
+constexpr int kGrad2dStride = 10;
+
+// Static per-batch table passed by value to kernels (kernel arguments).
+struct ViewTable {
+    int n_views;
+    int tile;
+    int ntx[kMaxViews];
+    int nty[kMaxViews];
+    int width[kMaxViews];
+    int height[kMaxViews];
+    int g_begin[kMaxViews];
+    int g_end[kMaxViews];
+    int tile_base[kMaxViews + 1];
+    long long pix_base[kMaxViews + 1];
+    long long pair_base[kMaxViews + 1];
+};
+
+struct Settings {
+    float alpha_min, alpha_max, t_min, blur, z_near, fov_clamp;
+    float bg0, bg1, bg2;
+};
+
+// Counters at the head of the saved buffer.
+enum { CNT_K = 0, CNT_V = 1, CNT_OVERFLOW = 2, CNT_KEFF = 3 };
+
+__device__ __forceinline__ int view_of_pair(const ViewTable& vt, long long q) {
+    int b = 0;
+    for (int k = 1; k < vt.n_views; ++k)
+        if (q >= vt.pair_base[k]) b = k;
+    return b;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int t) {
+    int b = 0;
+    for (int k = 1; k < vt.n_views; ++k)
+        if (t >= vt.tile_base[k]) b = k;
+    return b;
+}
+
+// Footprint rectangle in tiles of a projected Gaussian (centre u, v; bounding
+// half-extents ex, ey), in float32 exactly as written: pixels
+// [floor((u - ex) - 0.5), ceil((u + ex) - 0.5)] clamped to the image, then // T.
+// Returns false when the rectangle is empty.
+__device__ __forceinline__ bool tile_rect(float u, float v, float ex, float ey, int W, int H,
+                                          int T, int& tx0, int& ty0, int& tx1, int& ty1) {
+    float fx0 = floorf(__fsub_rn(__fsub_rn(u, ex), 0.5f));
+    float fx1 = ceilf(__fsub_rn(__fadd_rn(u, ex), 0.5f));
+    float fy0 = floorf(__fsub_rn(__fsub_rn(v, ey), 0.5f));
+    float fy1 = ceilf(__fsub_rn(__fadd_rn(v, ey), 0.5f));
+    int x0 = fx0 < 0.f ? 0 : (fx0 > (float)W ? W : (int)fx0);
+    int x1 = fx1 > (float)(W - 1) ? W - 1 : (fx1 < -1.f ? -1 : (int)fx1);
+    int y0 = fy0 < 0.f ? 0 : (fy0 > (float)H ? H : (int)fy0);
+    int y1 = fy1 > (float)(H - 1) ? H - 1 : (fy1 < -1.f ? -1 : (int)fy1);
+    if (x0 > x1 || y0 > y1) return false;
+    tx0 = x0 / T;
+    tx1 = x1 / T;
+    ty0 = y0 / T;
+    ty1 = y1 / T;
+    return true;
+}
+
+// Real spherical harmonics (Condon-Shortley phase, l-major, m = -l..l) as polynomials in
+// the unit direction; the constants are the normalisations sqrt((2l+1)/(4pi)(l-m)!/(l+m)!)
+// times the sqrt(2) of the real combination, folded into each monomial.
+struct SHConst {
+    static constexpr float c0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+    static constexpr float c1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+    static constexpr float c2a = 1.0925484305920792f;   // sqrt(15/pi)/2
+    static constexpr float c2b = 0.31539156525252005f;  // sqrt(5/pi)/4
+    static constexpr float c2c = 0.54627421529603959f;  // sqrt(15/pi)/4
+    static constexpr float c3a = 0.59004358992664352f;  // sqrt(35/(2 pi))/4
+    static constexpr float c3b = 2.8906114426405538f;   // sqrt(105/pi)/2
+    static constexpr float c3c = 0.45704579946446572f;  // sqrt(21/(2 pi))/4
+    static constexpr float c3d = 0.37317633259011540f;  // sqrt(7/pi)/4
+    static constexpr float c3e = 1.4453057213202769f;   // sqrt(105/pi)/4
+};
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+    Y[0] = SHConst::c0;
+    if (deg < 1) return;
+    Y[1] = -SHConst::c1 * y;
+    Y[2] = SHConst::c1 * z;
+    Y[3] = -SHConst::c1 * x;
+    if (deg < 2) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = SHConst::c2a * x * y;
+    Y[5] = -SHConst::c2a * y * z;
+    Y[6] = SHConst::c2b * (2.f * zz - xx - yy);
+    Y[7] = -SHConst::c2a * x * z;
+    Y[8] = SHConst::c2c * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -SHConst::c3a * y * (3.f * xx - yy);
+    Y[10] = SHConst::c3b * x * y * z;
+    Y[11] = -SHConst::c3c * y * (4.f * zz - xx - yy);
+    Y[12] = SHConst::c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -SHConst::c3c * x * (4.f * zz - xx - yy);
+    Y[14] = SHConst::c3e * z * (xx - yy);
+    Y[15] = -SHConst::c3a * x * (xx - 3.f * yy);
+}
+
+// Gradient of each basis polynomial with respect to (x, y, z): dY[k][0..2].
+__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, float (*dY)[3]) {
+    dY[0][0] = dY[0][1] = dY[0][2] = 0.f;
+    if (deg < 1) return;
+    dY[1][0] = 0.f; dY[1][1] = -SHConst::c1; dY[1][2] = 0.f;
+    dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = SHConst::c1;
+    dY[3][0] = -SHConst::c1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+    if (deg < 2) return;
+    float xx = x * x, yy = y * y, zz = z * z;
+    dY[4][0] = SHConst::c2a * y; dY[4][1] = SHConst::c2a * x; dY[4][2] = 0.f;
+    dY[5][0] = 0.f; dY[5][1] = -SHConst::c2a * z; dY[5][2] = -SHConst::c2a * y;
+    dY[6][0] = -2.f * SHConst::c2b * x; dY[6][1] = -2.f * SHConst::c2b * y; dY[6][2] = 4.f * SHConst::c2b * z;
+    dY[7][0] = -SHConst::c2a * z; dY[7][1] = 0.f; dY[7][2] = -SHConst::c2a * x;
+    dY[8][0] = 2.f * SHConst::c2c * x; dY[8][1] = -2.f * SHConst::c2c * y; dY[8][2] = 0.f;
+    if (deg < 3) return;
+    dY[9][0] = -6.f * SHConst::c3a * x * y;
+    dY[9][1] = -SHConst::c3a * (3.f * xx - 3.f * yy);
+    dY[9][2] = 0.f;
+    dY[10][0] = SHConst::c3b * y * z; dY[10][1] = SHConst::c3b * x * z; dY[10][2] = SHConst::c3b * x * y;
+    dY[11][0] = 2.f * SHConst::c3c * x * y;
+    dY[11][1] = -SHConst::c3c * (4.f * zz - xx - 3.f * yy);
+    dY[11][2] = -8.f * SHConst::c3c * y * z;
+    dY[12][0] = -6.f * SHConst::c3d * x * z;
+    dY[12][1] = -6.f * SHConst::c3d * y * z;
+    dY[12][2] = SHConst::c3d * (6.f * zz - 3.f * xx - 3.f * yy);
+    dY[13][0] = -SHConst::c3c * (4.f * zz - 3.f * xx - yy);
+    dY[13][1] = 2.f * SHConst::c3c * x * y;
+    dY[13][2] = -8.f * SHConst::c3c * x * z;
+    dY[14][0] = 2.f * SHConst::c3e * x * z; dY[14][1] = -2.f * SHConst::c3e * y * z;
+    dY[14][2] = SHConst::c3e * (xx - yy);
+    dY[15][0] = -SHConst::c3a * (3.f * xx - 3.f * yy);
+    dY[15][1] = 6.f * SHConst::c3a * x * y;
+    dY[15][2] = 0.f;
+}
+
+// Unit quaternion (w, x, y, z) -> row-major rotation matrix.
+__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Wave-wide sum of one float (64 lanes); every lane gets the total.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Sum of 16 per-lane values over the wave; lane L returns the total of slot (L >> 2) & 15.
+__device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
+    const int lane = __lane_id();
+    float w8[8];
+    {
+        const bool hi = lane & 32;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float send = hi ? v[j] : v[j + 8];
+            const float keep = hi ? v[j + 8] : v[j];
+            w8[j] = keep + __shfl_xor(send, 32, 64);
+        }
+    }
+    float w4[4];
+    {
+        const bool hi = lane & 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float send = hi ? w8[j] : w8[j + 4];
+            const float keep = hi ? w8[j + 4] : w8[j];
+            w4[j] = keep + __shfl_xor(send, 16, 64);
+        }
+    }
+    float w2[2];
+    {
+        const bool hi = lane & 8;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float send = hi ? w4[j] : w4[j + 2];
+            const float keep = hi ? w4[j + 2] : w4[j];
+            w2[j] = keep + __shfl_xor(send, 8, 64);
+        }
+    }
+    float w1;
+    {
+        const bool hi = lane & 4;
+        const float send = hi ? w2[0] : w2[1];
+        const float keep = hi ? w2[1] : w2[0];
+        w1 = keep + __shfl_xor(send, 4, 64);
+    }
+    w1 += __shfl_xor(w1, 1, 64);
+    w1 += __shfl_xor(w1, 2, 64);
+    return w1;
+}
+
+
+// Host-side launchers (one per kernel family), defined next to their kernels.
+struct ProjectArgs {
+    ViewTable vt;
+    Settings st;
+    int n, sh_degree;
+    const float *means, *log_scales, *quats, *logits, *sh;
+    const ags_camera* cams;
+    float* records;
+    uint32_t* pair_count;
+    uint32_t* pair_z;
+};
+void launch_project_fwd(const ProjectArgs& a, hipStream_t s);
+
+void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s);
+void launch_fill_f32(float* p, float v, long long n, hipStream_t s);
+
+// Exclusive scan of n u32 values (n read from device if n_dev != nullptr, else n_max).
+// Value source: src[i], or src[idx[i]] when idx != nullptr, or (src[i] != 0) when
+// as_flags.  Writes out[i] and total to *total (if non-null).
+struct ScanTemp {
+    uint32_t* block_sums;   // >= scan_blocks(n_max)
+};
+long long scan_blocks(long long n_max);
+void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32_t* out,
+                 long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
+                 hipStream_t s);
+
+// LSD radix sort of (key, value) u32 pairs on bits [0, bits), n read from n_dev.
+struct SortTemp {
+    uint32_t* hist;         // 256 * grid
+    uint32_t* hist_sums;    // scan_blocks(256 * grid)
+    int grid;
+};
+int sort_grid(long long n_max);
+int sort_passes(int bits);
+// keys/vals: [0] = input, [1] = other buffer; returns index of the buffer holding the
+// result (0 or 1).
+int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
+                      int bits, SortTemp tmp, hipStream_t s);
+
+struct BinArgs {
+    ViewTable vt;
+    const float* records;
+    const uint32_t* pair_count;
+    const uint32_t* pair_z;
+    uint32_t* counters;
+    long long n_pairs;
+    long long capacity;
+    uint32_t* vis_off;       // [n_pairs] scan of visibility
+    uint32_t* depth_keys[2]; // [n_pairs]
+    uint32_t* depth_vals[2];
+    uint32_t* emit_off;      // [n_pairs] scan of tile counts in depth order
+    uint32_t* tile_keys[2];  // [capacity]
+    uint32_t* tile_vals[2];
+    uint32_t* ranges;        // [n_tiles][2]
+    uint32_t* final_vals;    // where the tile-sorted pair ids must end (== one of tile_vals)
+    int tile_bits;
+    ScanTemp scan_tmp;
+    SortTemp sort_tmp;
+};
+void launch_count_from_records(const ViewTable& vt, const float* records, const uint8_t* valid,
+                               long long n_pairs, uint32_t* pair_count, uint32_t* pair_z,
+                               hipStream_t s);
+// Runs visibility scan + compaction, depth sort, tile-count scan, emission, tile sort and
+// ranges.  Returns 0 or a HIP error.
+int launch_binning(BinArgs& a, hipStream_t s);
+
+struct RasterArgs {
+    ViewTable vt;
+    Settings st;
+    const float* records;
+    const uint32_t* tile_pairs;
+    const uint32_t* ranges;
+    float* rgb;
+    float* depth;
+    float* alpha;
+    float* t_final;
+    uint32_t* last;
+};
+int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_t s);
+
+struct RasterBwdArgs {
+    ViewTable vt;
+    Settings st;
+    const float* records;
+    const uint32_t* tile_pairs;
+    const uint32_t* ranges;
+    const float* t_final;
+    const uint32_t* last;
+    // upstream mode
+    const float* d_rgb;
+    const float* d_depth;
+    const float* d_alpha;
+    // loss mode (fused L1 prologue); d_depth then points at the scattered LiDAR adjoint
+    int loss_mode;
+    const float* rgb;
+    const float* gt_rgb;
+    const uint8_t* mask;
+    float l1_scale[kMaxViews];   // w_l1 / (3 n_b)
+    float* loss_partials;        // one per block (loss mode)
+    float* grad2d;               // [n_pairs][10]
+};
+int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
+int raster_blocks(const ViewTable& vt);
+
+struct LidarArgs {
+    ViewTable vt;
+    const float* depth;
+    const int32_t* pix;
+    const float* val;
+    const float* sigma;
+    long long n_targets;
+    long long target_off[kMaxViews + 1];
+    float scale[kMaxViews];      // lambda / |Omega_b|
+    float* d_depth;              // dense [P] (zeroed before)
+    float* loss_partials;
+};
+int lidar_blocks(long long n_targets);
+void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s);
+void launch_sum_partials(const float* partials, long long n, float* out, hipStream_t s);
+
+struct ProjectBwdArgs {
+    ViewTable vt;
+    Settings st;
+    int n, sh_degree;
+    const float *means, *log_scales, *quats, *logits, *sh;
+    const ags_camera* cams;
+    const uint32_t* pair_count;
+    const float* grad2d;
+    float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
+    int accumulate;
+};
+void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
+
+struct AdamArgs {
+    int n, sh_k;
+    float* p[5];
+    const float* g[5];
+    float* m[5];
+    float* v[5];
+    float lr[6];
+    float beta1, beta2, eps;
+    const int32_t* step;
+};
+void launch_adam(const AdamArgs& a, hipStream_t s);
+void launch_pose_step(ags_camera* cams, int n_views, const float* g, float* m, float* v,
+                      int32_t* step, int advance, float lr, float b1, float b2, float eps,
+                      hipStream_t s);
+
+}  // namespace ags

@@ -1,0 +1,292 @@
+// Adjoint of the projection (Sec. III-B) for every view, summed over views per Gaussian,
+// plus each view's SE(3) pose adjoint (poses refined through the projection, Sec. III-C).
+//
+// One thread per Gaussian loops over the views that see it (the same splat set is shared
+// by all cameras, so its gradient is the sum over views), reads the pair's ten 2D adjoints
+// (u, v, conic a b c, opacity, rgb, depth), recomputes the forward quantities and chains:
+//   conic -> Sigma':     G' = -K G_K K, G_K = [[ga, gb/2], [gb/2, gc]]
+//   Sigma' = T Sigma T^T with T = J R_b:  G_Sigma += T^T G' T,  G_T = 2 G' T Sigma
+//   T -> J -> x_c (x/z, y/z clamp: zero through the clamped coordinate), (u, v) -> x_c,
+//   depth z -> x_c; colour: Y(d) for the coefficients, grad Y projected on the sphere for
+//   the direction d = (mu - C_b) / |mu - C_b|;  mu <- R_b^T g_xc + direction term.
+// Pose, left perturbation W_b <- Exp(delta) W_b with delta = (rho, phi):
+//   g_rho += g_xc + R_b g_dir (the camera centre moves by -R_b^T rho),
+//   g_phi += x_c x g_xc + (N_12 - N_21, N_20 - N_02, N_01 - N_10), N = R_b G_T^T J.
+// The per-view pose sums are reduced over the wave (transposing butterfly) and added with
+// one atomic instruction per wave.  Shared-Gaussian terms (Sigma -> scale, rotation;
+// opacity -> logit) are chained once after the view loop.
+#include "common.h"
+
+namespace ags {
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < a.n;
+    const int n = a.n;
+    const int lane = __lane_id();
+    const ViewTable& vt = a.vt;
+
+    float mx = 0.f, my = 0.f, mz = 0.f, ls0 = 0.f, ls1 = 0.f, ls2 = 0.f;
+    float qw = 1.f, qx = 0.f, qy = 0.f, qz = 0.f, logit = 0.f;
+    if (active) {
+        mx = a.means[i]; my = a.means[n + i]; mz = a.means[2 * n + i];
+        ls0 = a.log_scales[i]; ls1 = a.log_scales[n + i]; ls2 = a.log_scales[2 * n + i];
+        qw = a.quats[i]; qx = a.quats[n + i]; qy = a.quats[2 * n + i]; qz = a.quats[3 * n + i];
+        logit = a.logits[i];
+    }
+    const float s0 = __expf(ls0), s1 = __expf(ls1), s2 = __expf(ls2);
+    const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
+    const float qinv = rsqrtf(qn2);
+    const float uw = qw * qinv, ux = qx * qinv, uy = qy * qinv, uz = qz * qinv;
+    float Rq[9];
+    quat_to_rot(uw, ux, uy, uz, Rq);
+    float M[9] = {Rq[0] * s0, Rq[1] * s1, Rq[2] * s2, Rq[3] * s0, Rq[4] * s1, Rq[5] * s2,
+                  Rq[6] * s0, Rq[7] * s1, Rq[8] * s2};
+    float Sg[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            Sg[r][c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+
+    float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float gmu[3] = {0.f, 0.f, 0.f};
+    float go = 0.f;
+    float f[K][3];
+    float gf[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gf[k][c] = 0.f;
+            f[k][c] = 0.f;
+        }
+    bool f_loaded = false;
+
+    for (int b = 0; b < vt.n_views; ++b) {
+        const bool in_range = active && i >= vt.g_begin[b] && i < vt.g_end[b];
+        const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
+        const bool vis = in_range && a.pair_count[q] != 0u;
+        float pose[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) pose[k] = 0.f;
+        if (vis) {
+            if (!f_loaded) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) f[k][c] = a.sh[(long long)(k * 3 + c) * n + i];
+                f_loaded = true;
+            }
+            const float* g2 = a.grad2d + q * kGrad2dStride;
+            const float g_u = g2[0], g_v = g2[1], g_a = g2[2], g_b = g2[3], g_c = g2[4];
+            const float g_o = g2[5], g_r = g2[6], g_g = g2[7], g_bl = g2[8], g_zd = g2[9];
+            const ags_camera cam = a.cams[b];
+            const float* R = cam.R;
+            const float x = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
+            const float y = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
+            const float z = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
+            const float rz = 1.f / z, rz2 = rz * rz;
+            const float limx = a.st.fov_clamp * (float)vt.width[b] / (2.f * cam.fx);
+            const float limy = a.st.fov_clamp * (float)vt.height[b] / (2.f * cam.fy);
+            const float xz = x * rz, yz = y * rz;
+            const bool clx = xz < -limx || xz > limx;
+            const bool cly = yz < -limy || yz > limy;
+            const float txz = fminf(fmaxf(xz, -limx), limx);
+            const float tyz = fminf(fmaxf(yz, -limy), limy);
+            const float j00 = cam.fx * rz, j02 = -cam.fx * txz * rz;
+            const float j11 = cam.fy * rz, j12 = -cam.fy * tyz * rz;
+            float T[2][3];
+            for (int k = 0; k < 3; ++k) {
+                T[0][k] = j00 * R[k] + j02 * R[6 + k];
+                T[1][k] = j11 * R[3 + k] + j12 * R[6 + k];
+            }
+            // Sigma' = T Sigma T^T + blur
+            float TS[2][3];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 3; ++c)
+                    TS[r][c] = T[r][0] * Sg[0][c] + T[r][1] * Sg[1][c] + T[r][2] * Sg[2][c];
+            const float ca = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + a.st.blur;
+            const float cb = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+            const float cc = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + a.st.blur;
+            const float idet = 1.f / (ca * cc - cb * cb);
+            const float KA = cc * idet, KB = -cb * idet, KC = ca * idet;
+            // G' = -K G_K K
+            const float p = g_a, r2 = 0.5f * g_b, s = g_c;
+            const float k00 = KA * p + KB * r2, k01 = KA * r2 + KB * s;
+            const float k10 = KB * p + KC * r2, k11 = KB * r2 + KC * s;
+            const float G00 = -(k00 * KA + k01 * KB);
+            const float G01 = -(k00 * KB + k01 * KC);
+            const float G11 = -(k10 * KB + k11 * KC);
+            // U = G' T (2x3)
+            float U[2][3];
+            for (int c = 0; c < 3; ++c) {
+                U[0][c] = G00 * T[0][c] + G01 * T[1][c];
+                U[1][c] = G01 * T[0][c] + G11 * T[1][c];
+            }
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) GSig[r][c] += T[0][r] * U[0][c] + T[1][r] * U[1][c];
+            // G_T = 2 U Sigma
+            float GT[2][3];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 3; ++c)
+                    GT[r][c] = 2.f * (U[r][0] * Sg[0][c] + U[r][1] * Sg[1][c] + U[r][2] * Sg[2][c]);
+            // G_J = G_T R^T (only the entries of J that are not structurally zero matter)
+            float GJ[2][3];
+            for (int r = 0; r < 2; ++r)
+                for (int m = 0; m < 3; ++m)
+                    GJ[r][m] = GT[r][0] * R[3 * m] + GT[r][1] * R[3 * m + 1] + GT[r][2] * R[3 * m + 2];
+            // rotation of the view through T: N = R G_T^T J, N[m][c] = sum_r GJ[r][m] J[r][c]
+            // J = [[j00, 0, j02], [0, j11, j12]]
+            const float N01 = GJ[1][0] * j11;
+            const float N10 = GJ[0][1] * j00;
+            const float N02 = GJ[0][0] * j02 + GJ[1][0] * j12;
+            const float N20 = GJ[0][2] * j00;
+            const float N12 = GJ[0][1] * j02 + GJ[1][1] * j12;
+            const float N21 = GJ[1][2] * j11;
+            // x_c adjoint
+            float gx = g_u * cam.fx * rz;
+            float gy = g_v * cam.fy * rz;
+            float gz = -(g_u * cam.fx * x + g_v * cam.fy * y) * rz2 + g_zd;
+            gz += -cam.fx * rz2 * GJ[0][0] - cam.fy * rz2 * GJ[1][1];
+            if (!clx) {
+                gx += -cam.fx * rz2 * GJ[0][2];
+                gz += 2.f * cam.fx * x * rz2 * rz * GJ[0][2];
+            } else {
+                gz += cam.fx * txz * rz2 * GJ[0][2];
+            }
+            if (!cly) {
+                gy += -cam.fy * rz2 * GJ[1][2];
+                gz += 2.f * cam.fy * y * rz2 * rz * GJ[1][2];
+            } else {
+                gz += cam.fy * tyz * rz2 * GJ[1][2];
+            }
+            // colour
+            const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
+            const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
+            const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
+            float dvx = mx - Cx, dvy = my - Cy, dvz = mz - Cz;
+            const float il = rsqrtf(dvx * dvx + dvy * dvy + dvz * dvz);
+            const float dx = dvx * il, dy = dvy * il, dz = dvz * il;
+            float Y[16];
+            sh_basis(DEG, dx, dy, dz, Y);
+            const float grgb[3] = {g_r, g_g, g_bl};
+            float gcol[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc += Y[k] * f[k][c];
+                gcol[c] = acc >= 0.f ? grgb[c] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gf[k][c] += Y[k] * gcol[c];
+            float gdir[3] = {0.f, 0.f, 0.f};
+            if (DEG > 0) {
+                float dY[16][3];
+                sh_basis_grad(DEG, dx, dy, dz, dY);
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    const float w = f[k][0] * gcol[0] + f[k][1] * gcol[1] + f[k][2] * gcol[2];
+                    gdir[0] += dY[k][0] * w;
+                    gdir[1] += dY[k][1] * w;
+                    gdir[2] += dY[k][2] * w;
+                }
+                const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
+                gdir[0] = (gdir[0] - dd * dx) * il;
+                gdir[1] = (gdir[1] - dd * dy) * il;
+                gdir[2] = (gdir[2] - dd * dz) * il;
+            }
+            // mean
+            gmu[0] += R[0] * gx + R[3] * gy + R[6] * gz + gdir[0];
+            gmu[1] += R[1] * gx + R[4] * gy + R[7] * gz + gdir[1];
+            gmu[2] += R[2] * gx + R[5] * gy + R[8] * gz + gdir[2];
+            go += g_o;
+            // pose
+            pose[0] = gx + R[0] * gdir[0] + R[1] * gdir[1] + R[2] * gdir[2];
+            pose[1] = gy + R[3] * gdir[0] + R[4] * gdir[1] + R[5] * gdir[2];
+            pose[2] = gz + R[6] * gdir[0] + R[7] * gdir[1] + R[8] * gdir[2];
+            pose[3] = (y * gz - z * gy) + (N12 - N21);
+            pose[4] = (z * gx - x * gz) + (N20 - N02);
+            pose[5] = (x * gy - y * gx) + (N01 - N10);
+        }
+        if (__ballot(vis) != 0ull) {
+            const float tot = wave_transpose_sum16(pose);
+            const int slot = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && slot < 6) atomicAdd(a.g_pose + b * 6 + slot, tot);
+        }
+    }
+    if (!active) return;
+
+    // Sigma = M M^T, M = Rq diag(s): G_M = 2 G_Sigma M (G_Sigma symmetrised)
+    float GS[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) GS[r][c] = 0.5f * (GSig[r][c] + GSig[c][r]);
+    float GM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            GM[3 * r + c] = 2.f * (GS[r][0] * M[c] + GS[r][1] * M[3 + c] + GS[r][2] * M[6 + c]);
+    const float sc[3] = {s0, s1, s2};
+    float gls[3];
+    float GR[9];
+    for (int c = 0; c < 3; ++c) {
+        const float gS = Rq[c] * GM[c] + Rq[3 + c] * GM[3 + c] + Rq[6 + c] * GM[6 + c];
+        gls[c] = gS * sc[c];
+        GR[c] = GM[c] * sc[c];
+        GR[3 + c] = GM[3 + c] * sc[c];
+        GR[6 + c] = GM[6 + c] * sc[c];
+    }
+    // rotation matrix of the unit quaternion (w, x, y, z) -> its adjoint
+    const float gw = 2.f * (-uz * GR[1] + uy * GR[2] + uz * GR[3] - ux * GR[5] - uy * GR[6] + ux * GR[7]);
+    const float gx_ = 2.f * (uy * GR[1] + uz * GR[2] + uy * GR[3] - uw * GR[5] + uz * GR[6] + uw * GR[7]) -
+                      4.f * ux * (GR[4] + GR[8]);
+    const float gy_ = 2.f * (ux * GR[1] + uw * GR[2] + ux * GR[3] + uz * GR[5] - uw * GR[6] + uz * GR[7]) -
+                      4.f * uy * (GR[0] + GR[8]);
+    const float gz_ = 2.f * (-uw * GR[1] + ux * GR[2] + uw * GR[3] + uy * GR[5] + ux * GR[6] + uy * GR[7]) -
+                      4.f * uz * (GR[0] + GR[4]);
+    // normalisation q / |q|
+    const float dot = uw * gw + ux * gx_ + uy * gy_ + uz * gz_;
+    const float gq[4] = {(gw - uw * dot) * qinv, (gx_ - ux * dot) * qinv, (gy_ - uy * dot) * qinv,
+                         (gz_ - uz * dot) * qinv};
+    const float o = 1.f / (1.f + __expf(-logit));
+    const float glogit = go * o * (1.f - o);
+
+    if (a.accumulate) {
+        for (int c = 0; c < 3; ++c) {
+            a.g_means[c * n + i] += gmu[c];
+            a.g_log_scales[c * n + i] += gls[c];
+        }
+        for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] += gq[c];
+        a.g_logits[i] += glogit;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a.g_sh[(long long)(k * 3 + c) * n + i] += gf[k][c];
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            a.g_means[c * n + i] = gmu[c];
+            a.g_log_scales[c * n + i] = gls[c];
+        }
+        for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = gq[c];
+        a.g_logits[i] = glogit;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a.g_sh[(long long)(k * 3 + c) * n + i] = gf[k][c];
+    }
+}
+
+void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
+    if (a.n <= 0) return;
+    dim3 grid((a.n + 255) / 256), block(256);
+    switch (a.sh_degree) {
+        case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, a); break;
+    }
+}
+
+}  // namespace ags

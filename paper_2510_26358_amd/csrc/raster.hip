@@ -1,0 +1,343 @@
+// Tile rasterisation of all views in one launch: forward compositing and its adjoint.
+//
+// A workgroup owns one T x T tile of one view (the global tile id selects the view), so a
+// rig's views and a set of submaps share one launch.  The tile's depth-ordered Gaussian
+// list is streamed through LDS in batches; every lane reads the same record (LDS
+// broadcast) and composites its pixel(s) front to back (Sec. III-B, standard 3DGS):
+//   power = -1/2 (a dx^2 + c dy^2) - b dx dy, (dx, dy) = (u, v) - pixel centre
+//   alpha = min(alpha_max, o e^power), skipped when power > 0 or alpha < alpha_min
+//   T' = T (1 - alpha); stop (excluding this Gaussian) when T' < t_min
+//   C += alpha T rgb; D += alpha T z; A += alpha T; T = T'
+// A workgroup stops fetching batches once every pixel has stopped, and a wave whose lanes
+// have all stopped skips the rest of a batch.  The forward keeps 8 bytes per pixel
+// (final T and the list position of the last contributor) so the backward recomputes
+// transmittance instead of storing per-pixel blend lists.
+//
+// The backward walks the list back to front from the last contributor, recovering
+// T_k = T_{k+1} / (1 - alpha_k) and accumulating suffix sums S = sum_{j>k} w_j f_j:
+//   dL/dalpha_k = T_k (gC . c_k + gD z_k + gA)
+//                 - (gC . S^C + gD S^D + gA S^A + T_final gC . bg) / (1 - alpha_k)
+// then chains through alpha = o e^power (unless clamped) to (u, v, conic, o), and gives
+// dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian sums of a wave are reduced
+// with a transposing butterfly (17 lane exchanges instead of 60) so one atomic instruction
+// with ten active lanes updates the pair's adjoint.
+#include "common.h"
+
+namespace ags {
+
+struct TileCoord {
+    int b, px0, py0, W, H;
+    long long pix0;  // first pixel of the view in the flat image buffers
+};
+
+__device__ __forceinline__ TileCoord tile_coord(const ViewTable& vt, int tile) {
+    TileCoord c;
+    c.b = view_of_tile(vt, tile);
+    int local = tile - vt.tile_base[c.b];
+    int ntx = vt.ntx[c.b];
+    c.px0 = (local % ntx) * vt.tile;
+    c.py0 = (local / ntx) * vt.tile;
+    c.W = vt.width[c.b];
+    c.H = vt.height[c.b];
+    c.pix0 = vt.pix_base[c.b];
+    return c;
+}
+
+// Pixel k of thread t: PPT vertically adjacent pixels per thread, so a 64-lane wave covers
+// a compact 16 x 4 * PPT (T = 16) block.
+template <int T, int PPT>
+__device__ __forceinline__ void pixel_of(int t, int k, int& x, int& y) {
+    x = t % T;
+    y = (t / T) * PPT + k;
+}
+
+template <int T, int PPT, int M>
+__global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
+    constexpr int NT = T * T / PPT;
+    __shared__ float4 srec[M][3];
+    const TileCoord tc = tile_coord(a.vt, blockIdx.x);
+    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x;
+
+    float cx[PPT], cy[PPT], Tr[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], A[PPT];
+    uint32_t last[PPT];
+    bool inside[PPT], done[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        int lx, ly;
+        pixel_of<T, PPT>(tid, k, lx, ly);
+        const int px = tc.px0 + lx, py = tc.py0 + ly;
+        inside[k] = px < tc.W && py < tc.H;
+        done[k] = !inside[k];
+        cx[k] = (float)px + 0.5f;
+        cy[k] = (float)py + 0.5f;
+        Tr[k] = 1.f;
+        C0[k] = C1[k] = C2[k] = D[k] = A[k] = 0.f;
+        last[k] = 0;
+    }
+    const float amin = a.st.alpha_min, amax = a.st.alpha_max, tmin = a.st.t_min;
+
+    for (uint32_t bs = start; bs < end; bs += M) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) any |= !done[k];
+        if (__syncthreads_count(any) == 0) break;
+#pragma unroll
+        for (int l = tid; l < M; l += NT) {
+            const uint32_t e = bs + l;
+            if (e < end) {
+                const uint32_t q = a.tile_pairs[e];
+                const float4* r = reinterpret_cast<const float4*>(a.records + (long long)q * kRecFloats);
+                srec[l][0] = r[0];
+                srec[l][1] = r[1];
+                srec[l][2] = r[2];
+            }
+        }
+        __syncthreads();
+        const int nb = (int)min((uint32_t)M, end - bs);
+        if (any) {
+            for (int j = 0; j < nb; ++j) {
+                bool live = false;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) live |= !done[k];
+                if (!live) break;
+                const float4 r0 = srec[j][0], r1 = srec[j][1], r2 = srec[j][2];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (done[k]) continue;
+                    const float dx = r0.x - cx[k], dy = r0.y - cy[k];
+                    const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+                    if (power > 0.f) continue;
+                    const float alpha = fminf(amax, r1.y * __expf(power));
+                    if (alpha < amin) continue;
+                    const float tn = Tr[k] * (1.f - alpha);
+                    if (tn < tmin) {
+                        done[k] = true;
+                        continue;
+                    }
+                    const float w = alpha * Tr[k];
+                    C0[k] += w * r2.y;
+                    C1[k] += w * r2.z;
+                    C2[k] += w * r2.w;
+                    D[k] += w * r1.z;
+                    A[k] += w;
+                    Tr[k] = tn;
+                    last[k] = bs - start + j + 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const long long plane = (long long)tc.W * tc.H;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!inside[k]) continue;
+        int lx, ly;
+        pixel_of<T, PPT>(tid, k, lx, ly);
+        const long long p = (long long)(tc.py0 + ly) * tc.W + (tc.px0 + lx);
+        const long long gp = tc.pix0 + p;
+        float* rgb = a.rgb + 3 * tc.pix0;
+        rgb[p] = C0[k] + Tr[k] * a.st.bg0;
+        rgb[plane + p] = C1[k] + Tr[k] * a.st.bg1;
+        rgb[2 * plane + p] = C2[k] + Tr[k] * a.st.bg2;
+        a.depth[gp] = D[k];
+        a.alpha[gp] = A[k];
+        a.t_final[gp] = Tr[k];
+        a.last[gp] = last[k];
+    }
+}
+
+template <int T, int PPT, int M>
+__global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a) {
+    constexpr int NT = T * T / PPT;
+    __shared__ float4 srec[M][3];
+    __shared__ uint32_t sq[M];
+    __shared__ uint32_t smax;
+    __shared__ float sred[NT / 64];
+    const TileCoord tc = tile_coord(a.vt, blockIdx.x);
+    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+
+    float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], bgt[PPT];
+    float S0[PPT], S1[PPT], S2[PPT], SD[PPT], SA[PPT];
+    uint32_t last[PPT];
+    float loss_part = 0.f;
+    uint32_t mylast = 0;
+    const long long plane = (long long)tc.W * tc.H;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        int lx, ly;
+        pixel_of<T, PPT>(tid, k, lx, ly);
+        const int px = tc.px0 + lx, py = tc.py0 + ly;
+        cx[k] = (float)px + 0.5f;
+        cy[k] = (float)py + 0.5f;
+        S0[k] = S1[k] = S2[k] = SD[k] = SA[k] = 0.f;
+        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = 0.f;
+        Tr[k] = 1.f;
+        last[k] = 0;
+        bgt[k] = 0.f;
+        if (px < tc.W && py < tc.H) {
+            const long long p = (long long)py * tc.W + px;
+            const long long gp = tc.pix0 + p;
+            Tr[k] = a.t_final[gp];
+            last[k] = a.last[gp];
+            if (a.loss_mode) {
+                const bool on = a.mask ? (a.mask[gp] != 0) : true;
+                if (on) {
+                    const float sc = a.l1_scale[tc.b];
+                    const float* rgb = a.rgb + 3 * tc.pix0;
+                    const float* gt = a.gt_rgb + 3 * tc.pix0;
+                    const float d0 = rgb[p] - gt[p];
+                    const float d1 = rgb[plane + p] - gt[plane + p];
+                    const float d2 = rgb[2 * plane + p] - gt[2 * plane + p];
+                    gC0[k] = d0 > 0.f ? sc : (d0 < 0.f ? -sc : 0.f);
+                    gC1[k] = d1 > 0.f ? sc : (d1 < 0.f ? -sc : 0.f);
+                    gC2[k] = d2 > 0.f ? sc : (d2 < 0.f ? -sc : 0.f);
+                    loss_part += sc * (fabsf(d0) + fabsf(d1) + fabsf(d2));
+                }
+                if (a.d_depth) gD[k] = a.d_depth[gp];
+            } else {
+                if (a.d_rgb) {
+                    const float* g = a.d_rgb + 3 * tc.pix0;
+                    gC0[k] = g[p];
+                    gC1[k] = g[plane + p];
+                    gC2[k] = g[2 * plane + p];
+                }
+                if (a.d_depth) gD[k] = a.d_depth[gp];
+                if (a.d_alpha) gA[k] = a.d_alpha[gp];
+            }
+            bgt[k] = Tr[k] * (gC0[k] * a.st.bg0 + gC1[k] * a.st.bg1 + gC2[k] * a.st.bg2);
+            mylast = max(mylast, last[k]);
+        }
+    }
+    if (a.loss_mode) {
+        // block sum of the L1 partials (deterministic order)
+        float s = wave_sum(loss_part);
+        if (lane == 0) sred[tid >> 6] = s;
+    }
+    if (tid == 0) smax = 0;
+    __syncthreads();
+    atomicMax(&smax, mylast);
+    if (a.loss_mode && tid == 0) {
+        float s = 0.f;
+        for (int w = 0; w < NT / 64; ++w) s += sred[w];
+        a.loss_partials[blockIdx.x] = s;
+    }
+    __syncthreads();
+    const uint32_t maxlast = smax;
+    // wave-uniform bound: entries at or past every lane's last contributor are skipped
+    uint32_t wlast = mylast;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+
+    const float amin = a.st.alpha_min, amax = a.st.alpha_max;
+    const float bg0 = a.st.bg0, bg1 = a.st.bg1, bg2 = a.st.bg2;
+    (void)bg0; (void)bg1; (void)bg2;
+
+    for (int hi = (int)maxlast; hi > 0; hi -= M) {
+        const int lo = hi - M > 0 ? hi - M : 0;
+        for (int l = tid; l < hi - lo; l += NT) {
+            const uint32_t q = a.tile_pairs[start + lo + l];
+            const float4* r = reinterpret_cast<const float4*>(a.records + (long long)q * kRecFloats);
+            srec[l][0] = r[0];
+            srec[l][1] = r[1];
+            srec[l][2] = r[2];
+            sq[l] = q;
+        }
+        __syncthreads();
+        for (int j = hi - 1; j >= lo; --j) {
+            if ((uint32_t)j >= wlast) continue;  // wave-uniform
+            const float4 r0 = srec[j - lo][0], r1 = srec[j - lo][1], r2 = srec[j - lo][2];
+            float g[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) g[s] = 0.f;
+            bool contrib = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if ((uint32_t)j >= last[k]) continue;
+                const float dx = r0.x - cx[k], dy = r0.y - cy[k];
+                const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+                if (power > 0.f) continue;
+                const float G = __expf(power);
+                const float araw = r1.y * G;
+                const float alpha = fminf(amax, araw);
+                if (alpha < amin) continue;
+                contrib = true;
+                const float om = 1.f - alpha;
+                const float Tk = Tr[k] / om;
+                const float w = alpha * Tk;
+                // colour / depth adjoints
+                g[6] += w * gC0[k];
+                g[7] += w * gC1[k];
+                g[8] += w * gC2[k];
+                g[9] += w * gD[k];
+                const float ga = Tk * (gC0[k] * r2.y + gC1[k] * r2.z + gC2[k] * r2.w + gD[k] * r1.z + gA[k]) -
+                                 (gC0[k] * S0[k] + gC1[k] * S1[k] + gC2[k] * S2[k] + gD[k] * SD[k] +
+                                  gA[k] * SA[k] + bgt[k]) / om;
+                S0[k] += w * r2.y;
+                S1[k] += w * r2.z;
+                S2[k] += w * r2.w;
+                SD[k] += w * r1.z;
+                SA[k] += w;
+                Tr[k] = Tk;
+                if (araw <= amax) {
+                    const float gp = ga * alpha;  // dL/dpower
+                    g[5] += ga * G;               // dL/do
+                    g[0] += -gp * (r0.z * dx + r0.w * dy);
+                    g[1] += -gp * (r0.w * dx + r1.x * dy);
+                    g[2] += -0.5f * gp * dx * dx;
+                    g[3] += -gp * dx * dy;
+                    g[4] += -0.5f * gp * dy * dy;
+                }
+            }
+            if (__ballot(contrib) == 0ull) continue;
+            const float tot = wave_transpose_sum16(g);
+            const int slot = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && slot < kGrad2d)
+                atomicAdd(a.grad2d + (long long)sq[j - lo] * kGrad2dStride + slot, tot);
+        }
+        __syncthreads();
+    }
+}
+
+int raster_blocks(const ViewTable& vt) { return vt.tile_base[vt.n_views]; }
+
+#define AGS_RASTER_CONFIGS(X) \
+    X(8, 1, 64)               \
+    X(8, 1, 128)              \
+    X(16, 1, 128)             \
+    X(16, 1, 256)             \
+    X(16, 2, 128)             \
+    X(16, 2, 256)             \
+    X(16, 4, 64)              \
+    X(32, 4, 256)             \
+    X(32, 2, 512)
+
+int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_t s) {
+    const int nb = raster_blocks(a.vt);
+    if (nb <= 0) return 0;
+#define X(t_, p_, m_)                                                                              \
+    if (T == t_ && ppt == p_ && batch == m_) {                                                     \
+        hipLaunchKernelGGL((raster_fwd_kernel<t_, p_, m_>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        return 0;                                                                                  \
+    }
+    AGS_RASTER_CONFIGS(X)
+#undef X
+    return AGS_ERR_NOT_SUPPORTED;
+}
+
+int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s) {
+    const int nb = raster_blocks(a.vt);
+    if (nb <= 0) return 0;
+#define X(t_, p_, m_)                                                                              \
+    if (T == t_ && ppt == p_ && batch == m_) {                                                     \
+        hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        return 0;                                                                                  \
+    }
+    AGS_RASTER_CONFIGS(X)
+#undef X
+    return AGS_ERR_NOT_SUPPORTED;
+}
+
+}  // namespace ags

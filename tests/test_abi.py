@@ -1,0 +1,104 @@
+"""The C-ABI library loads and exports every function include/agsplat.h declares; host-only
+calls (version, error strings, defaults, buffer sizing and argument validation) behave as
+documented.  No call here touches a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "agsplat.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2510_26358_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2510_26358_amd import build
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ags_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_2510_26358_amd import _lib
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_version_errors_and_defaults(lib):
+    from paper_2510_26358_amd import _lib as L
+    assert lib.ags_version() == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.ags_error_string(code)
+    cfg = L.Config()
+    lib.ags_config_default(C.byref(cfg))
+    assert abs(cfg.alpha_min - 1 / 255) < 1e-9 and abs(cfg.alpha_max - 0.99) < 1e-7
+    assert abs(cfg.t_min - 1e-4) < 1e-10 and cfg.tile == 16 and cfg.batch == 256
+
+
+def _views(ws, hs, g0, g1):
+    from paper_2510_26358_amd.rasterizer import ViewSpec
+    return ViewSpec(ws, hs, g0, g1)
+
+
+def test_buffer_sizes_layout(lib):
+    from paper_2510_26358_amd import _lib as L
+    cfg = L.Config()
+    lib.ags_config_default(C.byref(cfg))
+    v = _views([1280, 640], [800, 400], [0, 100], [1000, 1000])
+    s = L.Sizes()
+    assert lib.ags_buffer_sizes(C.byref(cfg), C.byref(v.c), 1000, 3, 12345, C.byref(s)) == 0
+    assert s.n_pairs == 1000 + 900
+    assert s.n_pixels == 1280 * 800 + 640 * 400
+    assert s.n_tiles == 80 * 50 + 40 * 25
+    assert s.tile_bits == 13  # 5000 tiles
+    offs = [s.off_counters, s.off_records, s.off_pair_count, s.off_tile_pairs, s.off_ranges,
+            s.off_t_final, s.off_last]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+    assert s.off_records - s.off_counters >= 16
+    assert s.off_pair_count - s.off_records >= 1900 * 48
+    assert s.off_ranges - s.off_tile_pairs >= 12345 * 4
+    assert s.saved_bytes >= s.off_last + 4 * s.n_pixels
+
+
+@pytest.mark.parametrize("case", ["views0", "gend", "gneg", "width0", "tile", "batch", "cap", "deg"])
+def test_buffer_sizes_rejects_bad_arguments(lib, case):
+    from paper_2510_26358_amd import _lib as L
+    cfg = L.Config()
+    lib.ags_config_default(C.byref(cfg))
+    ws, hs, g0, g1, n, deg, cap = [64], [48], [0], [10], 10, 0, 100
+    if case == "gend":
+        g1 = [11]
+    if case == "gneg":
+        g0 = [-1]
+    if case == "width0":
+        ws = [0]
+    if case == "tile":
+        cfg.tile = 12
+    if case == "batch":
+        cfg.batch = 100
+    if case == "cap":
+        cap = -1
+    if case == "deg":
+        deg = 4
+    v = _views(ws, hs, g0, g1)
+    if case == "views0":
+        v.c.n_views = 0
+    s = L.Sizes()
+    assert lib.ags_buffer_sizes(C.byref(cfg), C.byref(v.c), n, deg, cap, C.byref(s)) == L.AGS_ERR_INVALID_ARG
+
+
+def test_null_context_is_rejected_without_touching_a_device(lib):
+    from paper_2510_26358_amd import _lib as L
+    assert lib.ags_render_fwd(None, None, None, None, 0, None, None, None, 0, None) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_profile_enable(None, 1) == L.AGS_ERR_INVALID_ARG
