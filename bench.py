@@ -1,0 +1,273 @@
+"""Benchmark: forward + backward Mpixel/s of the batched multi-view rasteriser vs a per-view
+loop of the same kernels, with the L1 + LiDAR-KL loss, on one MI355X.
+
+Workload (default): 1M orchard-row Gaussians (SH degree 3) seen by a 4-camera rig
+(yaw 0, +60, -60, 180 deg) at 1280x800; target images are renders of the unperturbed map,
+the rendered state has means jittered by 1 cm and poses perturbed; LiDAR depth targets on
+~5 % of the pixels.  One step = projection, binning, depth/tile sorts, raster forward,
+LiDAR adjoint, raster backward with the fused L1 prologue, projection/pose backward -- all
+views in one launch per stage.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this build uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixel/s, batched multi-view vs per-view loop, at oracle tolerance"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2510_26358_amd import scenes
+    if name == "multi_view":
+        sc = scenes.multi_view_scene()
+    elif name == "single_view":
+        sc = scenes.single_view_scene()
+    elif name == "refine":
+        sc = scenes.refinement_scene()
+    elif name == "submaps":
+        sc = scenes.submap_scene()
+    elif name == "tiny":
+        sc = scenes.tiny_scene()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return sc
+
+
+def setup(sc, ras):
+    """Upload the perturbed state; targets = renders of the unperturbed map."""
+    import torch
+    from paper_2510_26358_amd import scenes
+    from paper_2510_26358_amd.rasterizer import (LossTargets, SplatParams, ViewSpec, cameras_tensor)
+    views = ViewSpec.from_scene(sc)
+    p_gt = SplatParams.from_scene(sc)
+    cams_gt = cameras_tensor(sc.cameras)
+    out_gt, buf = ras.render(p_gt, cams_gt, views)
+    torch.cuda.synchronize()
+    gt = [out_gt[0][3 * a:3 * b].view(3, h, w).cpu().numpy() for a, b, w, h in
+          zip(views.pix_base[:-1], views.pix_base[1:], views.widths, views.heights)]
+    if sc.name != "tiny":
+        st = scenes.perturb(sc, seed=77)
+    else:
+        st = sc
+    p = SplatParams.from_scene(st)
+    cams = cameras_tensor(st.cameras)
+    tg = LossTargets.from_scene(sc, views, gt=gt if sc.name != "tiny" else None)
+    del out_gt, buf
+    return p, cams, views, tg
+
+
+def calibrate(ras, p, cams, views, headroom=1.15):
+    out, buf = ras.render(p, cams, views)
+    k, v, over, keff = buf.counters()
+    cap = int(k * headroom) + 4096
+    return cap, int(k), int(v)
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k):
+    """Roofline of the slowest stage, from the library's per-stage HIP events over the timed
+    steps.  Algorithmic work per launch is stated in the design doc."""
+    import torch
+    stages = {k: v for k, v in prof.items() if v[1] > 0}
+    name = max(stages, key=lambda k: stages[k][0])
+    ms_avg = stages[name][0] / stages[name][1]
+    P = views.n_pixels
+    last = buf.view(sizes.off_last, P, torch.int32).cpu().numpy().astype(np.int64)
+    evals = int(last.sum())
+    k, v, over, keff = buf.counters()
+    info = {"stage": name, "avg_ms": ms_avg, "pairs_evaluated": evals, "K": int(k), "V": int(v)}
+    if name in ("raster_bwd", "raster_fwd"):
+        flops_per = 60 if name == "raster_bwd" else 22
+        achieved = evals * flops_per / (ms_avg * 1e-3) / 1e12
+        rf = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+              "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    else:
+        # HBM-bound stages: algorithmic bytes per launch
+        F = 11 + 3 * sh_k
+        Q = sizes.n_pairs
+        if name == "project_bwd":
+            by = 4 * F * n_gauss * 2 + 40 * int(v) + 48 * int(v)
+        elif name == "project_fwd":
+            by = 4 * F * n_gauss + 52 * int(v) + 4 * Q
+        else:
+            by = 4 * 4 * Q + 8 * 4 * int(v) + 2 * 16 * int(keff)
+        achieved = by / (ms_avg * 1e-3) / 1e9
+        rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    return rf, info
+
+
+def cpu_baseline(sc, sample_px=1024, seed=5):
+    """The FP64 oracle (unmodified) timed on the host: fwd + bwd of the same loss on a seeded
+    sample of view 0's pixels (L1 mask = the sample, LiDAR targets inside it)."""
+    import torch
+    from oracle.render import loss_and_grads
+    from oracle.settings import RenderSettings
+    rng = np.random.default_rng(seed)
+    cam = sc.cameras[0]
+    pix = np.sort(rng.choice(cam.width * cam.height, sample_px, replace=False))
+    sub = sc.copy()
+    sub.cameras = [sub.cameras[0]]
+    sub.gt_rgb = [sub.gt_rgb[0]] if sub.gt_rgb else [np.zeros((3, cam.height, cam.width), np.float32)]
+    lid = sc.lidar[0] if sc.lidar else {"pix": np.zeros(0, np.int32)}
+    keep = np.isin(lid["pix"], pix)
+    sub.lidar = [{k: np.asarray(v)[keep] for k, v in lid.items()}]
+    t0 = time.perf_counter()
+    loss_and_grads(sub, RenderSettings(), masks=[pix])
+    dt = time.perf_counter() - t0
+    return {"value": round(sample_px / dt / 1e6, 8), "unit": "Mpixel/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample_px} seeded pixels of view 0 (L1 + LiDAR inside the sample), fwd+bwd over all "
+                      f"{sc.n} Gaussians, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="multi_view")
+    ap.add_argument("--tile", default="auto", help="8, 16, 32 or auto (autotuner)")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--ppt", type=int, default=1)
+    ap.add_argument("--no-loop", action="store_true", help="skip the per-view loop comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
+              f"design in DESIGN.md, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_26358_amd.rasterizer import Rasterizer
+
+    t0 = time.perf_counter()
+    sc = make_workload(args.workload)
+    log(f"[bench] workload {sc.name}: N={sc.n}, views={len(sc.cameras)}, P={sc.n_pixels} "
+        f"(generated in {time.perf_counter() - t0:.1f}s)")
+    auto = args.tile == "auto"
+    ras = Rasterizer(0, tile=16 if auto else int(args.tile), batch=args.batch, px_per_thread=args.ppt)
+    p, cams, views, tg = setup(sc, ras)
+    tuned = None
+    if auto:
+        from paper_2510_26358_amd.tune import tune
+        tuned = tune(ras, p, cams, views, tg, use_cache=False, log=log)
+        log(f"[bench] autotuner picked tile/batch/ppt = {tuned['best']}")
+    tile, batch, ppt = ras.cfg.tile, ras.cfg.batch, ras.cfg.px_per_thread
+    cap, K, V = calibrate(ras, p, cams, views)
+    log(f"[bench] V={V} visible pairs, K={K} intersections, capacity {cap}")
+    buf = ras.buffers(views, p.n, p.sh_degree, cap)
+    out = ras.outputs(views)
+    grads = p.zeros_like()
+    pose = torch.zeros(views.n_views, 6, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+
+    def step():
+        ras.forward_into(p, cams, views, buf, out)
+        ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+
+    t_b = time_steps(step, args.steps, args.warmup)
+    P = views.n_pixels
+    mpx = P / t_b / 1e6
+    log(f"[bench] batched: {t_b * 1e3:.3f} ms/step, {mpx:.1f} Mpixel/s, loss {loss.item():.5f}")
+    assert buf.counters()[2] == 0, "capacity overflow during timing"
+
+    # per-stage times over a second timed pass with events enabled
+    roof, info = None, None
+    if not args.no_profile:
+        ras.profile(True)
+        ras.profile_reset()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof = ras.profile_read()
+        ras.profile(False)
+        stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1] > 0}
+        log(f"[bench] per-stage avg ms: {stage_ms}")
+        roof, info = dominant_roofline(prof, views, buf, buf.sizes, args.steps, p.n,
+                                       (p.sh_degree + 1) ** 2)
+        info["stage_ms"] = stage_ms
+
+    loop = None
+    if not args.no_loop and views.n_views > 1:
+        from paper_2510_26358_amd.rasterizer import LossTargets
+        per = []
+        for b in range(views.n_views):
+            vb = views.subset(b)
+            cb = cams[b:b + 1].contiguous()
+            capb, _, _ = calibrate(ras, p, cb, vb)
+            bb = ras.buffers(vb, p.n, p.sh_degree, capb)
+            ob = ras.outputs(vb)
+            pb = views.pix_base
+            tgb = LossTargets(tg.gt_rgb[3 * pb[b]:3 * pb[b + 1]], None, [tg.l1_count[b]],
+                              tg.depth_pix[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
+                              tg.depth_val[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
+                              tg.depth_sigma[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
+                              [0, tg.depth_offsets[b + 1] - tg.depth_offsets[b]], tg.w_l1, tg.lambda_lidar)
+            per.append((vb, cb, bb, ob, tgb, torch.zeros(1, 6, device="cuda")))
+
+        def loop_step():
+            for b, (vb, cb, bb, ob, tgb, pz) in enumerate(per):
+                ras.forward_into(p, cb, vb, bb, ob)
+                ras.backward_into(p, cb, vb, bb, ob, grads, pz, loss=tgb, loss_out=loss, accumulate=b > 0)
+
+        t_l = time_steps(loop_step, args.steps, args.warmup)
+        loop = {"value": round(P / t_l / 1e6, 2), "ms_per_step": round(t_l * 1e3, 4),
+                "speedup_batched": round(t_l / t_b, 3)}
+        log(f"[bench] per-view loop: {t_l * 1e3:.3f} ms/step, {P / t_l / 1e6:.1f} Mpixel/s "
+            f"(batched speedup {t_l / t_b:.2f}x)")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the FP64 oracle on a pixel sample (host CPU)...")
+        cpu = cpu_baseline(sc)
+        log(f"[bench] cpu oracle: {cpu}")
+
+    rec = {
+        "metric": METRIC, "value": round(mpx, 2), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "n_gaussians": sc.n, "views": views.n_views,
+                   "resolution": [[w, h] for w, h in zip(views.widths, views.heights)],
+                   "pixels": P, "sh_degree": sc.sh_degree, "loss": "L1 + LiDAR KL",
+                   "tile": tile, "lds_batch": batch, "px_per_thread": ppt,
+                   "autotuned": None if tuned is None else tuned["ms"],
+                   "visible_pairs": V, "intersections": K},
+        "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -58,7 +58,7 @@ struct Layout {
     size_t f_pair_z, f_vis_off, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_hist_sums, f_block_sums, f_total;
     // bwd ws
-    size_t b_grad2d, b_ddepth, b_partials, b_total;
+    size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_total;
     long long n_partials;
 };
 
@@ -156,6 +156,8 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
     L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
     L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
+    L.b_pose_part = o; o = align_up(o + (size_t)(project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
+                                         views->n_views * 6 * 4);
     L.b_total = o;
     return AGS_OK;
 }
@@ -480,7 +482,6 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     {
         Scope sc(ctx, ST_CLEAR, s);
         launch_fill_f32(grad2d, 0.f, L.Q * kGrad2dStride, s);
-        if (!grads->accumulate) launch_fill_f32(grads->pose, 0.f, 6LL * views->n_views, s);
         if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
         if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, L.n_partials - L.n_tiles, s);
     }
@@ -558,6 +559,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.g_sh = grads->sh;
         pa.g_pose = grads->pose;
         pa.accumulate = grads->accumulate;
+        pa.pose_partials = at<float>(ws, L.b_pose_part);
         launch_project_bwd(pa, s);
     }
     if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);

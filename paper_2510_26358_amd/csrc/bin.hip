@@ -32,34 +32,58 @@ __global__ void finalize_counts_kernel(uint32_t* counters, long long capacity) {
     counters[CNT_KEFF] = over ? (uint32_t)capacity : k;
 }
 
-// One thread per visible pair in depth order: write its tiles' ids and the pair id.
+// One thread per output slot k: the owning pair is the last j (depth order) with
+// emit_off[j] <= k; slot k - emit_off[j] of that pair's tile rectangle (row-major) gives
+// the tile.  Every visible pair owns >= 1 slot, so the 256 slots of a workgroup belong to at
+// most 256 consecutive pairs: one global binary search per workgroup finds the first, the
+// following 257 offsets are staged in LDS and each thread searches there.  Balanced however
+// unequal the footprints are, and the writes are coalesced.
 __global__ __launch_bounds__(256) void emit_kernel(ViewTable vt, const float* records,
-                                                   const uint32_t* pair_count,
                                                    const uint32_t* depth_vals, const uint32_t* emit_off,
                                                    const uint32_t* counters, long long capacity,
-                                                   long long n_max, uint32_t* tile_keys,
-                                                   uint32_t* tile_vals) {
-    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long nv = counters[CNT_V];
-    if (j >= nv || j >= n_max) return;
-    const uint32_t q = depth_vals[j];
+                                                   uint32_t* tile_keys, uint32_t* tile_vals) {
+    __shared__ uint32_t s_off[257];
+    __shared__ long long s_j0;
+    const long long k0 = (long long)blockIdx.x * 256;
+    long long keff = counters[CNT_KEFF];
+    if (keff > capacity) keff = capacity;
+    const long long nv = counters[CNT_V];
+    if (k0 >= keff || nv == 0) return;  // uniform per workgroup
+    if (threadIdx.x == 0) {
+        long long lo = 0, hi = nv - 1;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if ((long long)emit_off[mid] <= k0) lo = mid;
+            else hi = mid - 1;
+        }
+        s_j0 = lo;
+    }
+    __syncthreads();
+    const long long j0 = s_j0;
+    for (int t = threadIdx.x; t < 257; t += 256) {
+        const long long j = j0 + t;
+        s_off[t] = j < nv ? emit_off[j] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    const long long k = k0 + threadIdx.x;
+    if (k >= keff) return;
+    int lo = 0, hi = 256;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((long long)s_off[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const long long r = k - (long long)s_off[lo];
+    const uint32_t q = depth_vals[j0 + lo];
     const int b = view_of_pair(vt, q);
     const float4* rec = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-    int tx0, ty0, tx1, ty1;
-    if (!tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1))
-        return;
-    long long k = emit_off[j];
-    const int ntx = vt.ntx[b];
-    const int tb = vt.tile_base[b];
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = tx0; tx <= tx1; ++tx, ++k) {
-            if (k < capacity) {
-                tile_keys[k] = (uint32_t)(tb + ty * ntx + tx);
-                tile_vals[k] = q;
-            }
-        }
-    }
+    int tx0 = 0, ty0 = 0, tx1 = 0, ty1 = 0;
+    tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1);
+    const int w = tx1 - tx0 + 1;
+    const int tx = tx0 + (int)(r % w), ty = ty0 + (int)(r / w);
+    tile_keys[k] = (uint32_t)(vt.tile_base[b] + ty * vt.ntx[b] + tx);
+    tile_vals[k] = q;
 }
 
 __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* counters, long long n_max,
@@ -117,8 +141,9 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     //    number of tile-sort passes ends in final_vals
     const int tp = sort_passes(a.tile_bits);
     const int first = (a.final_vals == a.tile_vals[0]) ? (tp % 2) : 1 - (tp % 2);
-    hipLaunchKernelGGL(emit_kernel, dim3(qgrid), dim3(256), 0, s, a.vt, a.records, a.pair_count, dvals,
-                       a.emit_off, a.counters, a.capacity, Q, a.tile_keys[first], a.tile_vals[first]);
+    const unsigned kgrid = (unsigned)((a.capacity + 255) / 256 > 0 ? (a.capacity + 255) / 256 : 1);
+    hipLaunchKernelGGL(emit_kernel, dim3(kgrid), dim3(256), 0, s, a.vt, a.records, dvals, a.emit_off,
+                       a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first]);
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};
     uint32_t* tv[2] = {a.tile_vals[first], a.tile_vals[1 - first]};
@@ -126,7 +151,6 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     // 6. per-tile ranges
     const long long n_tiles = a.vt.tile_base[a.vt.n_views];
     launch_fill_u32(a.ranges, 0u, 2 * n_tiles, s);
-    const unsigned kgrid = (unsigned)((a.capacity + 255) / 256 > 0 ? (a.capacity + 255) / 256 : 1);
     hipLaunchKernelGGL(ranges_kernel, dim3(kgrid), dim3(256), 0, s, tk[rt], a.counters, a.capacity,
                        a.ranges);
     (void)tv;

@@ -146,6 +146,47 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
     dY[15][2] = 0.f;
 }
 
+// sum_k w[k] grad Y_k(x, y, z) for k >= 1, without materialising the 16 x 3 Jacobian.
+__device__ __forceinline__ void sh_grad_dot(int deg, float x, float y, float z, const float* w, float* g) {
+    g[0] = g[1] = g[2] = 0.f;
+    if (deg < 1) return;
+    g[0] += -SHConst::c1 * w[3];
+    g[1] += -SHConst::c1 * w[1];
+    g[2] += SHConst::c1 * w[2];
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    g[0] += SHConst::c2a * (y * w[4] - z * w[7]) + SHConst::c2b * (-2.f * x) * w[6] + 2.f * SHConst::c2c * x * w[8];
+    g[1] += SHConst::c2a * (x * w[4] - z * w[5]) + SHConst::c2b * (-2.f * y) * w[6] - 2.f * SHConst::c2c * y * w[8];
+    g[2] += -SHConst::c2a * (y * w[5] + x * w[7]) + 4.f * SHConst::c2b * z * w[6];
+    if (deg < 3) return;
+    g[0] += -6.f * SHConst::c3a * x * y * w[9] + SHConst::c3b * y * z * w[10] +
+            2.f * SHConst::c3c * x * y * w[11] - 6.f * SHConst::c3d * x * z * w[12] -
+            SHConst::c3c * (4.f * zz - 3.f * xx - yy) * w[13] + 2.f * SHConst::c3e * x * z * w[14] -
+            SHConst::c3a * (3.f * xx - 3.f * yy) * w[15];
+    g[1] += -SHConst::c3a * (3.f * xx - 3.f * yy) * w[9] + SHConst::c3b * x * z * w[10] -
+            SHConst::c3c * (4.f * zz - xx - 3.f * yy) * w[11] - 6.f * SHConst::c3d * y * z * w[12] +
+            2.f * SHConst::c3c * x * y * w[13] - 2.f * SHConst::c3e * y * z * w[14] +
+            6.f * SHConst::c3a * x * y * w[15];
+    g[2] += SHConst::c3b * x * y * w[10] - 8.f * SHConst::c3c * y * z * w[11] +
+            SHConst::c3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12] - 8.f * SHConst::c3c * x * z * w[13] +
+            SHConst::c3e * (xx - yy) * w[14];
+}
+
+// Row r of a structure-of-arrays buffer with n columns: a wave-uniform base pointer, so
+// per-lane accesses need only the 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ T* sh_row(T* base, int n, int r) {
+    return base + (size_t)r * (size_t)n;
+}
+
+// Returns p unchanged but opaque to the optimiser (an empty asm on a scalar register), so
+// addresses derived from it inside a loop are not hoisted into long-lived vector registers.
+template <typename T>
+__device__ __forceinline__ T* opaque_ptr(T* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 // Unit quaternion (w, x, y, z) -> row-major rotation matrix.
 __device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
     R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
@@ -162,28 +203,34 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
-// Sum of 16 per-lane values over the wave; lane L returns the total of slot (L >> 2) & 15.
+// Sum of 16 per-lane values over the 64-lane wave (a transposing butterfly).  On return
+// lane L holds the total of slot (L >> 2) & 15.  Each stage pairs lanes that differ in one
+// selector bit; a lane keeps the half of its slots named by that bit and adds the
+// partner's copy of the same half.  Bits 5 and 4 use the gfx950 lane-swap instructions
+// (v_permlane32_swap / v_permlane16_swap exchange exactly those halves, so keep + partner
+// is result[0] + result[1] on every lane); bits 3 and 2 use DPP row_ror:8 and
+// row_half_mirror (involutions pairing lanes that differ in that bit); bits 1 and 0 are
+// quad permutations.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
     const int lane = __lane_id();
     float w8[8];
-    {
-        const bool hi = lane & 32;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float send = hi ? v[j] : v[j + 8];
-            const float keep = hi ? v[j + 8] : v[j];
-            w8[j] = keep + __shfl_xor(send, 32, 64);
-        }
+    for (int j = 0; j < 8; ++j) {
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 8]), false,
+                                                  false);
+        w8[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
     float w4[4];
-    {
-        const bool hi = lane & 16;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float send = hi ? w8[j] : w8[j + 4];
-            const float keep = hi ? w8[j + 4] : w8[j];
-            w4[j] = keep + __shfl_xor(send, 16, 64);
-        }
+    for (int j = 0; j < 4; ++j) {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[j]), __float_as_uint(w8[j + 4]), false,
+                                                  false);
+        w4[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
     float w2[2];
     {
@@ -192,7 +239,7 @@ __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
         for (int j = 0; j < 2; ++j) {
             const float send = hi ? w4[j] : w4[j + 2];
             const float keep = hi ? w4[j + 2] : w4[j];
-            w2[j] = keep + __shfl_xor(send, 8, 64);
+            w2[j] = keep + dpp_mov<0x128>(send);  // row_ror:8 == lane ^ 8 inside a row
         }
     }
     float w1;
@@ -200,13 +247,12 @@ __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
         const bool hi = lane & 4;
         const float send = hi ? w2[0] : w2[1];
         const float keep = hi ? w2[1] : w2[0];
-        w1 = keep + __shfl_xor(send, 4, 64);
+        w1 = keep + dpp_mov<0x141>(send);  // row_half_mirror: lane i <-> 7 - i in 8-lane halves
     }
-    w1 += __shfl_xor(w1, 1, 64);
-    w1 += __shfl_xor(w1, 2, 64);
+    w1 += dpp_mov<0xB1>(w1);  // quad_perm [1, 0, 3, 2]: lane ^ 1
+    w1 += dpp_mov<0x4E>(w1);  // quad_perm [2, 3, 0, 1]: lane ^ 2
     return w1;
 }
-
 
 // Host-side launchers (one per kernel family), defined next to their kernels.
 struct ProjectArgs {
@@ -338,8 +384,10 @@ struct ProjectBwdArgs {
     const uint32_t* pair_count;
     const float* grad2d;
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
+    float* pose_partials;  // [project_bwd_blocks(n)][n_views][6]
     int accumulate;
 };
+int project_bwd_blocks(int n);
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
 
 struct AdamArgs {

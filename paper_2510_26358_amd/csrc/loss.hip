@@ -47,18 +47,22 @@ void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s) {
 }
 
 // Deterministic sum of the per-block loss partials (fixed order, one workgroup).
-__global__ __launch_bounds__(256) void sum_partials_kernel(const float* p, long long n, float* out) {
-    __shared__ float sred[4];
+__global__ __launch_bounds__(1024) void sum_partials_kernel(const float* p, long long n, float* out) {
+    __shared__ float sred[16];
     float s = 0.f;
-    for (long long i = threadIdx.x; i < n; i += 256) s += p[i];
+    for (long long i = threadIdx.x; i < n; i += 1024) s += p[i];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = sred[0] + sred[1] + sred[2] + sred[3];
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int w = 0; w < 16; ++w) t += sred[w];
+        out[0] = t;
+    }
 }
 
 void launch_sum_partials(const float* partials, long long n, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, n, out);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, out);
 }
 
 }  // namespace ags

@@ -44,9 +44,6 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
     const float S22 = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
     const float lnterm = 2.f * __logf(255.f * o);
 
-    float f[K][3];
-    bool sh_loaded = false;
-
     for (int b = 0; b < vt.n_views; ++b) {
         if (i < vt.g_begin[b] || i >= vt.g_end[b]) continue;
         const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
@@ -89,13 +86,6 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
                 int tx0, ty0, tx1, ty1;
                 if (tile_rect(u, v, ex, ey, W, H, vt.tile, tx0, ty0, tx1, ty1)) {
                     cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-                    if (!sh_loaded) {
-#pragma unroll
-                        for (int k = 0; k < K; ++k)
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) f[k][c] = a.sh[(long long)(k * 3 + c) * n + i];
-                        sh_loaded = true;
-                    }
                     // camera centre C = -R^T t; direction d = (mu - C) / |mu - C|
                     const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
                     const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
@@ -105,14 +95,15 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
                     dx *= il; dy *= il; dz *= il;
                     float Y[16];
                     sh_basis(DEG, dx, dy, dz, Y);
-                    float col[3];
+                    // coefficients are streamed (a second visible view hits the cache)
+                    const float* shp = opaque_ptr(a.sh);
+                    float col[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float acc = 0.f;
+                    for (int k = 0; k < K; ++k)
 #pragma unroll
-                        for (int k = 0; k < K; ++k) acc += Y[k] * f[k][c];
-                        col[c] = fmaxf(acc + 0.5f, 0.f);
-                    }
+                        for (int c = 0; c < 3; ++c) col[c] += Y[k] * sh_row(shp, n, k * 3 + c)[(uint32_t)i];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) col[c] = fmaxf(col[c] + 0.5f, 0.f);
                     float4* rec = reinterpret_cast<float4*>(a.records + q * kRecFloats);
                     rec[0] = make_float4(u, v, cc * idet, -cb * idet);
                     rec[1] = make_float4(ca * idet, o, z, ex);

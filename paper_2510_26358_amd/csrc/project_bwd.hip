@@ -12,12 +12,15 @@
 // Pose, left perturbation W_b <- Exp(delta) W_b with delta = (rho, phi):
 //   g_rho += g_xc + R_b g_dir (the camera centre moves by -R_b^T rho),
 //   g_phi += x_c x g_xc + (N_12 - N_21, N_20 - N_02, N_01 - N_10), N = R_b G_T^T J.
-// The per-view pose sums are reduced over the wave (transposing butterfly) and added with
-// one atomic instruction per wave.  Shared-Gaussian terms (Sigma -> scale, rotation;
+// The per-view pose sums are reduced over the wave (transposing butterfly), then over the
+// workgroup in LDS, into one partial per workgroup and view; a second kernel adds the
+// partials in a fixed order (deterministic, and no contention on the 6 B floats).  Shared-Gaussian terms (Sigma -> scale, rotation;
 // opacity -> logit) are chained once after the view loop.
 #include "common.h"
 
 namespace ags {
+
+void launch_project_bwd_main(const ProjectBwdArgs& a, hipStream_t s);
 
 template <int DEG>
 __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
@@ -26,7 +29,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     const bool active = i < a.n;
     const int n = a.n;
     const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
     const ViewTable& vt = a.vt;
+    __shared__ float spose[kMaxViews][6][4];
+    for (int t = threadIdx.x; t < kMaxViews * 6 * 4; t += 256) (&spose[0][0][0])[t] = 0.f;
+    __syncthreads();
 
     float mx = 0.f, my = 0.f, mz = 0.f, ls0 = 0.f, ls1 = 0.f, ls2 = 0.f;
     float qw = 1.f, qx = 0.f, qy = 0.f, qz = 0.f, logit = 0.f;
@@ -40,28 +47,21 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     const float qn2 = qw * qw + qx * qx + qy * qy + qz * qz;
     const float qinv = rsqrtf(qn2);
     const float uw = qw * qinv, ux = qx * qinv, uy = qy * qinv, uz = qz * qinv;
-    float Rq[9];
-    quat_to_rot(uw, ux, uy, uz, Rq);
-    float M[9] = {Rq[0] * s0, Rq[1] * s1, Rq[2] * s2, Rq[3] * s0, Rq[4] * s1, Rq[5] * s2,
-                  Rq[6] * s0, Rq[7] * s1, Rq[8] * s2};
     float Sg[3][3];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            Sg[r][c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    {
+        float Rq[9];
+        quat_to_rot(uw, ux, uy, uz, Rq);
+        const float M[9] = {Rq[0] * s0, Rq[1] * s1, Rq[2] * s2, Rq[3] * s0, Rq[4] * s1, Rq[5] * s2,
+                            Rq[6] * s0, Rq[7] * s1, Rq[8] * s2};
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                Sg[r][c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    }
 
     float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
-    float f[K][3];
-    float gf[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            gf[k][c] = 0.f;
-            f[k][c] = 0.f;
-        }
-    bool f_loaded = false;
+    bool sh_written = a.accumulate != 0;
 
     for (int b = 0; b < vt.n_views; ++b) {
         const bool in_range = active && i >= vt.g_begin[b] && i < vt.g_end[b];
@@ -71,17 +71,10 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) pose[k] = 0.f;
         if (vis) {
-            if (!f_loaded) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) f[k][c] = a.sh[(long long)(k * 3 + c) * n + i];
-                f_loaded = true;
-            }
-            const float* g2 = a.grad2d + q * kGrad2dStride;
+            const float* g2 = opaque_ptr(a.grad2d) + q * kGrad2dStride;
             const float g_u = g2[0], g_v = g2[1], g_a = g2[2], g_b = g2[3], g_c = g2[4];
             const float g_o = g2[5], g_r = g2[6], g_g = g2[7], g_bl = g2[8], g_zd = g2[9];
-            const ags_camera cam = a.cams[b];
+            const ags_camera cam = opaque_ptr(a.cams)[b];
             const float* R = cam.R;
             const float x = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
             const float y = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
@@ -171,28 +164,43 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             float Y[16];
             sh_basis(DEG, dx, dy, dz, Y);
             const float grgb[3] = {g_r, g_g, g_bl};
-            float gcol[3];
+            // One pass over the coefficients per channel gives the raw colour and its
+            // gradient in the direction, G_c = sum_k f_kc grad Y_k; then g_dir = sum_c gcol_c G_c.
+            const float* shp = opaque_ptr(a.sh);
+            float* gshp = opaque_ptr(a.g_sh);
+            float raw[3], G[3][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                float w[16];
+#pragma unroll
+                for (int k = 0; k < K; ++k) w[k] = sh_row(shp, n, k * 3 + c)[(uint32_t)i];
                 float acc = 0.5f;
 #pragma unroll
-                for (int k = 0; k < K; ++k) acc += Y[k] * f[k][c];
-                gcol[c] = acc >= 0.f ? grgb[c] : 0.f;
+                for (int k = 0; k < K; ++k) acc += Y[k] * w[k];
+                raw[c] = acc;
+                sh_grad_dot(DEG, dx, dy, dz, w, G[c]);
             }
+            float gcol[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gcol[c] = raw[c] >= 0.f ? grgb[c] : 0.f;
+            // SH-coefficient adjoints go to memory per visible view: a plain store for the
+            // first one (overwrite mode), a return-less atomic add for later views.
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gf[k][c] += Y[k] * gcol[c];
+                for (int c = 0; c < 3; ++c) {
+                    float* dst = sh_row(gshp, n, k * 3 + c) + (uint32_t)i;
+                    if (sh_written) atomicAdd(dst, Y[k] * gcol[c]);
+                    else *dst = Y[k] * gcol[c];
+                }
+            sh_written = true;
             float gdir[3] = {0.f, 0.f, 0.f};
             if (DEG > 0) {
-                float dY[16][3];
-                sh_basis_grad(DEG, dx, dy, dz, dY);
 #pragma unroll
-                for (int k = 1; k < K; ++k) {
-                    const float w = f[k][0] * gcol[0] + f[k][1] * gcol[1] + f[k][2] * gcol[2];
-                    gdir[0] += dY[k][0] * w;
-                    gdir[1] += dY[k][1] * w;
-                    gdir[2] += dY[k][2] * w;
+                for (int c = 0; c < 3; ++c) {
+                    gdir[0] += gcol[c] * G[c][0];
+                    gdir[1] += gcol[c] * G[c][1];
+                    gdir[2] += gcol[c] * G[c][2];
                 }
                 const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
                 gdir[0] = (gdir[0] - dd * dx) * il;
@@ -215,12 +223,22 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         if (__ballot(vis) != 0ull) {
             const float tot = wave_transpose_sum16(pose);
             const int slot = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && slot < 6) atomicAdd(a.g_pose + b * 6 + slot, tot);
+            if ((lane & 3) == 0 && slot < 6) spose[b][slot][wave] = tot;
         }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < vt.n_views * 6; t += 256) {
+        const int b = t / 6, k = t % 6;
+        a.pose_partials[((long long)blockIdx.x * vt.n_views + b) * 6 + k] =
+            spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3];
     }
     if (!active) return;
 
     // Sigma = M M^T, M = Rq diag(s): G_M = 2 G_Sigma M (G_Sigma symmetrised)
+    float Rq[9];
+    quat_to_rot(uw, ux, uy, uz, Rq);
+    const float M[9] = {Rq[0] * s0, Rq[1] * s1, Rq[2] * s2, Rq[3] * s0, Rq[4] * s1, Rq[5] * s2,
+                        Rq[6] * s0, Rq[7] * s1, Rq[8] * s2};
     float GS[3][3];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) GS[r][c] = 0.5f * (GSig[r][c] + GSig[c][r]);
@@ -260,10 +278,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         }
         for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] += gq[c];
         a.g_logits[i] += glogit;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a.g_sh[(long long)(k * 3 + c) * n + i] += gf[k][c];
     } else {
         for (int c = 0; c < 3; ++c) {
             a.g_means[c * n + i] = gmu[c];
@@ -271,15 +285,44 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         }
         for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = gq[c];
         a.g_logits[i] = glogit;
+        if (!sh_written) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a.g_sh[(long long)(k * 3 + c) * n + i] = gf[k][c];
+                for (int c = 0; c < 3; ++c) sh_row(a.g_sh, n, k * 3 + c)[(uint32_t)i] = 0.f;
+        }
     }
 }
 
+// Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component).
+__global__ __launch_bounds__(256) void pose_reduce_kernel(const float* partials, int n_blocks, int n_views,
+                                                         float* pose, int accumulate) {
+    __shared__ float sred[4];
+    const int bk = blockIdx.x;  // b * 6 + k
+    float s = 0.f;
+    for (int g = threadIdx.x; g < n_blocks; g += 256) s += partials[(long long)g * n_views * 6 + bk];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float t = sred[0] + sred[1] + sred[2] + sred[3];
+        pose[bk] = accumulate ? pose[bk] + t : t;
+    }
+}
+
+int project_bwd_blocks(int n) { return n > 0 ? (n + 255) / 256 : 0; }
+
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
-    if (a.n <= 0) return;
+    const int nb = project_bwd_blocks(a.n);
+    if (nb > 0) launch_project_bwd_main(a, s);
+    if (nb > 0)
+        hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, nb,
+                           a.vt.n_views, a.g_pose, a.accumulate);
+    else if (!a.accumulate)
+        launch_fill_f32(a.g_pose, 0.f, 6LL * a.vt.n_views, s);
+}
+
+void launch_project_bwd_main(const ProjectBwdArgs& a, hipStream_t s) {
     dim3 grid((a.n + 255) / 256), block(256);
     switch (a.sh_degree) {
         case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, a); break;

@@ -43,6 +43,19 @@ __device__ __forceinline__ TileCoord tile_coord(const ViewTable& vt, int tile) {
     return c;
 }
 
+// Copy record q into LDS, replacing the footprint extent (not needed by compositing) with
+// ln(alpha_min / o): a Gaussian whose power is below it cannot reach alpha_min, so the exp
+// is skipped.  Forward and backward stage the same value, so their decisions agree.
+__device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, float4* dst) {
+    const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
+    const float4 r0 = r[0], r2 = r[2];
+    float4 r1 = r[1];
+    r1.w = __logf(amin / r1.y);
+    dst[0] = r0;
+    dst[1] = r1;
+    dst[2] = r2;
+}
+
 // Pixel k of thread t: PPT vertically adjacent pixels per thread, so a 64-lane wave covers
 // a compact 16 x 4 * PPT (T = 16) block.
 template <int T, int PPT>
@@ -87,10 +100,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
             const uint32_t e = bs + l;
             if (e < end) {
                 const uint32_t q = a.tile_pairs[e];
-                const float4* r = reinterpret_cast<const float4*>(a.records + (long long)q * kRecFloats);
-                srec[l][0] = r[0];
-                srec[l][1] = r[1];
-                srec[l][2] = r[2];
+                stage_record(a.records, q, amin, srec[l]);
             }
         }
         __syncthreads();
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                     if (done[k]) continue;
                     const float dx = r0.x - cx[k], dy = r0.y - cy[k];
                     const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
-                    if (power > 0.f) continue;
+                    if (power > 0.f || power < r1.w) continue;  // r1.w = ln(alpha_min / o)
                     const float alpha = fminf(amax, r1.y * __expf(power));
                     if (alpha < amin) continue;
                     const float tn = Tr[k] * (1.f - alpha);
@@ -158,6 +168,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
     const int tid = threadIdx.x;
     const int lane = __lane_id();
+    const float amin = a.st.alpha_min;
 
     float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], bgt[PPT];
     float S0[PPT], S1[PPT], S2[PPT], SD[PPT], SA[PPT];
@@ -231,18 +242,13 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
 
-    const float amin = a.st.alpha_min, amax = a.st.alpha_max;
-    const float bg0 = a.st.bg0, bg1 = a.st.bg1, bg2 = a.st.bg2;
-    (void)bg0; (void)bg1; (void)bg2;
+    const float amax = a.st.alpha_max;
 
     for (int hi = (int)maxlast; hi > 0; hi -= M) {
         const int lo = hi - M > 0 ? hi - M : 0;
         for (int l = tid; l < hi - lo; l += NT) {
             const uint32_t q = a.tile_pairs[start + lo + l];
-            const float4* r = reinterpret_cast<const float4*>(a.records + (long long)q * kRecFloats);
-            srec[l][0] = r[0];
-            srec[l][1] = r[1];
-            srec[l][2] = r[2];
+            stage_record(a.records, q, amin, srec[l]);
             sq[l] = q;
         }
         __syncthreads();
@@ -258,14 +264,14 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 if ((uint32_t)j >= last[k]) continue;
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
                 const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
-                if (power > 0.f) continue;
+                if (power > 0.f || power < r1.w) continue;
                 const float G = __expf(power);
                 const float araw = r1.y * G;
                 const float alpha = fminf(amax, araw);
                 if (alpha < amin) continue;
                 contrib = true;
-                const float om = 1.f - alpha;
-                const float Tk = Tr[k] / om;
+                const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
+                const float Tk = Tr[k] * rom;
                 const float w = alpha * Tk;
                 // colour / depth adjoints
                 g[6] += w * gC0[k];
@@ -274,7 +280,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 g[9] += w * gD[k];
                 const float ga = Tk * (gC0[k] * r2.y + gC1[k] * r2.z + gC2[k] * r2.w + gD[k] * r1.z + gA[k]) -
                                  (gC0[k] * S0[k] + gC1[k] * S1[k] + gC2[k] * S2[k] + gD[k] * SD[k] +
-                                  gA[k] * SA[k] + bgt[k]) / om;
+                                  gA[k] * SA[k] + bgt[k]) * rom;
                 S0[k] += w * r2.y;
                 S1[k] += w * r2.z;
                 S2[k] += w * r2.w;

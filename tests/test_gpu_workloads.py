@@ -1,0 +1,216 @@
+"""GPU tests at the benchmark's sizes and launch configuration, plus modes and edge cases.
+
+Full-size scenes are compared with the oracle on seeded pixel samples: the forward on the
+sampled pixels, the gradients with the L1 mask set to the sample and the LiDAR targets
+restricted to it (so both sides differentiate the same objective).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.optim import adam_update, pose_update
+from oracle.render import loss_and_grads, render
+from oracle.settings import RenderSettings
+from paper_2510_26358_amd import scenes
+from paper_2510_26358_amd.rasterizer import (LossTargets, Rasterizer, SplatParams, ViewSpec,
+                                             cameras_tensor, split_views)
+from tests.gpu_helpers import (TOL_ALPHA, TOL_DEPTH_REL, TOL_RGB, grad_close, run_forward,
+                               run_loss_backward)
+from tests.oracle_helpers import random_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ras():
+    return Rasterizer(0)
+
+
+def _sample_pixels(cam, rng, n_tiles=2, n_rand=96, T=16):
+    ntx, nty = (cam.width + T - 1) // T, (cam.height + T - 1) // T
+    pix = []
+    for t in rng.choice(ntx * nty, n_tiles, replace=False):
+        tx, ty = t % ntx, t // ntx
+        ys, xs = np.mgrid[ty * T:min(cam.height, ty * T + T), tx * T:min(cam.width, tx * T + T)]
+        pix.append((ys * cam.width + xs).ravel())
+    pix.append(rng.choice(cam.width * cam.height, n_rand, replace=False))
+    return np.unique(np.concatenate(pix))
+
+
+def _restrict_lidar(lid, pix):
+    keep = np.isin(lid["pix"], pix)
+    return {k: np.asarray(v)[keep] for k, v in lid.items()}
+
+
+@pytest.mark.parametrize("maker", ["single_view", "multi_view"])
+def test_full_size_forward_and_gradients_on_pixel_samples(ras, maker):
+    sc = scenes.CONFIGS[maker]()
+    rng = np.random.default_rng(4242)
+    samples = [_sample_pixels(c, rng) for c in sc.cameras]
+    sc.lidar = [_restrict_lidar(l, p) for l, p in zip(sc.lidar, samples)]
+    g = run_loss_backward(sc, ras, masks=samples, w_l1=1.0, lam=0.1)
+    ref = loss_and_grads(sc, RenderSettings(), masks=samples, w_l1=1.0, lam=0.1)
+    # forward on the sampled pixels
+    for b, (gv, rv) in enumerate(zip(g["fwd"], ref["views"])):
+        pix = rv["pix"]
+        ok = ~rv["ambiguous"]
+        rgb = gv["rgb"].reshape(3, -1)[:, pix].T
+        e_rgb = np.abs(rgb - rv["rgb"])[ok].max(initial=0)
+        e_a = np.abs(gv["alpha"].reshape(-1)[pix] - rv["alpha"])[ok].max(initial=0)
+        e_d = (np.abs(gv["depth"].reshape(-1)[pix] - rv["depth"]) / np.maximum(1, np.abs(rv["depth"])))[ok].max(initial=0)
+        print(f"view {b}: {len(pix)} px, ambiguous {rv['ambiguous'].sum()}, rgb {e_rgb:.2e} alpha {e_a:.2e} depth {e_d:.2e}")
+        assert e_rgb <= TOL_RGB and e_a <= TOL_ALPHA and e_d <= TOL_DEPTH_REL
+        assert rv["ambiguous"].mean() <= 0.02
+    print("loss", g["loss"], ref["loss"], "excluded gaussians", ref["amb_gauss"].sum())
+    assert abs(g["loss"] - ref["loss"]) <= 1e-4 * max(1.0, abs(ref["loss"]))
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ok, msg = grad_close(g["grads"][name], ref["grads"][name], ref["amb_gauss"])
+        print(name, msg)
+        assert ok, (name, msg)
+    ok, msg = grad_close(g["pose"], ref["pose"])
+    print("pose", msg)
+    assert ok, msg
+
+
+def test_batched_forward_is_bit_identical_to_per_view(ras):
+    sc = random_scene(301, n=600, sh_degree=2, n_views=2, width=80, height=56, f=70.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    out, _ = ras.render(p, cams, views)
+    batched = split_views(*out, views)
+    for b in range(views.n_views):
+        vb = views.subset(b)
+        ob, _ = ras.render(p, cams[b:b + 1].contiguous(), vb)
+        single = split_views(*ob, vb)[0]
+        for x, y in zip(batched[b], single):
+            assert torch.equal(x, y)
+
+
+def test_upstream_mode_gradients(ras):
+    sc = random_scene(311, n=300, sh_degree=3, n_views=2, width=64, height=48, f=60.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    out, buf = ras.render(p, cams, views)
+    rng = np.random.default_rng(312)
+    up = []
+    flat = [[], [], []]
+    for c in sc.cameras:
+        u = {"rgb": rng.normal(size=(3, c.height, c.width)).astype(np.float32),
+             "depth": rng.normal(size=(c.height, c.width)).astype(np.float32),
+             "alpha": rng.normal(size=(c.height, c.width)).astype(np.float32)}
+        up.append(u)
+        flat[0].append(u["rgb"].ravel())
+        flat[1].append(u["depth"].ravel())
+        flat[2].append(u["alpha"].ravel())
+    ups = tuple(torch.from_numpy(np.concatenate(f)).cuda() for f in flat)
+    grads = p.zeros_like()
+    pose = torch.zeros(views.n_views, 6, device="cuda")
+    ras.backward_into(p, cams, views, buf, out, grads, pose, upstream=ups)
+    torch.cuda.synchronize()
+    ref = loss_and_grads(sc, RenderSettings(), upstream=up)
+    names = ["means", "log_scales", "quats", "opacity_logits", "sh"]
+    for name, gg in zip(names, grads.to_numpy_aos()):
+        ok, msg = grad_close(gg, ref["grads"][name], ref["amb_gauss"])
+        print(name, msg)
+        assert ok, (name, msg)
+    ok, msg = grad_close(pose.cpu().numpy(), ref["pose"])
+    assert ok, msg
+
+
+def test_autograd_function_matches_fused_loss(ras):
+    from paper_2510_26358_amd.autograd import render, render_loss
+    sc = random_scene(321, n=250, sh_degree=1, n_views=1, width=48, height=40, f=50.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    tg = LossTargets.from_scene(sc, views, w_l1=1.0, lambda_lidar=0.0)
+    leaves = [t.clone().requires_grad_(True) for t in p.tensors()]
+    pose = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    rgb, depth, alpha = render(*leaves, pose, ras, cams, views, sc.sh_degree)
+    gt = tg.gt_rgb
+    loss = (rgb - gt).abs().sum() / rgb.numel()
+    loss.backward()
+    g1 = [t.grad.clone() for t in leaves] + [pose.grad.clone()]
+    leaves2 = [t.clone().requires_grad_(True) for t in p.tensors()]
+    pose2 = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    loss2 = render_loss(*leaves2, pose2, ras, cams, views, sc.sh_degree, tg)
+    loss2.backward()
+    assert abs(loss.item() - loss2.item()) <= 1e-5 * max(1, abs(loss.item()))
+    for a, b in zip(g1, [t.grad for t in leaves2] + [pose2.grad]):
+        assert torch.allclose(a, b, rtol=1e-4, atol=1e-7 * max(1.0, float(b.abs().max())))
+
+
+def test_empty_and_degenerate_inputs(ras):
+    sc = random_scene(331, n=50, sh_degree=0, n_views=2, width=40, height=30, f=40.0)
+    # view 0 sees no Gaussian (empty range); every Gaussian is behind view 1
+    sc.cameras[0].g_begin = sc.cameras[0].g_end = 10
+    sc.means[:, 2] = -5.0
+    res, (p, cams, views, out, buf) = run_forward(sc, ras)
+    for r in res:
+        assert np.all(r["alpha"] == 0) and np.all(r["depth"] == 0) and np.all(r["rgb"] == 0)
+    g = run_loss_backward(sc, ras)
+    for v in g["grads"].values():
+        assert np.all(v == 0)
+    assert np.all(g["pose"] == 0)
+    # no Gaussians at all
+    sc0 = random_scene(332, n=1, sh_degree=0)
+    sc0.means = sc0.means[:0]
+    sc0.log_scales, sc0.quats = sc0.log_scales[:0], sc0.quats[:0]
+    sc0.opacity_logits, sc0.sh = sc0.opacity_logits[:0], sc0.sh[:0]
+    sc0.cameras[0].g_begin = sc0.cameras[0].g_end = 0
+    res0, _ = run_forward(sc0, ras)
+    assert np.all(res0[0]["alpha"] == 0)
+
+
+def test_adam_and_pose_step_match_oracle(ras):
+    import ctypes as C
+    from paper_2510_26358_amd import _lib as L
+    rng = np.random.default_rng(341)
+    sc = random_scene(341, n=77, sh_degree=3, n_views=2)
+    p = SplatParams.from_scene(sc)
+    g = p.zeros_like()
+    for t in g.tensors():
+        t.copy_(torch.from_numpy(rng.normal(size=tuple(t.shape)).astype(np.float32)))
+    m, v = p.zeros_like(), p.zeros_like()
+    hp = L.Adam(1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4, 1e-3, 0.9, 0.999, 1e-15)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    lib = ras.lib
+    gr = L.Grads(*[t.data_ptr() for t in g.tensors()], 0, 0)
+    p0 = [t.cpu().numpy().astype(np.float64) for t in p.tensors()]
+    for it in range(3):
+        rc = lib.ags_adam_step(ras.ctx, C.byref(hp), C.byref(p.c()), C.byref(gr), C.byref(m.c()),
+                               C.byref(v.c()), C.c_void_p(step.data_ptr()), C.c_void_p(0))
+        assert rc == 0
+        step += 1
+    torch.cuda.synchronize()
+    lrs = [1e-3, 5e-3, 1e-3, 5e-2]
+    for k, (t, p_init) in enumerate(zip(p.tensors(), p0)):
+        gk = g.tensors()[k].cpu().numpy().astype(np.float64)
+        pp, mm, vv = p_init.copy(), np.zeros_like(p_init), np.zeros_like(p_init)
+        for it in range(3):
+            if k < 4:
+                pp, mm, vv = adam_update(pp, gk, mm, vv, it + 1, lrs[k])
+            else:
+                lr = np.full(pp.shape, 1.25e-4)
+                lr[0] = 2.5e-3
+                newp, mm, vv = adam_update(pp, gk, mm, vv, it + 1, 1.0)
+                pp = pp + (newp - pp) * lr
+        assert np.allclose(t.cpu().numpy(), pp, rtol=1e-5, atol=1e-7), k
+    # pose: two views, one step
+    cams = cameras_tensor(sc.cameras)
+    pg = torch.from_numpy(rng.normal(size=(2, 6)).astype(np.float32)).cuda()
+    pm, pv = torch.zeros(2, 6, device="cuda"), torch.zeros(2, 6, device="cuda")
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    rc = lib.ags_pose_step(ras.ctx, C.byref(hp), C.c_void_p(cams.data_ptr()), 2, C.c_void_p(pg.data_ptr()),
+                           C.c_void_p(pm.data_ptr()), C.c_void_p(pv.data_ptr()), C.c_void_p(step.data_ptr()), 1,
+                           C.c_void_p(0))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(step.item()) == 2
+    for b, c in enumerate(sc.cameras):
+        R2, t2, _, _ = pose_update(c.R, c.t, pg[b].cpu().numpy().astype(np.float64), np.zeros(6), np.zeros(6), 1, 1e-3)
+        got = cams[b].cpu().numpy()
+        assert np.allclose(got[:9].reshape(3, 3), R2, atol=2e-6)
+        assert np.allclose(got[9:12], t2, atol=2e-6 * max(1, np.abs(t2).max()))
