@@ -159,9 +159,13 @@ def main():
     ap.add_argument("--tile", default="auto", help="8, 16, 32 or auto (autotuner)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--ppt", type=int, default=1)
+    ap.add_argument("--batch-bwd", type=int, default=0)
+    ap.add_argument("--ppt-bwd", type=int, default=0)
     ap.add_argument("--no-loop", action="store_true", help="skip the per-view loop comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -171,12 +175,21 @@ def main():
     import torch
     from paper_2510_26358_amd.rasterizer import Rasterizer
 
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {4 * n} bytes read and written")
+        del src, dst
     t0 = time.perf_counter()
     sc = make_workload(args.workload)
     log(f"[bench] workload {sc.name}: N={sc.n}, views={len(sc.cameras)}, P={sc.n_pixels} "
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     auto = args.tile == "auto"
-    ras = Rasterizer(0, tile=16 if auto else int(args.tile), batch=args.batch, px_per_thread=args.ppt)
+    ras = Rasterizer(0, tile=16 if auto else int(args.tile), batch=args.batch, px_per_thread=args.ppt,
+                     batch_bwd=args.batch_bwd, px_per_thread_bwd=args.ppt_bwd)
     p, cams, views, tg = setup(sc, ras)
     tuned = None
     if auto:
@@ -184,6 +197,8 @@ def main():
         tuned = tune(ras, p, cams, views, tg, use_cache=False, log=log)
         log(f"[bench] autotuner picked tile/batch/ppt = {tuned['best']}")
     tile, batch, ppt = ras.cfg.tile, ras.cfg.batch, ras.cfg.px_per_thread
+    batch_b = ras.cfg.batch_bwd or batch
+    ppt_b = ras.cfg.px_per_thread_bwd or ppt
     cap, K, V = calibrate(ras, p, cams, views)
     log(f"[bench] V={V} visible pairs, K={K} intersections, capacity {cap}")
     buf = ras.buffers(views, p.n, p.sh_degree, cap)
@@ -261,7 +276,8 @@ def main():
         "config": {"workload": sc.name, "n_gaussians": sc.n, "views": views.n_views,
                    "resolution": [[w, h] for w, h in zip(views.widths, views.heights)],
                    "pixels": P, "sh_degree": sc.sh_degree, "loss": "L1 + LiDAR KL",
-                   "tile": tile, "lds_batch": batch, "px_per_thread": ppt,
+                   "tile": tile, "lds_batch": batch, "px_per_thread": ppt, "lds_batch_bwd": batch_b,
+                   "px_per_thread_bwd": ppt_b,
                    "autotuned": None if tuned is None else tuned["ms"],
                    "visible_pairs": V, "intersections": K},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,

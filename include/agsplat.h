@@ -62,13 +62,18 @@ enum {
  * skipped), alpha_max 0.99 (alpha clamp), t_min 1e-4 (compositing stops before the
  * transmittance would drop below it; that Gaussian is excluded), blur 0.3 px^2 added to
  * the diagonal of Sigma', z_near 0.2 (Gaussians closer are culled), fov_clamp 1.3 (x/z
- * and y/z clamped to +-1.3 half-FOV tangents inside J only), bg = 0, tile 16. */
+ * and y/z clamped to +-1.3 half-FOV tangents inside J only), bg = 0, tile 16, batch 256,
+ * one pixel per thread, backward shape = forward shape.  The supported (tile, batch,
+ * pixels per thread) launch shapes are (8,64,1) (8,128,1) (16,128,1) (16,256,1) (16,128,2)
+ * (16,256,2) (16,64,4) (32,256,4) (32,512,2); others give AGS_ERR_NOT_SUPPORTED at launch. */
 typedef struct ags_config {
     float alpha_min, alpha_max, t_min, blur, z_near, fov_clamp;
     float bg[3];
     int tile;          /* tile edge in pixels: 8, 16 or 32 (binning and raster) */
-    int batch;         /* Gaussians staged in LDS per batch: 64, 128, 256 or 512 */
-    int px_per_thread; /* raster pixels per thread: 1, 2 or 4 */
+    int batch;         /* forward: Gaussians staged in LDS per batch: 64, 128, 256 or 512 */
+    int px_per_thread; /* forward: pixels per thread: 1, 2 or 4 */
+    int batch_bwd;     /* backward launch shape; 0 = same as the forward */
+    int px_per_thread_bwd;
 } ags_config;
 
 /* Camera b, device array element (64 bytes).  World->camera rotation R (row-major) and

@@ -31,7 +31,7 @@ class Config(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
                 ("blur", C.c_float), ("z_near", C.c_float), ("fov_clamp", C.c_float),
                 ("bg", C.c_float * 3), ("tile", C.c_int), ("batch", C.c_int),
-                ("px_per_thread", C.c_int)]
+                ("px_per_thread", C.c_int), ("batch_bwd", C.c_int), ("px_per_thread_bwd", C.c_int)]
 
 
 class Views(C.Structure):

@@ -73,6 +73,12 @@ int check_config(const ags_config* c) {
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return AGS_ERR_INVALID_ARG;
     if (c->batch != 64 && c->batch != 128 && c->batch != 256 && c->batch != 512) return AGS_ERR_INVALID_ARG;
     if (c->px_per_thread != 1 && c->px_per_thread != 2 && c->px_per_thread != 4) return AGS_ERR_INVALID_ARG;
+    if (c->batch_bwd != 0 && c->batch_bwd != 64 && c->batch_bwd != 128 && c->batch_bwd != 256 &&
+        c->batch_bwd != 512)
+        return AGS_ERR_INVALID_ARG;
+    if (c->px_per_thread_bwd != 0 && c->px_per_thread_bwd != 1 && c->px_per_thread_bwd != 2 &&
+        c->px_per_thread_bwd != 4)
+        return AGS_ERR_INVALID_ARG;
     if (!(c->alpha_min > 0.f && c->alpha_min < c->alpha_max && c->alpha_max < 1.f)) return AGS_ERR_INVALID_ARG;
     if (!(c->t_min > 0.f && c->t_min < 1.f) || !(c->blur >= 0.f) || !(c->z_near > 0.f) ||
         !(c->fov_clamp > 0.f))
@@ -299,6 +305,8 @@ void ags_config_default(ags_config* c) {
     c->tile = 16;
     c->batch = 256;
     c->px_per_thread = 1;
+    c->batch_bwd = 0;
+    c->px_per_thread_bwd = 0;
 }
 
 int ags_ctx_create(ags_ctx** out, int device, const ags_config* cfg) {
@@ -534,7 +542,9 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     }
     {
         Scope sc(ctx, ST_RASTER_BWD, s);
-        rc = launch_raster_bwd(ra, ctx->cfg.tile, ctx->cfg.batch, ctx->cfg.px_per_thread, s);
+        const int mb = ctx->cfg.batch_bwd ? ctx->cfg.batch_bwd : ctx->cfg.batch;
+        const int pb = ctx->cfg.px_per_thread_bwd ? ctx->cfg.px_per_thread_bwd : ctx->cfg.px_per_thread;
+        rc = launch_raster_bwd(ra, ctx->cfg.tile, mb, pb, s);
         if (rc) return rc;
     }
     {

@@ -382,7 +382,7 @@ struct ProjectBwdArgs {
     const float *means, *log_scales, *quats, *logits, *sh;
     const ags_camera* cams;
     const uint32_t* pair_count;
-    const float* grad2d;
+    float* grad2d;  // read; slots 6..8 overwritten with the clamp-masked colour adjoint
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
     float* pose_partials;  // [project_bwd_blocks(n)][n_views][6]
     int accumulate;

@@ -61,7 +61,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
-    bool sh_written = a.accumulate != 0;
 
     for (int b = 0; b < vt.n_views; ++b) {
         const bool in_range = active && i >= vt.g_begin[b] && i < vt.g_end[b];
@@ -167,7 +166,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             // One pass over the coefficients per channel gives the raw colour and its
             // gradient in the direction, G_c = sum_k f_kc grad Y_k; then g_dir = sum_c gcol_c G_c.
             const float* shp = opaque_ptr(a.sh);
-            float* gshp = opaque_ptr(a.g_sh);
             float raw[3], G[3][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -183,17 +181,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             float gcol[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) gcol[c] = raw[c] >= 0.f ? grgb[c] : 0.f;
-            // SH-coefficient adjoints go to memory per visible view: a plain store for the
-            // first one (overwrite mode), a return-less atomic add for later views.
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float* dst = sh_row(gshp, n, k * 3 + c) + (uint32_t)i;
-                    if (sh_written) atomicAdd(dst, Y[k] * gcol[c]);
-                    else *dst = Y[k] * gcol[c];
-                }
-            sh_written = true;
+            // the clamp-masked colour adjoint, for the SH-coefficient pass
+            float* g2w = opaque_ptr(a.grad2d) + q * kGrad2dStride;
+            g2w[6] = gcol[0];
+            g2w[7] = gcol[1];
+            g2w[8] = gcol[2];
             float gdir[3] = {0.f, 0.f, 0.f};
             if (DEG > 0) {
 #pragma unroll
@@ -285,13 +277,53 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         }
         for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = gq[c];
         a.g_logits[i] = glogit;
-        if (!sh_written) {
+    }
+}
+
+// SH-coefficient adjoint: dL/df_kc = sum over visible views of Y_k(d_b) gcol_b,c, with
+// gcol the clamp-masked colour adjoint the geometry pass left in the pair's slots 6..8.
+// One thread per Gaussian; the K x 3 sums stay in registers and are written once.
+template <int DEG>
+__global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int n = a.n;
+    const ViewTable& vt = a.vt;
+    const float mx = a.means[i], my = a.means[n + i], mz = a.means[2 * n + i];
+    float acc[K][3];
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.f;
+    for (int b = 0; b < vt.n_views; ++b) {
+        if (i < vt.g_begin[b] || i >= vt.g_end[b]) continue;
+        const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
+        if (a.pair_count[q] == 0u) continue;
+        const float* g2 = a.grad2d + q * kGrad2dStride;
+        const float gc0 = g2[6], gc1 = g2[7], gc2 = g2[8];
+        const ags_camera cam = a.cams[b];
+        const float* R = cam.R;
+        const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
+        const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
+        const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
+        float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+        const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= il; dy *= il; dz *= il;
+        float Y[16];
+        sh_basis(DEG, dx, dy, dz, Y);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sh_row(a.g_sh, n, k * 3 + c)[(uint32_t)i] = 0.f;
+        for (int k = 0; k < K; ++k) {
+            acc[k][0] += Y[k] * gc0;
+            acc[k][1] += Y[k] * gc1;
+            acc[k][2] += Y[k] * gc2;
         }
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float* dst = sh_row(a.g_sh, n, k * 3 + c) + (uint32_t)i;
+            *dst = a.accumulate ? *dst + acc[k][c] : acc[k][c];
+        }
 }
 
 // Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component).
@@ -315,6 +347,14 @@ int project_bwd_blocks(int n) { return n > 0 ? (n + 255) / 256 : 0; }
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
     const int nb = project_bwd_blocks(a.n);
     if (nb > 0) launch_project_bwd_main(a, s);
+    if (nb > 0) {
+        switch (a.sh_degree) {
+            case 0: hipLaunchKernelGGL(sh_bwd_kernel<0>, dim3(nb), dim3(256), 0, s, a); break;
+            case 1: hipLaunchKernelGGL(sh_bwd_kernel<1>, dim3(nb), dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(sh_bwd_kernel<2>, dim3(nb), dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL(sh_bwd_kernel<3>, dim3(nb), dim3(256), 0, s, a); break;
+        }
+    }
     if (nb > 0)
         hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, nb,
                            a.vt.n_views, a.g_pose, a.accumulate);

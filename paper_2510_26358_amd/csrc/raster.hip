@@ -43,33 +43,102 @@ __device__ __forceinline__ TileCoord tile_coord(const ViewTable& vt, int tile) {
     return c;
 }
 
-// Copy record q into LDS, replacing the footprint extent (not needed by compositing) with
-// ln(alpha_min / o): a Gaussian whose power is below it cannot reach alpha_min, so the exp
-// is skipped.  Forward and backward stage the same value, so their decisions agree.
-__device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, float4* dst) {
-    const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
-    const float4 r0 = r[0], r2 = r[2];
-    float4 r1 = r[1];
-    r1.w = __logf(amin / r1.y);
-    dst[0] = r0;
-    dst[1] = r1;
-    dst[2] = r2;
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs on XCD g % 8).
+// Give each XCD one contiguous band of tiles instead of every 8th tile, so the Gaussians
+// (records and adjoint lines) a workgroup touches stay in its own XCD's L2.  A bijection
+// on [0, n_tiles).
+__device__ __forceinline__ int xcd_tile(int g, int n_tiles) {
+    const int q = n_tiles >> 3, r = n_tiles & 7, x = g & 7;
+    return x * q + (x < r ? x : r) + (g >> 3);
 }
 
-// Pixel k of thread t: PPT vertically adjacent pixels per thread, so a 64-lane wave covers
-// a compact 16 x 4 * PPT (T = 16) block.
+// Each wave owns a rectangular block of the tile: 8 columns x 8 PPT rows when the tile has
+// enough waves for its 8-wide column strips, else the full tile width.  Lane l covers
+// column l % BW and PPT vertically adjacent rows.  The per-record wave mask below lets a
+// whole wave skip Gaussians whose footprint box misses its block.
 template <int T, int PPT>
+struct WaveGrid {
+    static constexpr int NT = T * T / PPT;
+    static constexpr int NW = NT / 64;
+    static constexpr int BW = (NW >= T / 8) ? 8 : T;
+    static constexpr int COLS = T / BW;
+    static constexpr int BH = 64 * PPT / BW;
+    static_assert(COLS * (T / BH) == NW, "wave blocks must tile the tile");
+};
+
+// BLOCKS = false: row strips (thread t covers column t % T and PPT rows), used by the
+// forward, where full-width rows keep the output writes coalesced.  BLOCKS = true: the wave
+// blocks above, used by the backward together with the wave mask.
+template <int T, int PPT, bool BLOCKS>
 __device__ __forceinline__ void pixel_of(int t, int k, int& x, int& y) {
-    x = t % T;
-    y = (t / T) * PPT + k;
+    if (BLOCKS) {
+        using G = WaveGrid<T, PPT>;
+        const int w = t >> 6, l = t & 63;
+        x = (w % G::COLS) * G::BW + l % G::BW;
+        y = (w / G::COLS) * G::BH + (l / G::BW) * PPT + k;
+    } else {
+        x = t % T;
+        y = (t / T) * PPT + k;
+    }
+}
+
+// Bit w set when the record's pixel footprint box (the binning rectangle, clamped to the
+// image) intersects wave w's block of the tile at (px0, py0).
+template <int T, int PPT>
+__device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float ey, int W, int H, int px0,
+                                              int py0) {
+    using G = WaveGrid<T, PPT>;
+    const float fx0 = floorf(__fsub_rn(__fsub_rn(u, ex), 0.5f));
+    const float fx1 = ceilf(__fsub_rn(__fadd_rn(u, ex), 0.5f));
+    const float fy0 = floorf(__fsub_rn(__fsub_rn(v, ey), 0.5f));
+    const float fy1 = ceilf(__fsub_rn(__fadd_rn(v, ey), 0.5f));
+    // relative to the tile, clamped to [-1, T]
+    const int x0 = (int)fminf(fmaxf(fx0 - (float)px0, -1.f), (float)T);
+    const int x1 = (int)fminf(fmaxf(fx1 - (float)px0, -1.f), (float)T);
+    const int y0 = (int)fminf(fmaxf(fy0 - (float)py0, -1.f), (float)T);
+    const int y1 = (int)fminf(fmaxf(fy1 - (float)py0, -1.f), (float)T);
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < G::NW; ++w) {
+        const int bx0 = (w % G::COLS) * G::BW, by0 = (w / G::COLS) * G::BH;
+        if (x0 <= bx0 + G::BW - 1 && x1 >= bx0 && y0 <= by0 + G::BH - 1 && y1 >= by0) m |= 1u << w;
+    }
+    (void)W;
+    (void)H;
+    return m;
+}
+
+// Copy record q into LDS in the form the per-pixel loops use: the conic (a, b, c) becomes
+// (-a/2, -b, -c/2) so power = dx (A' dx + B' dy) + C' dy^2 costs five operations; the
+// footprint extent is replaced by ln(alpha_min / o) (a Gaussian whose power is below it
+// cannot reach alpha_min, so its exp is skipped) and by the mask of wave blocks its
+// footprint box touches.  Forward and backward stage identical values, so their decisions
+// agree; every skipped (pixel, Gaussian) pair has alpha < alpha_min, so the result is the
+// same as evaluating it.
+// LDS layout: [0] = (u, v, -a/2, -b), [1] = (-c/2, o, z, ln(alpha_min/o)),
+//             [2] = (wave mask bits, r, g, b).
+template <int T, int PPT, bool MASK>
+__device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
+                                             int px0, int py0, float4* dst) {
+    const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    dst[0] = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
+    dst[1] = make_float4(-0.5f * r1.x, r1.y, r1.z, __logf(amin / r1.y));
+    const uint32_t m = MASK ? wave_mask<T, PPT>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : 0xFFFFFFFFu;
+    dst[2] = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
+}
+
+__device__ __forceinline__ float power_of(const float4& r0, const float4& r1, float dx, float dy) {
+    return dx * (r0.z * dx + r0.w * dy) + r1.x * dy * dy;
 }
 
 template <int T, int PPT, int M>
 __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ float4 srec[M][3];
-    const TileCoord tc = tile_coord(a.vt, blockIdx.x);
-    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord(a.vt, tile);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const int tid = threadIdx.x;
 
     float cx[PPT], cy[PPT], Tr[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], A[PPT];
@@ -78,7 +147,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         int lx, ly;
-        pixel_of<T, PPT>(tid, k, lx, ly);
+        pixel_of<T, PPT, false>(tid, k, lx, ly);
         const int px = tc.px0 + lx, py = tc.py0 + ly;
         inside[k] = px < tc.W && py < tc.H;
         done[k] = !inside[k];
@@ -100,7 +169,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
             const uint32_t e = bs + l;
             if (e < end) {
                 const uint32_t q = a.tile_pairs[e];
-                stage_record(a.records, q, amin, srec[l]);
+                stage_record<T, PPT, false>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
             }
         }
         __syncthreads();
@@ -110,29 +179,29 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                 bool live = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) live |= !done[k];
-                if (!live) break;
+                if (__ballot(live) == 0ull) break;  // wave-uniform: every pixel has stopped
                 const float4 r0 = srec[j][0], r1 = srec[j][1], r2 = srec[j][2];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (done[k]) continue;
+                    // one predicate, one branch: the exp is cheap next to divergent control
                     const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                    const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
-                    if (power > 0.f || power < r1.w) continue;  // r1.w = ln(alpha_min / o)
+                    const float power = power_of(r0, r1, dx, dy);
                     const float alpha = fminf(amax, r1.y * __expf(power));
-                    if (alpha < amin) continue;
-                    const float tn = Tr[k] * (1.f - alpha);
-                    if (tn < tmin) {
-                        done[k] = true;
-                        continue;
+                    // r1.w = ln(alpha_min / o): below it alpha cannot reach alpha_min
+                    const bool keep = !done[k] && power <= 0.f && power >= r1.w && alpha >= amin;
+                    if (keep) {
+                        const float tn = Tr[k] * (1.f - alpha);
+                        const bool stop = tn < tmin;
+                        const float w = stop ? 0.f : alpha * Tr[k];
+                        C0[k] += w * r2.y;
+                        C1[k] += w * r2.z;
+                        C2[k] += w * r2.w;
+                        D[k] += w * r1.z;
+                        A[k] += w;
+                        Tr[k] = stop ? Tr[k] : tn;
+                        last[k] = stop ? last[k] : bs - start + j + 1;
+                        done[k] = stop;
                     }
-                    const float w = alpha * Tr[k];
-                    C0[k] += w * r2.y;
-                    C1[k] += w * r2.z;
-                    C2[k] += w * r2.w;
-                    D[k] += w * r1.z;
-                    A[k] += w;
-                    Tr[k] = tn;
-                    last[k] = bs - start + j + 1;
                 }
             }
         }
@@ -143,7 +212,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     for (int k = 0; k < PPT; ++k) {
         if (!inside[k]) continue;
         int lx, ly;
-        pixel_of<T, PPT>(tid, k, lx, ly);
+        pixel_of<T, PPT, false>(tid, k, lx, ly);
         const long long p = (long long)(tc.py0 + ly) * tc.W + (tc.px0 + lx);
         const long long gp = tc.pix0 + p;
         float* rgb = a.rgb + 3 * tc.pix0;
@@ -164,10 +233,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     __shared__ uint32_t sq[M];
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
-    const TileCoord tc = tile_coord(a.vt, blockIdx.x);
-    const uint32_t start = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord(a.vt, tile);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const int tid = threadIdx.x;
     const int lane = __lane_id();
+    const int wave = tid >> 6;
     const float amin = a.st.alpha_min;
 
     float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], bgt[PPT];
@@ -179,7 +250,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         int lx, ly;
-        pixel_of<T, PPT>(tid, k, lx, ly);
+        pixel_of<T, PPT, true>(tid, k, lx, ly);
         const int px = tc.px0 + lx, py = tc.py0 + ly;
         cx[k] = (float)px + 0.5f;
         cy[k] = (float)py + 0.5f;
@@ -233,7 +304,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     if (a.loss_mode && tid == 0) {
         float s = 0.f;
         for (int w = 0; w < NT / 64; ++w) s += sred[w];
-        a.loss_partials[blockIdx.x] = s;
+        a.loss_partials[tile] = s;
     }
     __syncthreads();
     const uint32_t maxlast = smax;
@@ -248,27 +319,27 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         const int lo = hi - M > 0 ? hi - M : 0;
         for (int l = tid; l < hi - lo; l += NT) {
             const uint32_t q = a.tile_pairs[start + lo + l];
-            stage_record(a.records, q, amin, srec[l]);
+            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
             sq[l] = q;
         }
         __syncthreads();
         for (int j = hi - 1; j >= lo; --j) {
             if ((uint32_t)j >= wlast) continue;  // wave-uniform
             const float4 r0 = srec[j - lo][0], r1 = srec[j - lo][1], r2 = srec[j - lo][2];
+            if (!((__float_as_uint(r2.x) >> wave) & 1u)) continue;  // wave-uniform
             float g[16];
 #pragma unroll
             for (int s = 0; s < 16; ++s) g[s] = 0.f;
             bool contrib = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if ((uint32_t)j >= last[k]) continue;
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
-                if (power > 0.f || power < r1.w) continue;
+                const float power = power_of(r0, r1, dx, dy);
                 const float G = __expf(power);
                 const float araw = r1.y * G;
                 const float alpha = fminf(amax, araw);
-                if (alpha < amin) continue;
+                const bool keep = (uint32_t)j < last[k] && power <= 0.f && power >= r1.w && alpha >= amin;
+                if (!keep) continue;
                 contrib = true;
                 const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
                 const float Tk = Tr[k] * rom;
@@ -288,13 +359,15 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 SA[k] += w;
                 Tr[k] = Tk;
                 if (araw <= amax) {
+                    // power = A' dx^2 + B' dx dy + C' dy^2 with (A', B', C') = (-a/2, -b, -c/2)
                     const float gp = ga * alpha;  // dL/dpower
                     g[5] += ga * G;               // dL/do
-                    g[0] += -gp * (r0.z * dx + r0.w * dy);
-                    g[1] += -gp * (r0.w * dx + r1.x * dy);
-                    g[2] += -0.5f * gp * dx * dx;
-                    g[3] += -gp * dx * dy;
-                    g[4] += -0.5f * gp * dy * dy;
+                    g[0] += gp * (2.f * r0.z * dx + r0.w * dy);
+                    g[1] += gp * (r0.w * dx + 2.f * r1.x * dy);
+                    const float hgx = -0.5f * gp * dx;
+                    g[2] += hgx * dx;                 // dpower/da = -dx^2 / 2
+                    g[3] += 2.f * hgx * dy;           // dpower/db = -dx dy
+                    g[4] += -0.5f * gp * dy * dy;     // dpower/dc = -dy^2 / 2
                 }
             }
             if (__ballot(contrib) == 0ull) continue;

@@ -191,7 +191,7 @@ class Rasterizer:
     """A library context plus settings.  One instance per stream at a time."""
 
     def __init__(self, device: int = 0, tile: int = 16, batch: int = 256, px_per_thread: int = 1,
-                 **settings):
+                 batch_bwd: int = 0, px_per_thread_bwd: int = 0, **settings):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("libagsplat needs a ROCm GPU; none is visible")
@@ -199,6 +199,7 @@ class Rasterizer:
         cfg = L.Config()
         self.lib.ags_config_default(C.byref(cfg))
         cfg.tile, cfg.batch, cfg.px_per_thread = tile, batch, px_per_thread
+        cfg.batch_bwd, cfg.px_per_thread_bwd = batch_bwd, px_per_thread_bwd
         for k, v in settings.items():
             if k == "bg":
                 cfg.bg = (C.c_float * 3)(*v)
