@@ -164,6 +164,7 @@ def main():
     ap.add_argument("--no-loop", action="store_true", help="skip the per-view loop comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -206,16 +207,39 @@ def main():
     grads = p.zeros_like()
     pose = torch.zeros(views.n_views, 6, device="cuda")
     loss = torch.zeros(1, device="cuda")
+    refiner = None
+    if args.workload == "refine":
+        from paper_2510_26358_amd.refine import Refiner
+        refiner = Refiner(ras, p, cams, views, tg, capacity=cap)
 
-    def step():
-        ras.forward_into(p, cams, views, buf, out)
-        ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+        def step():
+            refiner.step()
+    else:
+        def step():
+            ras.forward_into(p, cams, views, buf, out)
+            ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
 
-    t_b = time_steps(step, args.steps, args.warmup)
+    t_eager = None
+    if refiner is None:
+        t_eager = time_steps(step, args.steps, args.warmup)
+        log(f"[bench] batched (eager launches): {t_eager * 1e3:.3f} ms/step")
+    timed = step
+    if not args.no_graph:
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        timed = graph.replay
+    t_b = time_steps(timed, args.steps, args.warmup)
     P = views.n_pixels
     mpx = P / t_b / 1e6
-    log(f"[bench] batched: {t_b * 1e3:.3f} ms/step, {mpx:.1f} Mpixel/s, loss {loss.item():.5f}")
-    assert buf.counters()[2] == 0, "capacity overflow during timing"
+    lval = (refiner.loss if refiner is not None else loss).item()
+    log(f"[bench] batched{' (graph)' if not args.no_graph else ''}: {t_b * 1e3:.3f} ms/step, {mpx:.1f} Mpixel/s, "
+        f"loss {lval:.5f}")
+    over_buf = refiner.buf if refiner is not None else buf
+    assert over_buf.counters()[2] == 0, "capacity overflow during timing"
 
     # per-stage times over a second timed pass with events enabled
     roof, info = None, None
@@ -229,12 +253,12 @@ def main():
         ras.profile(False)
         stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1] > 0}
         log(f"[bench] per-stage avg ms: {stage_ms}")
-        roof, info = dominant_roofline(prof, views, buf, buf.sizes, args.steps, p.n,
+        roof, info = dominant_roofline(prof, views, over_buf, over_buf.sizes, args.steps, p.n,
                                        (p.sh_degree + 1) ** 2)
         info["stage_ms"] = stage_ms
 
     loop = None
-    if not args.no_loop and views.n_views > 1:
+    if not args.no_loop and views.n_views > 1 and refiner is None:
         from paper_2510_26358_amd.rasterizer import LossTargets
         per = []
         for b in range(views.n_views):
@@ -258,7 +282,8 @@ def main():
 
         t_l = time_steps(loop_step, args.steps, args.warmup)
         loop = {"value": round(P / t_l / 1e6, 2), "ms_per_step": round(t_l * 1e3, 4),
-                "speedup_batched": round(t_l / t_b, 3)}
+                "speedup_batched": round(t_l / t_b, 3),
+                "speedup_batched_eager": round(t_l / t_eager, 3) if t_eager else None}
         log(f"[bench] per-view loop: {t_l * 1e3:.3f} ms/step, {P / t_l / 1e6:.1f} Mpixel/s "
             f"(batched speedup {t_l / t_b:.2f}x)")
 
@@ -272,6 +297,8 @@ def main():
         "metric": METRIC, "value": round(mpx, 2), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "timing": "HIP graph replay" if not args.no_graph else "eager launches",
+        "ms_per_step_eager": round(t_eager * 1e3, 4) if t_eager else None,
         "data": "synthetic",
         "config": {"workload": sc.name, "n_gaussians": sc.n, "views": views.n_views,
                    "resolution": [[w, h] for w, h in zip(views.widths, views.heights)],

@@ -1,0 +1,89 @@
+"""Joint map + pose refinement loop with a HIP-graph-captured step.
+
+One step = batched forward render, fused L1 + LiDAR-KL backward (Sec. III-C), Adam on the
+Gaussian parameters and Adam on each camera's se(3) increment followed by the left
+retraction W_b <- Exp(delta_b) W_b (the paper refines splats and poses jointly through the
+multimodal loss, Sec. III-C).  Every buffer is allocated once; the library calls only
+enqueue kernels (no allocation, no host synchronisation, no memset nodes), so the whole
+step is captured once and replayed.  The step counter lives in device memory.
+
+The intersection count is data dependent: the capacity is fixed when capturing (with
+headroom), and `check_capacity()` (one host read) reports an overflow so the caller can
+re-capture with a larger capacity.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+from .rasterizer import LossTargets, Rasterizer, SplatParams, ViewSpec
+
+DEFAULT_LR = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity": 5e-2, "sh0": 2.5e-3,
+              "shrest": 1.25e-4, "pose": 1e-3}
+
+
+class Refiner:
+    def __init__(self, ras: Rasterizer, params: SplatParams, cams: torch.Tensor, views: ViewSpec,
+                 targets: LossTargets, lr: dict | None = None, capacity: int | None = None,
+                 headroom: float = 1.3, betas=(0.9, 0.999), eps=1e-15):
+        self.ras, self.p, self.cams, self.views, self.targets = ras, params, cams, views, targets
+        lr = {**DEFAULT_LR, **(lr or {})}
+        self.hp = L.Adam(lr["means"], lr["log_scales"], lr["quats"], lr["opacity"], lr["sh0"], lr["shrest"],
+                         lr["pose"], betas[0], betas[1], eps)
+        dev = params.means.device
+        if capacity is None:
+            _, b = ras.render(params, cams, views)
+            capacity = int(b.counters()[0] * headroom) + 4096
+            del b
+        self.buf = ras.buffers(views, params.n, params.sh_degree, capacity)
+        self.out = ras.outputs(views)
+        self.grads = params.zeros_like()
+        self.m = params.zeros_like()
+        self.v = params.zeros_like()
+        B = views.n_views
+        self.pose_grad = torch.zeros(B, 6, device=dev)
+        self.pose_m = torch.zeros(B, 6, device=dev)
+        self.pose_v = torch.zeros(B, 6, device=dev)
+        self.step_no = torch.ones(1, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros(1, device=dev)
+        self.graph = None
+        self._keep = None
+
+    # ---------------------------------------------------------------- one step
+    def step(self):
+        """Enqueue one optimisation step on the current stream (no host sync)."""
+        ras, lib = self.ras, self.ras.lib
+        ras.forward_into(self.p, self.cams, self.views, self.buf, self.out)
+        ras.backward_into(self.p, self.cams, self.views, self.buf, self.out, self.grads, self.pose_grad,
+                          loss=self.targets, loss_out=self.loss)
+        gr = L.Grads(*[t.data_ptr() for t in self.grads.tensors()], self.pose_grad.data_ptr(), 0)
+        pc, mc, vc = self.p.c(), self.m.c(), self.v.c()
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        L.check(lib.ags_adam_step(ras.ctx, C.byref(self.hp), C.byref(pc), C.byref(gr), C.byref(mc), C.byref(vc),
+                                  C.c_void_p(self.step_no.data_ptr()), stream), "ags_adam_step", ras.ctx)
+        L.check(lib.ags_pose_step(ras.ctx, C.byref(self.hp), C.c_void_p(self.cams.data_ptr()), self.views.n_views,
+                                  C.c_void_p(self.pose_grad.data_ptr()), C.c_void_p(self.pose_m.data_ptr()),
+                                  C.c_void_p(self.pose_v.data_ptr()), C.c_void_p(self.step_no.data_ptr()), 1,
+                                  stream), "ags_pose_step", ras.ctx)
+
+    def capture(self, warmup: int = 0):
+        """Capture one step into a HIP graph (after `warmup` eager steps)."""
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self, n: int = 1):
+        for _ in range(n):
+            self.graph.replay()
+
+    def check_capacity(self) -> bool:
+        """True when the last forward fitted its intersection capacity (synchronises)."""
+        k, v, over, keff = self.buf.counters()
+        return not over

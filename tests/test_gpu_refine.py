@@ -1,0 +1,126 @@
+"""Graph-captured refinement step (forward, fused-loss backward, Adam, se(3) pose update) and
+the pose-gradient check of the refinement workload: on a 4k-Gaussian crop of the 2M-Gaussian
+map, the HIP pose gradient against FP64 central finite differences (step 1e-6) of the
+oracle, every 10 steps of the loop."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.render import frozen_objective, loss_and_grads
+from oracle.settings import RenderSettings
+from paper_2510_26358_amd import scenes
+from paper_2510_26358_amd.rasterizer import (LossTargets, Rasterizer, SplatParams, ViewSpec,
+                                             cameras_tensor)
+from paper_2510_26358_amd.refine import Refiner
+from paper_2510_26358_amd.scenes import Camera, Scene
+from tests.oracle_helpers import random_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ras():
+    return Rasterizer(0)
+
+
+def _refiner(ras, sc, capacity=None):
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    tg = LossTargets.from_scene(sc, views, lambda_lidar=0.5)
+    return Refiner(ras, p, cams, views, tg, capacity=capacity)
+
+
+def test_graph_replay_matches_eager_steps(ras):
+    sc = random_scene(401, n=3000, sh_degree=3, n_views=2, width=96, height=72, f=80.0)
+    a = _refiner(ras, sc)
+    b = _refiner(ras, sc, capacity=a.buf.capacity)
+    b.capture()
+    losses = []
+    for it in range(4):
+        a.step()
+        b.replay()
+        # unrelated eager work and a synchronisation between replays
+        torch.ones(1000, device="cuda").sum().item()
+        torch.cuda.synchronize()
+        assert a.check_capacity() and b.check_capacity()
+        for x, y in zip(a.p.tensors(), b.p.tensors()):
+            assert torch.allclose(x, y, rtol=1e-5, atol=1e-6), it
+        assert torch.allclose(a.cams, b.cams, rtol=1e-5, atol=1e-6)
+        assert int(a.step_no.item()) == int(b.step_no.item()) == it + 2
+        losses.append(a.loss.item())
+        assert abs(a.loss.item() - b.loss.item()) <= 1e-4 * abs(a.loss.item())
+    assert losses[-1] < losses[0]
+
+
+def _crop(sc, cams_np, params_aos, rng, n_keep=4096, win=128):
+    """4096 Gaussians nearest (in 3D, in front of the camera) to the ray through the centre
+    of a seeded 128x128 window of view 0, seen through a window camera whose principal
+    point is shifted to the window."""
+    cam0 = sc.cameras[0]
+    R = cams_np[0, :9].reshape(3, 3).astype(np.float64)
+    t = cams_np[0, 9:12].astype(np.float64)
+    x0 = int(rng.integers(0, cam0.width - win))
+    y0 = int(rng.integers(0, cam0.height - win))
+    ray = np.array([(x0 + win / 2 - cam0.cx) / cam0.fx, (y0 + win / 2 - cam0.cy) / cam0.fy, 1.0])
+    ray /= np.linalg.norm(ray)
+    means, ls, q, lo, sh = params_aos
+    xc = means.astype(np.float64) @ R.T + t
+    along = xc @ ray
+    dist = np.linalg.norm(xc - along[:, None] * ray[None, :], axis=1)
+    dist[along < 0.5] = np.inf
+    keep = np.sort(np.argsort(dist)[:n_keep])
+    cam = Camera(R.astype(np.float32), t.astype(np.float32), cam0.fx, cam0.fy, cam0.cx - x0, cam0.cy - y0,
+                 win, win, 0, len(keep))
+    gt = sc.gt_rgb[0][:, y0:y0 + win, x0:x0 + win].copy()
+    lid = sc.lidar[0]
+    px, py = lid["pix"] % cam0.width, lid["pix"] // cam0.width
+    inside = (px >= x0) & (px < x0 + win) & (py >= y0) & (py < y0 + win)
+    lidar = {"pix": ((py[inside] - y0) * win + (px[inside] - x0)).astype(np.int32),
+             "depth": lid["depth"][inside], "sigma": lid["sigma"][inside]}
+    return Scene(means[keep].copy(), ls[keep].copy(), q[keep].copy(), lo[keep].copy(), sh[keep].copy(),
+                 sc.sh_degree, [cam], [gt], [lidar], name="crop")
+
+
+def test_refinement_pose_gradient_matches_fp64_finite_differences_every_10_steps(ras):
+    sc = scenes.refinement_scene()
+    st = scenes.perturb(sc, seed=77)
+    views = ViewSpec.from_scene(st)
+    p = SplatParams.from_scene(st)
+    cams = cameras_tensor(st.cameras)
+    tg = LossTargets.from_scene(sc, views, lambda_lidar=0.1)
+    ref = Refiner(ras, p, cams, views, tg)
+    ref.capture()
+    rng = np.random.default_rng(2515)
+    s = RenderSettings()
+    for it in range(21):
+        if it % 10 == 0:
+            torch.cuda.synchronize()
+            crop = _crop(sc, ref.cams.cpu().numpy(), ref.p.to_numpy_aos(), rng)
+            cv = ViewSpec.from_scene(crop)
+            cp = SplatParams.from_scene(crop)
+            cc = cameras_tensor(crop.cameras)
+            ct = LossTargets.from_scene(crop, cv, lambda_lidar=0.1)
+            out, buf = ras.render(cp, cc, cv)
+            gr = cp.zeros_like()
+            pose = torch.zeros(1, 6, device="cuda")
+            ras.backward_into(cp, cc, cv, buf, out, gr, pose, loss=ct)
+            torch.cuda.synchronize()
+            g_gpu = pose.cpu().numpy()[0].astype(np.float64)
+            r = loss_and_grads(crop, s, lam=0.1)
+            h = 1e-6
+            fd = np.zeros(6)
+            for j in range(6):
+                d = np.zeros((1, 6))
+                d[0, j] = h
+                fd[j] = (frozen_objective(crop, r["decisions"], s, lam=0.1, deltas=d) -
+                         frozen_objective(crop, r["decisions"], s, lam=0.1, deltas=-d)) / (2 * h)
+            err = np.abs(g_gpu - fd)
+            scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
+            print(f"step {it}: gpu {np.array2string(g_gpu, precision=5)} fd {np.array2string(fd, precision=5)} "
+                  f"max rel {np.max(err / scale):.2e}")
+            assert np.linalg.norm(g_gpu - fd) <= 1e-3 * np.linalg.norm(fd)
+            assert np.all(err <= 1e-3 * scale)
+        if it < 20:
+            ref.replay()
+    assert ref.check_capacity()
