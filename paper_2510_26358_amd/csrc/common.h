@@ -10,7 +10,9 @@ namespace ags {
 
 constexpr int kMaxViews = AGS_MAX_VIEWS;
 constexpr int kRecFloats = 12;       // projected record: u v a b c o z ex ey r g b
-constexpr int kGrad2d = 10;          // per-pair 2D adjoint: u v a b c o r g b z
+// per-pair 2D adjoint: 5 pixel moments of dL/dpower (turned into the centre and conic
+// adjoints by the projection backward), then o, r, g, b, z
+constexpr int kGrad2d = 10;
 constexpr int kGrad2dStride = 10;
 
 // Static per-batch table passed by value to kernels (kernel arguments).
@@ -251,6 +253,51 @@ __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
     }
     w1 += dpp_mov<0xB1>(w1);  // quad_perm [1, 0, 3, 2]: lane ^ 1
     w1 += dpp_mov<0x4E>(w1);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+    return w1;
+}
+
+// Sum of 10 per-lane values over the wave, same butterfly as above with the values placed
+// in slots {0..4, 8..12} so the first stage pairs real values only (the three all-zero
+// slot pairs are skipped).  On return lane L holds the total of slot (L >> 2) & 15; value
+// v lives in slot v for v < 5 and in slot v + 3 otherwise.
+__device__ __forceinline__ int slot_of_value10(int v) { return v < 5 ? v : v + 3; }
+
+__device__ __forceinline__ float wave_transpose_sum10(const float (&v)[10]) {
+    const int lane = __lane_id();
+    float w8[8];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 5]), false,
+                                                  false);
+        w8[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    w8[5] = w8[6] = w8[7] = 0.f;
+    float w4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[j]), __float_as_uint(w8[j + 4]), false,
+                                                  false);
+        w4[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float w2[2];
+    {
+        const bool hi = lane & 8;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float send = hi ? w4[j] : w4[j + 2];
+            const float keep = hi ? w4[j + 2] : w4[j];
+            w2[j] = keep + dpp_mov<0x128>(send);
+        }
+    }
+    float w1;
+    {
+        const bool hi = lane & 4;
+        const float send = hi ? w2[0] : w2[1];
+        const float keep = hi ? w2[1] : w2[0];
+        w1 = keep + dpp_mov<0x141>(send);
+    }
+    w1 += dpp_mov<0xB1>(w1);
+    w1 += dpp_mov<0x4E>(w1);
     return w1;
 }
 

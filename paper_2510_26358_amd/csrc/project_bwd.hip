@@ -71,7 +71,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         for (int k = 0; k < 16; ++k) pose[k] = 0.f;
         if (vis) {
             const float* g2 = opaque_ptr(a.grad2d) + q * kGrad2dStride;
-            const float g_u = g2[0], g_v = g2[1], g_a = g2[2], g_b = g2[3], g_c = g2[4];
+            // slots 0..4 hold pixel moments of dL/dpower: M1 = sum gp dx, M2 = sum gp dy,
+            // M3 = sum gp dx^2, M4 = sum gp dx dy, M5 = sum gp dy^2 (dx, dy = centre - pixel)
+            const float M1 = g2[0], M2 = g2[1], M3 = g2[2], M4 = g2[3], M5 = g2[4];
             const float g_o = g2[5], g_r = g2[6], g_g = g2[7], g_bl = g2[8], g_zd = g2[9];
             const ags_camera cam = opaque_ptr(a.cams)[b];
             const float* R = cam.R;
@@ -103,6 +105,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             const float cc = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + a.st.blur;
             const float idet = 1.f / (ca * cc - cb * cb);
             const float KA = cc * idet, KB = -cb * idet, KC = ca * idet;
+            // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 with conic (a, b, c) = (KA, KB, KC)
+            const float g_u = -(KA * M1 + KB * M2), g_v = -(KB * M1 + KC * M2);
+            const float g_a = -0.5f * M3, g_b = -M4, g_c = -0.5f * M5;
             // G' = -K G_K K
             const float p = g_a, r2 = 0.5f * g_b, s = g_c;
             const float k00 = KA * p + KB * r2, k01 = KA * r2 + KB * s;

@@ -17,10 +17,12 @@
 // T_k = T_{k+1} / (1 - alpha_k) and accumulating suffix sums S = sum_{j>k} w_j f_j:
 //   dL/dalpha_k = T_k (gC . c_k + gD z_k + gA)
 //                 - (gC . S^C + gD S^D + gA S^A + T_final gC . bg) / (1 - alpha_k)
-// then chains through alpha = o e^power (unless clamped) to (u, v, conic, o), and gives
-// dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian sums of a wave are reduced
-// with a transposing butterfly (17 lane exchanges instead of 60) so one atomic instruction
-// with ten active lanes updates the pair's adjoint.
+// (the bracket is kept as one running sum U), then chains through alpha = o e^power (unless
+// clamped) to the opacity and to dL/dpower, of which it keeps five pixel moments
+// (sum gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2) that the projection backward turns into
+// the centre and conic adjoints; dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian
+// sums of a wave are reduced with a transposing butterfly so one atomic instruction with
+// ten active lanes updates the pair's adjoint.
 #include "common.h"
 
 namespace ags {
@@ -109,21 +111,22 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 }
 
 // Copy record q into LDS in the form the per-pixel loops use: the conic (a, b, c) becomes
-// (-a/2, -b, -c/2) so power = dx (A' dx + B' dy) + C' dy^2 costs five operations; the
-// footprint extent is replaced by ln(alpha_min / o) (a Gaussian whose power is below it
-// cannot reach alpha_min, so its exp is skipped) and by the mask of wave blocks its
-// footprint box touches.  Forward and backward stage identical values, so their decisions
+// log2(e) (-a/2, -b, -c/2), so the exponent in base 2, p2 = dx (A' dx + B' dy) + C' dy^2,
+// costs five operations and e^power = exp2(p2) is one instruction; the footprint extent is
+// replaced by log2(alpha_min / o) (a Gaussian whose exponent is below it cannot reach
+// alpha_min) and by the mask of wave blocks its footprint box touches.  Forward and backward stage identical values, so their decisions
 // agree; every skipped (pixel, Gaussian) pair has alpha < alpha_min, so the result is the
 // same as evaluating it.
-// LDS layout: [0] = (u, v, -a/2, -b), [1] = (-c/2, o, z, ln(alpha_min/o)),
+// LDS layout: [0] = (u, v, -a/2 log2e, -b log2e), [1] = (-c/2 log2e, o, z, log2(alpha_min/o)),
 //             [2] = (wave mask bits, r, g, b).
 template <int T, int PPT, bool MASK>
 __device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
                                              int px0, int py0, float4* dst) {
     const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-    dst[0] = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-    dst[1] = make_float4(-0.5f * r1.x, r1.y, r1.z, __logf(amin / r1.y));
+    constexpr float kLog2e = 1.4426950408889634f;
+    dst[0] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    dst[1] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
     const uint32_t m = MASK ? wave_mask<T, PPT>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : 0xFFFFFFFFu;
     dst[2] = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
 }
@@ -185,10 +188,10 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                 for (int k = 0; k < PPT; ++k) {
                     // one predicate, one branch: the exp is cheap next to divergent control
                     const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                    const float power = power_of(r0, r1, dx, dy);
-                    const float alpha = fminf(amax, r1.y * __expf(power));
-                    // r1.w = ln(alpha_min / o): below it alpha cannot reach alpha_min
-                    const bool keep = !done[k] && power <= 0.f && power >= r1.w && alpha >= amin;
+                    const float p2 = power_of(r0, r1, dx, dy);
+                    const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
+                    // r1.w = log2(alpha_min / o): below it alpha cannot reach alpha_min
+                    const bool keep = !done[k] && p2 <= 0.f && p2 >= r1.w && alpha >= amin;
                     if (keep) {
                         const float tn = Tr[k] * (1.f - alpha);
                         const bool stop = tn < tmin;
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const int wave = tid >> 6;
     const float amin = a.st.alpha_min;
 
-    float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], bgt[PPT];
-    float S0[PPT], S1[PPT], S2[PPT], SD[PPT], SA[PPT];
+    // U = T_final gC.bg + sum over later contributors j of w_j (gC.c_j + gD z_j + gA)
+    float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], U[PPT];
     uint32_t last[PPT];
     float loss_part = 0.f;
     uint32_t mylast = 0;
@@ -254,11 +257,10 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         const int px = tc.px0 + lx, py = tc.py0 + ly;
         cx[k] = (float)px + 0.5f;
         cy[k] = (float)py + 0.5f;
-        S0[k] = S1[k] = S2[k] = SD[k] = SA[k] = 0.f;
         gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = 0.f;
         Tr[k] = 1.f;
         last[k] = 0;
-        bgt[k] = 0.f;
+        U[k] = 0.f;
         if (px < tc.W && py < tc.H) {
             const long long p = (long long)py * tc.W + px;
             const long long gp = tc.pix0 + p;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 if (a.d_depth) gD[k] = a.d_depth[gp];
                 if (a.d_alpha) gA[k] = a.d_alpha[gp];
             }
-            bgt[k] = Tr[k] * (gC0[k] * a.st.bg0 + gC1[k] * a.st.bg1 + gC2[k] * a.st.bg2);
+            U[k] = Tr[k] * (gC0[k] * a.st.bg0 + gC1[k] * a.st.bg1 + gC2[k] * a.st.bg2);
             mylast = max(mylast, last[k]);
         }
     }
@@ -327,54 +329,66 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             if ((uint32_t)j >= wlast) continue;  // wave-uniform
             const float4 r0 = srec[j - lo][0], r1 = srec[j - lo][1], r2 = srec[j - lo][2];
             if (!((__float_as_uint(r2.x) >> wave) & 1u)) continue;  // wave-uniform
-            float g[16];
+            // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
+            // passes
+            float p2v[PPT];
+            bool pass[PPT];
+            bool anyp = false;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) g[s] = 0.f;
+            for (int k = 0; k < PPT; ++k) {
+                p2v[k] = power_of(r0, r1, r0.x - cx[k], r0.y - cy[k]);
+                pass[k] = (uint32_t)j < last[k] && p2v[k] <= 0.f && p2v[k] >= r1.w;
+                anyp |= pass[k];
+            }
+            if (__ballot(anyp) == 0ull) continue;  // wave-uniform
+            float g[10];
+#pragma unroll
+            for (int s = 0; s < 10; ++s) g[s] = 0.f;
             bool contrib = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                const float power = power_of(r0, r1, dx, dy);
-                const float G = __expf(power);
+                const float p2 = p2v[k];
+                const float G = __builtin_amdgcn_exp2f(p2);  // e^power
                 const float araw = r1.y * G;
                 const float alpha = fminf(amax, araw);
-                const bool keep = (uint32_t)j < last[k] && power <= 0.f && power >= r1.w && alpha >= amin;
-                if (!keep) continue;
-                contrib = true;
+                const bool keep = pass[k] && alpha >= amin;
+                contrib |= keep;
+                // branch-free: a lane that does not keep this Gaussian gets w = 0 and a zero
+                // opacity/power adjoint, and keeps its T and U (alpha <= alpha_max < 1, so
+                // every quantity below stays finite)
                 const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
                 const float Tk = Tr[k] * rom;
-                const float w = alpha * Tk;
+                const float w = keep ? alpha * Tk : 0.f;
                 // colour / depth adjoints
                 g[6] += w * gC0[k];
                 g[7] += w * gC1[k];
                 g[8] += w * gC2[k];
                 g[9] += w * gD[k];
-                const float ga = Tk * (gC0[k] * r2.y + gC1[k] * r2.z + gC2[k] * r2.w + gD[k] * r1.z + gA[k]) -
-                                 (gC0[k] * S0[k] + gC1[k] * S1[k] + gC2[k] * S2[k] + gD[k] * SD[k] +
-                                  gA[k] * SA[k] + bgt[k]) * rom;
-                S0[k] += w * r2.y;
-                S1[k] += w * r2.z;
-                S2[k] += w * r2.w;
-                SD[k] += w * r1.z;
-                SA[k] += w;
-                Tr[k] = Tk;
-                if (araw <= amax) {
-                    // power = A' dx^2 + B' dx dy + C' dy^2 with (A', B', C') = (-a/2, -b, -c/2)
-                    const float gp = ga * alpha;  // dL/dpower
-                    g[5] += ga * G;               // dL/do
-                    g[0] += gp * (2.f * r0.z * dx + r0.w * dy);
-                    g[1] += gp * (r0.w * dx + 2.f * r1.x * dy);
-                    const float hgx = -0.5f * gp * dx;
-                    g[2] += hgx * dx;                 // dpower/da = -dx^2 / 2
-                    g[3] += 2.f * hgx * dy;           // dpower/db = -dx dy
-                    g[4] += -0.5f * gp * dy * dy;     // dpower/dc = -dy^2 / 2
-                }
+                const float qv = gC0[k] * r2.y + gC1[k] * r2.z + gC2[k] * r2.w + gD[k] * r1.z + gA[k];
+                const float ga = Tk * qv - U[k] * rom;  // dL/dalpha
+                U[k] += w * qv;
+                Tr[k] = keep ? Tk : Tr[k];
+                // through alpha = o e^power (no gradient where the alpha_max clamp is active)
+                const float gau = (keep && araw <= amax) ? ga : 0.f;
+                g[5] += gau * G;               // dL/do
+                const float gp = gau * alpha;  // dL/dpower
+                // pixel moments of dL/dpower; the projection backward turns them into the
+                // conic and centre adjoints: du = -(a M1 + b M2), dv = -(b M1 + c M2),
+                // da = -M3/2, db = -M4, dc = -M5/2
+                const float t1 = gp * dx, t2 = gp * dy;
+                g[0] += t1;
+                g[1] += t2;
+                g[2] += t1 * dx;
+                g[3] += t1 * dy;
+                g[4] += t2 * dy;
             }
             if (__ballot(contrib) == 0ull) continue;
-            const float tot = wave_transpose_sum16(g);
+            const float tot = wave_transpose_sum10(g);
             const int slot = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && slot < kGrad2d)
-                atomicAdd(a.grad2d + (long long)sq[j - lo] * kGrad2dStride + slot, tot);
+            const int val = slot < 5 ? slot : slot - 3;
+            if ((lane & 3) == 0 && (slot < 5 || (slot >= 8 && slot < 13)))
+                atomicAdd(a.grad2d + (long long)sq[j - lo] * kGrad2dStride + val, tot);
         }
         __syncthreads();
     }
