@@ -55,7 +55,7 @@ struct Layout {
     // saved
     size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_t_final, s_last, s_total;
     // fwd ws
-    size_t f_pair_z, f_vis_off, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_tkeys0, f_tkeys1,
+    size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_hist_sums, f_block_sums, f_total;
     // bwd ws
     size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_total;
@@ -144,12 +144,12 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     long long sb2 = scan_blocks(256LL * gmax);
     if (sb2 > sb) sb = sb2;
     L.f_pair_z = o; o = align_up(o + (size_t)Qs * 4);
-    L.f_vis_off = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dkeys0 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dkeys1 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dvals0 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dvals1 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_emit_off = o; o = align_up(o + (size_t)Qs * 4);
+    L.f_block_first = o; o = align_up(o + (size_t)(caps / 256 + 2) * 4);
     L.f_tkeys0 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tkeys1 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tvals1 = o; o = align_up(o + (size_t)caps * 4);
@@ -245,12 +245,12 @@ BinArgs bin_args(const Layout& L, void* saved, void* ws) {
     a.counters = at<uint32_t>(saved, L.s_counters);
     a.n_pairs = L.Q;
     a.capacity = L.cap;
-    a.vis_off = at<uint32_t>(ws, L.f_vis_off);
     a.depth_keys[0] = at<uint32_t>(ws, L.f_dkeys0);
     a.depth_keys[1] = at<uint32_t>(ws, L.f_dkeys1);
     a.depth_vals[0] = at<uint32_t>(ws, L.f_dvals0);
     a.depth_vals[1] = at<uint32_t>(ws, L.f_dvals1);
     a.emit_off = at<uint32_t>(ws, L.f_emit_off);
+    a.block_first = at<uint32_t>(ws, L.f_block_first);
     a.tile_keys[0] = at<uint32_t>(ws, L.f_tkeys0);
     a.tile_keys[1] = at<uint32_t>(ws, L.f_tkeys1);
     a.tile_vals[0] = at<uint32_t>(saved, L.s_tile_pairs);

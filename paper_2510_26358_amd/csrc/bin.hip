@@ -13,18 +13,6 @@
 
 namespace ags {
 
-__global__ void compact_visible_kernel(const uint32_t* pair_count, const uint32_t* pair_z,
-                                       const uint32_t* vis_off, long long n_pairs,
-                                       uint32_t* depth_keys, uint32_t* depth_vals) {
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_pairs) return;
-    if (pair_count[q] != 0u) {
-        uint32_t o = vis_off[q];
-        depth_keys[o] = pair_z[q];
-        depth_vals[o] = (uint32_t)q;
-    }
-}
-
 __global__ void finalize_counts_kernel(uint32_t* counters, long long capacity) {
     uint32_t k = counters[CNT_K];
     bool over = (long long)k > capacity;
@@ -32,34 +20,40 @@ __global__ void finalize_counts_kernel(uint32_t* counters, long long capacity) {
     counters[CNT_KEFF] = over ? (uint32_t)capacity : k;
 }
 
+// For every emission workgroup (256 output slots) the depth-ordered pair that owns its
+// first slot: pair j owns slots [emit_off[j], emit_off[j] + count), every count >= 1, so
+// each workgroup boundary lies in exactly one pair's range.
+__global__ void block_first_kernel(const uint32_t* pair_count, const uint32_t* depth_vals,
+                                   const uint32_t* emit_off, const uint32_t* counters, long long capacity,
+                                   long long n_max, uint32_t* block_first) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nv = counters[CNT_V];
+    if (j >= nv || j >= n_max) return;
+    long long keff = counters[CNT_KEFF];
+    if (keff > capacity) keff = capacity;
+    const long long o = emit_off[j];
+    const long long e = o + pair_count[depth_vals[j]];
+    for (long long m = (o + 255) / 256 * 256; m < e && m < keff; m += 256) block_first[m / 256] = (uint32_t)j;
+}
+
 // One thread per output slot k: the owning pair is the last j (depth order) with
 // emit_off[j] <= k; slot k - emit_off[j] of that pair's tile rectangle (row-major) gives
 // the tile.  Every visible pair owns >= 1 slot, so the 256 slots of a workgroup belong to at
-// most 256 consecutive pairs: one global binary search per workgroup finds the first, the
-// following 257 offsets are staged in LDS and each thread searches there.  Balanced however
-// unequal the footprints are, and the writes are coalesced.
+// most 256 consecutive pairs starting at block_first[workgroup]; their 257 offsets are
+// staged in LDS and each thread binary-searches there.  Balanced however unequal the
+// footprints are, and the writes are coalesced.
 __global__ __launch_bounds__(256) void emit_kernel(ViewTable vt, const float* records,
                                                    const uint32_t* depth_vals, const uint32_t* emit_off,
-                                                   const uint32_t* counters, long long capacity,
-                                                   uint32_t* tile_keys, uint32_t* tile_vals) {
+                                                   const uint32_t* block_first, const uint32_t* counters,
+                                                   long long capacity, uint32_t* tile_keys,
+                                                   uint32_t* tile_vals) {
     __shared__ uint32_t s_off[257];
-    __shared__ long long s_j0;
     const long long k0 = (long long)blockIdx.x * 256;
     long long keff = counters[CNT_KEFF];
     if (keff > capacity) keff = capacity;
     const long long nv = counters[CNT_V];
     if (k0 >= keff || nv == 0) return;  // uniform per workgroup
-    if (threadIdx.x == 0) {
-        long long lo = 0, hi = nv - 1;
-        while (lo < hi) {
-            const long long mid = (lo + hi + 1) >> 1;
-            if ((long long)emit_off[mid] <= k0) lo = mid;
-            else hi = mid - 1;
-        }
-        s_j0 = lo;
-    }
-    __syncthreads();
-    const long long j0 = s_j0;
+    const long long j0 = block_first[blockIdx.x];
     for (int t = threadIdx.x; t < 257; t += 256) {
         const long long j = j0 + t;
         s_off[t] = j < nv ? emit_off[j] : 0xFFFFFFFFu;
@@ -127,9 +121,8 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     const long long Q = a.n_pairs;
     const unsigned qgrid = (unsigned)((Q + 255) / 256 > 0 ? (Q + 255) / 256 : 1);
     // 1. visible pairs, compacted in pair order with their depth keys
-    launch_scan(a.pair_count, nullptr, true, a.vis_off, Q, nullptr, a.counters + CNT_V, a.scan_tmp, s);
-    hipLaunchKernelGGL(compact_visible_kernel, dim3(qgrid), dim3(256), 0, s, a.pair_count, a.pair_z,
-                       a.vis_off, Q, a.depth_keys[0], a.depth_vals[0]);
+    launch_scan_compact(a.pair_count, a.pair_z, Q, a.counters + CNT_V, a.depth_keys[0], a.depth_vals[0],
+                        a.scan_tmp, s);
     // 2. stable depth sort of the visible pairs
     int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.sort_tmp, s);
     const uint32_t* dvals = a.depth_vals[r];
@@ -142,8 +135,10 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     const int tp = sort_passes(a.tile_bits);
     const int first = (a.final_vals == a.tile_vals[0]) ? (tp % 2) : 1 - (tp % 2);
     const unsigned kgrid = (unsigned)((a.capacity + 255) / 256 > 0 ? (a.capacity + 255) / 256 : 1);
+    hipLaunchKernelGGL(block_first_kernel, dim3(qgrid), dim3(256), 0, s, a.pair_count, dvals, a.emit_off,
+                       a.counters, a.capacity, Q, a.block_first);
     hipLaunchKernelGGL(emit_kernel, dim3(kgrid), dim3(256), 0, s, a.vt, a.records, dvals, a.emit_off,
-                       a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first]);
+                       a.block_first, a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first]);
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};
     uint32_t* tv[2] = {a.tile_vals[first], a.tile_vals[1 - first]};

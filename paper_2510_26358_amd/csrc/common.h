@@ -328,6 +328,11 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
                  long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
                  hipStream_t s);
 
+// Order-preserving compaction: (payload[i], i) for every i < n with src[i] != 0, count to
+// *total.
+void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
+                         uint32_t* keys, uint32_t* vals, ScanTemp tmp, hipStream_t s);
+
 // LSD radix sort of (key, value) u32 pairs on bits [0, bits), n read from n_dev.
 struct SortTemp {
     uint32_t* hist;         // 256 * grid
@@ -349,10 +354,10 @@ struct BinArgs {
     uint32_t* counters;
     long long n_pairs;
     long long capacity;
-    uint32_t* vis_off;       // [n_pairs] scan of visibility
     uint32_t* depth_keys[2]; // [n_pairs]
     uint32_t* depth_vals[2];
     uint32_t* emit_off;      // [n_pairs] scan of tile counts in depth order
+    uint32_t* block_first;   // [capacity / 256 + 1] first depth-ordered pair of each emit workgroup
     uint32_t* tile_keys[2];  // [capacity]
     uint32_t* tile_vals[2];
     uint32_t* ranges;        // [n_tiles][2]

@@ -146,6 +146,47 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(
     }
 }
 
+// Apply phase that compacts instead of writing prefixes: element i with src[i] != 0 goes to
+// position prefix(i) of (keys, vals) as (payload[i], i).  Order-preserving.
+__global__ __launch_bounds__(kScanThreads) void scan_compact_kernel(
+    const uint32_t* src, const uint32_t* payload, long long n, const uint32_t* block_sums, uint32_t* keys,
+    uint32_t* vals) {
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    if (base >= n) return;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        long long i = base + (long long)threadIdx.x * kScanItems + k;
+        v[k] = (i < n && src[i] != 0u) ? 1u : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
+    uint32_t run = block_sums[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        long long i = base + (long long)threadIdx.x * kScanItems + k;
+        if (v[k]) {
+            keys[run] = payload[i];
+            vals[run] = (uint32_t)i;
+        }
+        run += v[k];
+    }
+}
+
+void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
+                         uint32_t* keys, uint32_t* vals, ScanTemp tmp, hipStream_t s) {
+    long long nb = scan_blocks(n);
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, nullptr, true, n,
+                       nullptr, tmp.block_sums);
+    hipLaunchKernelGGL(scan_blocksums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp.block_sums, nb, total);
+    hipLaunchKernelGGL(scan_compact_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, payload, n,
+                       tmp.block_sums, keys, vals);
+}
+
 void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32_t* out,
                  long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
                  hipStream_t s) {
@@ -165,9 +206,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortMaxGrid = 1024;
 
+// Workgroups per radix pass: about 8k items each, between 64 and 1024.
 int sort_grid(long long n_max) {
-    long long g = (n_max + 4095) / 4096;
-    return (int)(g < 1 ? 1 : (g > kSortMaxGrid ? kSortMaxGrid : g));
+    long long g = (n_max + 8191) / 8192;
+    return (int)(g < 64 ? 64 : (g > kSortMaxGrid ? kSortMaxGrid : g));
 }
 int sort_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
