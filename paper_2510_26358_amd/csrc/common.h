@@ -256,48 +256,52 @@ __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
     return w1;
 }
 
-// Sum of 10 per-lane values over the wave, same butterfly as above with the values placed
-// in slots {0..4, 8..12} so the first stage pairs real values only (the three all-zero
-// slot pairs are skipped).  On return lane L holds the total of slot (L >> 2) & 15; value
-// v lives in slot v for v < 5 and in slot v + 3 otherwise.
-__device__ __forceinline__ int slot_of_value10(int v) { return v < 5 ? v : v + 3; }
-
+// Sum of 10 per-lane values over the wave with the same butterfly, the values placed in
+// slots {0, 1, 2, 4, 5} (v < 5) and {8, 9, 10, 12, 13} (v >= 5) so that no stage pairs two
+// empty slots: 5 + 3 lane swaps, then 3 DPP stages.  Lanes of empty slots end with
+// meaningless sums (only empty-slot data flows into them).  On return lane L holds the
+// total of slot (L >> 2) & 15.
 __device__ __forceinline__ float wave_transpose_sum10(const float (&v)[10]) {
     const int lane = __lane_id();
-    float w8[8];
+    // stage 1 (lane bit 5): value j and j + 5 share slot low bits kSlot[j] = {0, 1, 2, 4, 5}
+    float w8[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 5]), false,
                                                   false);
         w8[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    w8[5] = w8[6] = w8[7] = 0.f;
-    float w4[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[j]), __float_as_uint(w8[j + 4]), false,
-                                                  false);
-        w4[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    // stage 2 (lane bit 4): slot low bits (0, 4) -> w8[0], w8[3]; (1, 5) -> w8[1], w8[4];
+    // (2, 6) -> w8[2] and an empty slot
+    float w4[3];
+    {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[0]), __float_as_uint(w8[3]), false, false);
+        w4[0] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[1]), __float_as_uint(w8[4]), false, false);
+        w4[1] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[2]), __float_as_uint(w8[2]), false, false);
+        w4[2] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+    // stage 3 (lane bit 3): (w4[0], w4[2]); w4[1]'s partner slot is empty, so both lane
+    // halves simply add their neighbour's w4[1]
     float w2[2];
     {
         const bool hi = lane & 8;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const float send = hi ? w4[j] : w4[j + 2];
-            const float keep = hi ? w4[j + 2] : w4[j];
-            w2[j] = keep + dpp_mov<0x128>(send);
-        }
+        const float send = hi ? w4[0] : w4[2];
+        const float keep = hi ? w4[2] : w4[0];
+        w2[0] = keep + dpp_mov<0x128>(send);  // row_ror:8 == lane ^ 8 inside a row
+        w2[1] = w4[1] + dpp_mov<0x128>(w4[1]);
     }
+    // stage 4 (lane bit 2), then lane bits 0 and 1
     float w1;
     {
         const bool hi = lane & 4;
         const float send = hi ? w2[0] : w2[1];
         const float keep = hi ? w2[1] : w2[0];
-        w1 = keep + dpp_mov<0x141>(send);
+        w1 = keep + dpp_mov<0x141>(send);  // row_half_mirror: lane i <-> 7 - i in 8-lane halves
     }
-    w1 += dpp_mov<0xB1>(w1);
-    w1 += dpp_mov<0x4E>(w1);
+    w1 += dpp_mov<0xB1>(w1);  // quad_perm [1, 0, 3, 2]: lane ^ 1
+    w1 += dpp_mov<0x4E>(w1);  // quad_perm [2, 3, 0, 1]: lane ^ 2
     return w1;
 }
 

@@ -114,21 +114,35 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 // log2(e) (-a/2, -b, -c/2), so the exponent in base 2, p2 = dx (A' dx + B' dy) + C' dy^2,
 // costs five operations and e^power = exp2(p2) is one instruction; the footprint extent is
 // replaced by log2(alpha_min / o) (a Gaussian whose exponent is below it cannot reach
-// alpha_min) and by the mask of wave blocks its footprint box touches.  Forward and backward stage identical values, so their decisions
-// agree; every skipped (pixel, Gaussian) pair has alpha < alpha_min, so the result is the
-// same as evaluating it.
-// LDS layout: [0] = (u, v, -a/2 log2e, -b log2e), [1] = (-c/2 log2e, o, z, log2(alpha_min/o)),
-//             [2] = (wave mask bits, r, g, b).
+// alpha_min) and by the mask of wave blocks its footprint box touches.  Forward and
+// backward stage identical values, so their decisions agree; every skipped (pixel,
+// Gaussian) pair has alpha < alpha_min, so the result is the same as evaluating it.
+// LDS layout (64 B, read at non-negative offsets from one per-lane address):
+//   [0] = (wave mask bits, r, g, b), [1] = (u, v, -a/2 log2e, -b log2e),
+//   [2] = (-c/2 log2e, o, z, log2(alpha_min/o)), [3] = (pair id, -, -, -).
+struct alignas(16) SRec {
+    float4 m, g0, g1;
+    uint32_t q, pad[3];
+};
+
 template <int T, int PPT, bool MASK>
 __device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
-                                             int px0, int py0, float4* dst) {
+                                             int px0, int py0, SRec& dst) {
     const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
     constexpr float kLog2e = 1.4426950408889634f;
-    dst[0] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
-    dst[1] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
     const uint32_t m = MASK ? wave_mask<T, PPT>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : 0xFFFFFFFFu;
-    dst[2] = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
+    dst.m = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
+    dst.g0 = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
+    dst.q = q;
+}
+
+// Keeps a value in a vector register from here on, so an LDS address derived from it is
+// advanced with one vector add per iteration instead of being rebuilt from scalars.
+template <typename V>
+__device__ __forceinline__ void in_vgpr(V& v) {
+    asm volatile("" : "+v"(v));
 }
 
 __device__ __forceinline__ float power_of(const float4& r0, const float4& r1, float dx, float dy) {
@@ -138,73 +152,78 @@ __device__ __forceinline__ float power_of(const float4& r0, const float4& r1, fl
 template <int T, int PPT, int M>
 __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     constexpr int NT = T * T / PPT;
-    __shared__ float4 srec[M][3];
+    __shared__ SRec srec[M];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const TileCoord tc = tile_coord(a.vt, tile);
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
+    const uint32_t end = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile + 1]);
     const int tid = threadIdx.x;
 
+    // A pixel that has stopped (or lies outside the image) gets cx = +inf: its exponent is
+    // then -inf (or NaN), below every threshold, so it keeps no further Gaussian without a
+    // separate flag test.
+    constexpr float kStopped = __builtin_huge_valf();
     float cx[PPT], cy[PPT], Tr[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], A[PPT];
     uint32_t last[PPT];
-    bool inside[PPT], done[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         int lx, ly;
         pixel_of<T, PPT, false>(tid, k, lx, ly);
         const int px = tc.px0 + lx, py = tc.py0 + ly;
-        inside[k] = px < tc.W && py < tc.H;
-        done[k] = !inside[k];
-        cx[k] = (float)px + 0.5f;
+        cx[k] = (px < tc.W && py < tc.H) ? (float)px + 0.5f : kStopped;
         cy[k] = (float)py + 0.5f;
         Tr[k] = 1.f;
         C0[k] = C1[k] = C2[k] = D[k] = A[k] = 0.f;
         last[k] = 0;
     }
-    const float amin = a.st.alpha_min, amax = a.st.alpha_max, tmin = a.st.t_min;
+    const float amin = a.st.alpha_min, tmin = a.st.t_min;
+    const float amax = __builtin_canonicalizef(a.st.alpha_max);
 
     for (uint32_t bs = start; bs < end; bs += M) {
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) any |= !done[k];
+        for (int k = 0; k < PPT; ++k) any |= cx[k] != kStopped;
         if (__syncthreads_count(any) == 0) break;
 #pragma unroll
         for (int l = tid; l < M; l += NT) {
             const uint32_t e = bs + l;
-            if (e < end) {
-                const uint32_t q = a.tile_pairs[e];
-                stage_record<T, PPT, false>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
-            }
+            if (e < end)
+                stage_record<T, PPT, false>(a.records, a.tile_pairs[e], amin, tc.W, tc.H, tc.px0, tc.py0,
+                                            srec[l]);
         }
         __syncthreads();
-        const int nb = (int)min((uint32_t)M, end - bs);
-        if (any) {
-            for (int j = 0; j < nb; ++j) {
-                bool live = false;
+        const uint32_t bend = end - bs > (uint32_t)M ? bs + M : end;
+        const char* sbase = reinterpret_cast<const char*>(srec);
+        uint32_t off = 0;  // byte offset of record e - bs in LDS
+        in_vgpr(off);
+        for (uint32_t e = bs; e < bend; ++e, off += sizeof(SRec)) {
+            bool live = false;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) live |= !done[k];
-                if (__ballot(live) == 0ull) break;  // wave-uniform: every pixel has stopped
-                const float4 r0 = srec[j][0], r1 = srec[j][1], r2 = srec[j][2];
+            for (int k = 0; k < PPT; ++k) live |= cx[k] != kStopped;
+            if (__ballot(live) == 0ull) break;  // wave-uniform: every pixel has stopped
+            const SRec& r = *reinterpret_cast<const SRec*>(sbase + off);
+            const float4 r0 = r.g0, r1 = r.g1;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    // one predicate, one branch: the exp is cheap next to divergent control
-                    const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                    const float p2 = power_of(r0, r1, dx, dy);
-                    const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
-                    // r1.w = log2(alpha_min / o): below it alpha cannot reach alpha_min
-                    const bool keep = !done[k] && p2 <= 0.f && p2 >= r1.w && alpha >= amin;
-                    if (keep) {
-                        const float tn = Tr[k] * (1.f - alpha);
-                        const bool stop = tn < tmin;
-                        const float w = stop ? 0.f : alpha * Tr[k];
-                        C0[k] += w * r2.y;
-                        C1[k] += w * r2.z;
-                        C2[k] += w * r2.w;
-                        D[k] += w * r1.z;
-                        A[k] += w;
-                        Tr[k] = stop ? Tr[k] : tn;
-                        last[k] = stop ? last[k] : bs - start + j + 1;
-                        done[k] = stop;
-                    }
+            for (int k = 0; k < PPT; ++k) {
+                // one predicate, one branch: the exp is cheap next to divergent control
+                const float dx = r0.x - cx[k], dy = r0.y - cy[k];
+                const float p2 = power_of(r0, r1, dx, dy);
+                const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
+                // r1.w = log2(alpha_min / o): below it alpha cannot reach alpha_min
+                const bool keep = p2 <= 0.f && p2 >= r1.w && alpha >= amin;
+                if (keep) {
+                    const float4 rc = r.m;
+                    const float tn = Tr[k] * (1.f - alpha);
+                    const bool stop = tn < tmin;
+                    const float w = stop ? 0.f : alpha * Tr[k];
+                    C0[k] += w * rc.y;
+                    C1[k] += w * rc.z;
+                    C2[k] += w * rc.w;
+                    D[k] += w * r1.z;
+                    A[k] += w;
+                    Tr[k] = stop ? Tr[k] : tn;
+                    last[k] = stop ? last[k] : e - start + 1;
+                    cx[k] = stop ? kStopped : cx[k];
                 }
             }
         }
@@ -213,9 +232,9 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     const long long plane = (long long)tc.W * tc.H;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if (!inside[k]) continue;
         int lx, ly;
         pixel_of<T, PPT, false>(tid, k, lx, ly);
+        if (tc.px0 + lx >= tc.W || tc.py0 + ly >= tc.H) continue;
         const long long p = (long long)(tc.py0 + ly) * tc.W + (tc.px0 + lx);
         const long long gp = tc.pix0 + p;
         float* rgb = a.rgb + 3 * tc.pix0;
@@ -232,13 +251,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
 template <int T, int PPT, int M>
 __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a) {
     constexpr int NT = T * T / PPT;
-    __shared__ float4 srec[M][3];
-    __shared__ uint32_t sq[M];
+    __shared__ SRec srec[M];
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const TileCoord tc = tile_coord(a.vt, tile);
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wave = tid >> 6;
@@ -314,23 +332,33 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     uint32_t wlast = mylast;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+    const int wl = (int)__builtin_amdgcn_readfirstlane(wlast);
 
-    const float amax = a.st.alpha_max;
+    const float amax = __builtin_canonicalizef(a.st.alpha_max);
+    const uint32_t wbit = 1u << wave;
+    // lane L ends the reduction holding slot (L >> 2) & 15; value v of the ten sums sits in
+    // slot kSlot[v % 5] + 8 (v / 5), see wave_transpose_sum10
+    const int slot = (lane >> 2) & 15, sl = slot & 7;
+    const bool red_lane = (lane & 3) == 0 && sl != 3 && sl < 6;
+    const int red_val = (sl < 3 ? sl : sl - 1) + 5 * (slot >> 3);
 
     for (int hi = (int)maxlast; hi > 0; hi -= M) {
         const int lo = hi - M > 0 ? hi - M : 0;
-        for (int l = tid; l < hi - lo; l += NT) {
-            const uint32_t q = a.tile_pairs[start + lo + l];
-            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
-            sq[l] = q;
-        }
+        for (int l = tid; l < hi - lo; l += NT)
+            stage_record<T, PPT, true>(a.records, a.tile_pairs[start + lo + l], amin, tc.W, tc.H, tc.px0,
+                                       tc.py0, srec[l]);
         __syncthreads();
-        for (int j = hi - 1; j >= lo; --j) {
-            if ((uint32_t)j >= wlast) continue;  // wave-uniform
-            const float4 r0 = srec[j - lo][0], r1 = srec[j - lo][1], r2 = srec[j - lo][2];
-            if (!((__float_as_uint(r2.x) >> wave) & 1u)) continue;  // wave-uniform
+        const int jtop = min(hi, wl);  // wave-uniform
+        int e = jtop - 1 - lo;         // LDS slot, advanced in a vector register
+        in_vgpr(e);
+        for (int j = jtop - 1; j >= lo; --j, --e) {
+            const SRec& r = srec[e];
+            const float4 rm = r.m;
+            if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) continue;  // wave-uniform
+            const float4 r0 = r.g0, r1 = r.g1;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
-            // passes
+            // passes (a lane passes exactly when it can keep this Gaussian, up to rounding of
+            // the threshold, and keeps are re-tested on alpha below)
             float p2v[PPT];
             bool pass[PPT];
             bool anyp = false;
@@ -343,9 +371,6 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             if (__ballot(anyp) == 0ull) continue;  // wave-uniform
             float g[10];
 #pragma unroll
-            for (int s = 0; s < 10; ++s) g[s] = 0.f;
-            bool contrib = false;
-#pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
                 const float p2 = p2v[k];
@@ -353,42 +378,31 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 const float araw = r1.y * G;
                 const float alpha = fminf(amax, araw);
                 const bool keep = pass[k] && alpha >= amin;
-                contrib |= keep;
                 // branch-free: a lane that does not keep this Gaussian gets w = 0 and a zero
                 // opacity/power adjoint, and keeps its T and U (alpha <= alpha_max < 1, so
                 // every quantity below stays finite)
                 const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
                 const float Tk = Tr[k] * rom;
                 const float w = keep ? alpha * Tk : 0.f;
-                // colour / depth adjoints
-                g[6] += w * gC0[k];
-                g[7] += w * gC1[k];
-                g[8] += w * gC2[k];
-                g[9] += w * gD[k];
-                const float qv = gC0[k] * r2.y + gC1[k] * r2.z + gC2[k] * r2.w + gD[k] * r1.z + gA[k];
+                const float qv = gC0[k] * rm.y + gC1[k] * rm.z + gC2[k] * rm.w + gD[k] * r1.z + gA[k];
                 const float ga = Tk * qv - U[k] * rom;  // dL/dalpha
                 U[k] += w * qv;
                 Tr[k] = keep ? Tk : Tr[k];
                 // through alpha = o e^power (no gradient where the alpha_max clamp is active)
                 const float gau = (keep && araw <= amax) ? ga : 0.f;
-                g[5] += gau * G;               // dL/do
                 const float gp = gau * alpha;  // dL/dpower
                 // pixel moments of dL/dpower; the projection backward turns them into the
                 // conic and centre adjoints: du = -(a M1 + b M2), dv = -(b M1 + c M2),
                 // da = -M3/2, db = -M4, dc = -M5/2
                 const float t1 = gp * dx, t2 = gp * dy;
-                g[0] += t1;
-                g[1] += t2;
-                g[2] += t1 * dx;
-                g[3] += t1 * dy;
-                g[4] += t2 * dy;
+                const float c[10] = {t1, t2, t1 * dx, t1 * dy, t2 * dy,  // moments
+                                     gau * G,                            // dL/do
+                                     w * gC0[k], w * gC1[k], w * gC2[k], w * gD[k]};
+#pragma unroll
+                for (int s = 0; s < 10; ++s) g[s] = k == 0 ? c[s] : g[s] + c[s];
             }
-            if (__ballot(contrib) == 0ull) continue;
             const float tot = wave_transpose_sum10(g);
-            const int slot = (lane >> 2) & 15;
-            const int val = slot < 5 ? slot : slot - 3;
-            if ((lane & 3) == 0 && (slot < 5 || (slot >= 8 && slot < 13)))
-                atomicAdd(a.grad2d + (long long)sq[j - lo] * kGrad2dStride + val, tot);
+            if (red_lane) atomicAdd(a.grad2d + (long long)r.q * kGrad2dStride + red_val, tot);
         }
         __syncthreads();
     }
