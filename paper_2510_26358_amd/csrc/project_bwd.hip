@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
                 Sg[r][c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
     }
 
+    const float o = 1.f / (1.f + __expf(-logit));
     float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
@@ -71,9 +72,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
         for (int k = 0; k < 16; ++k) pose[k] = 0.f;
         if (vis) {
             const float* g2 = opaque_ptr(a.grad2d) + q * kGrad2dStride;
-            // slots 0..4 hold pixel moments of dL/dpower: M1 = sum gp dx, M2 = sum gp dy,
-            // M3 = sum gp dx^2, M4 = sum gp dx dy, M5 = sum gp dy^2 (dx, dy = centre - pixel)
-            const float M1 = g2[0], M2 = g2[1], M3 = g2[2], M4 = g2[3], M5 = g2[4];
+            // slots 0..4 hold pixel moments of dL/dpower = o h (h = dL/do per pixel) without
+            // the factor o: sum h dx, h dy, h dx^2, h dx dy, h dy^2 (dx, dy = centre - pixel)
+            const float M1 = o * g2[0], M2 = o * g2[1], M3 = o * g2[2], M4 = o * g2[3], M5 = o * g2[4];
             const float g_o = g2[5], g_r = g2[6], g_g = g2[7], g_bl = g2[8], g_zd = g2[9];
             const ags_camera cam = opaque_ptr(a.cams)[b];
             const float* R = cam.R;
@@ -265,7 +266,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     const float dot = uw * gw + ux * gx_ + uy * gy_ + uz * gz_;
     const float gq[4] = {(gw - uw * dot) * qinv, (gx_ - ux * dot) * qinv, (gy_ - uy * dot) * qinv,
                          (gz_ - uz * dot) * qinv};
-    const float o = 1.f / (1.f + __expf(-logit));
     const float glogit = go * o * (1.f - o);
 
     if (a.accumulate) {

@@ -18,9 +18,10 @@
 //   dL/dalpha_k = T_k (gC . c_k + gD z_k + gA)
 //                 - (gC . S^C + gD S^D + gA S^A + T_final gC . bg) / (1 - alpha_k)
 // (the bracket is kept as one running sum U), then chains through alpha = o e^power (unless
-// clamped) to the opacity and to dL/dpower, of which it keeps five pixel moments
-// (sum gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2) that the projection backward turns into
-// the centre and conic adjoints; dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian
+// clamped) to the opacity, h = dL/do = e^power dL/dalpha, and to dL/dpower = o h, of which
+// it keeps five pixel moments without the factor o (sum h dx, h dy, h dx^2, h dx dy,
+// h dy^2); the projection backward applies o and turns them into the centre and conic
+// adjoints.  dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian
 // sums of a wave are reduced with a transposing butterfly so one atomic instruction with
 // ten active lanes updates the pair's adjoint.
 #include "common.h"
@@ -248,7 +249,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     }
 }
 
-template <int T, int PPT, int M>
+// GA: the upstream adjoint has an alpha term (dL/dA); the fused loss never has one.
+template <int T, int PPT, int M, bool GA>
 __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ SRec srec[M];
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                     gC2[k] = g[2 * plane + p];
                 }
                 if (a.d_depth) gD[k] = a.d_depth[gp];
-                if (a.d_alpha) gA[k] = a.d_alpha[gp];
+                if (GA) gA[k] = a.d_alpha[gp];
             }
             U[k] = Tr[k] * (gC0[k] * a.st.bg0 + gC1[k] * a.st.bg1 + gC2[k] * a.st.bg2);
             mylast = max(mylast, last[k]);
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const int wl = (int)__builtin_amdgcn_readfirstlane(wlast);
 
     const float amax = __builtin_canonicalizef(a.st.alpha_max);
-    const uint32_t wbit = 1u << wave;
+    const uint32_t wbit = 1u << __builtin_amdgcn_readfirstlane(wave);
     // lane L ends the reduction holding slot (L >> 2) & 15; value v of the ten sums sits in
     // slot kSlot[v % 5] + 8 (v / 5), see wave_transpose_sum10
     const int slot = (lane >> 2) & 15, sl = slot & 7;
@@ -378,25 +380,25 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 const float araw = r1.y * G;
                 const float alpha = fminf(amax, araw);
                 const bool keep = pass[k] && alpha >= amin;
-                // branch-free: a lane that does not keep this Gaussian gets w = 0 and a zero
-                // opacity/power adjoint, and keeps its T and U (alpha <= alpha_max < 1, so
-                // every quantity below stays finite)
-                const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
+                // branch-free: a lane that does not keep this Gaussian runs the same steps
+                // with alpha = 0, so its w is 0 and its T and U stay as they are (and every
+                // quantity stays finite: alpha <= alpha_max < 1)
+                const float ak = keep ? alpha : 0.f;
+                const float rom = __builtin_amdgcn_rcpf(1.f - ak);
                 const float Tk = Tr[k] * rom;
-                const float w = keep ? alpha * Tk : 0.f;
-                const float qv = gC0[k] * rm.y + gC1[k] * rm.z + gC2[k] * rm.w + gD[k] * r1.z + gA[k];
+                const float w = ak * Tk;
+                float qv = gC0[k] * rm.y + gC1[k] * rm.z + gC2[k] * rm.w + gD[k] * r1.z;
+                if (GA) qv += gA[k];
                 const float ga = Tk * qv - U[k] * rom;  // dL/dalpha
                 U[k] += w * qv;
-                Tr[k] = keep ? Tk : Tr[k];
-                // through alpha = o e^power (no gradient where the alpha_max clamp is active)
-                const float gau = (keep && araw <= amax) ? ga : 0.f;
-                const float gp = gau * alpha;  // dL/dpower
-                // pixel moments of dL/dpower; the projection backward turns them into the
-                // conic and centre adjoints: du = -(a M1 + b M2), dv = -(b M1 + c M2),
-                // da = -M3/2, db = -M4, dc = -M5/2
-                const float t1 = gp * dx, t2 = gp * dy;
-                const float c[10] = {t1, t2, t1 * dx, t1 * dy, t2 * dy,  // moments
-                                     gau * G,                            // dL/do
+                Tr[k] = Tk;
+                // through alpha = o e^power (no gradient where the alpha_max clamp is active):
+                // h = dL/do, and dL/dpower = h o, whose factor o the projection backward
+                // applies to the five pixel moments kept here (sum h dx, h dy, h dx^2, h dx dy,
+                // h dy^2); it turns them into the centre and conic adjoints
+                const float h = (keep && araw <= amax) ? ga * G : 0.f;
+                const float t1 = h * dx, t2 = h * dy;
+                const float c[10] = {t1, t2, t1 * dx, t1 * dy, t2 * dy, h,
                                      w * gC0[k], w * gC1[k], w * gC2[k], w * gD[k]};
 #pragma unroll
                 for (int s = 0; s < 10; ++s) g[s] = k == 0 ? c[s] : g[s] + c[s];
@@ -437,10 +439,14 @@ int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s) {
     const int nb = raster_blocks(a.vt);
     if (nb <= 0) return 0;
-#define X(t_, p_, m_)                                                                              \
-    if (T == t_ && ppt == p_ && batch == m_) {                                                     \
-        hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
-        return 0;                                                                                  \
+    const bool ga = !a.loss_mode && a.d_alpha != nullptr;
+#define X(t_, p_, m_)                                                                                      \
+    if (T == t_ && ppt == p_ && batch == m_) {                                                             \
+        if (ga)                                                                                            \
+            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, true>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a);  \
+        else                                                                                               \
+            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, false>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        return 0;                                                                                          \
     }
     AGS_RASTER_CONFIGS(X)
 #undef X
