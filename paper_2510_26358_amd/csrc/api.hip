@@ -56,7 +56,7 @@ struct Layout {
     size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_t_final, s_last, s_total;
     // fwd ws
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
-        f_tvals1, f_hist, f_hist_sums, f_block_sums, f_total;
+        f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
     // bwd ws
     size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_total;
     long long n_partials;
@@ -140,9 +140,7 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.s_total = o;
     o = 0;
     const int gmax = L.depth_grid > L.tile_grid ? L.depth_grid : L.tile_grid;
-    long long sb = scan_blocks(Qs);
-    long long sb2 = scan_blocks(256LL * gmax);
-    if (sb2 > sb) sb = sb2;
+    const long long sb = scan_blocks(Qs);
     L.f_pair_z = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dkeys0 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dkeys1 = o; o = align_up(o + (size_t)Qs * 4);
@@ -153,8 +151,8 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.f_tkeys0 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tkeys1 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tvals1 = o; o = align_up(o + (size_t)caps * 4);
-    L.f_hist = o; o = align_up(o + (size_t)256 * gmax * 4);
-    L.f_hist_sums = o; o = align_up(o + (size_t)sb * 4);
+    L.f_hist = o; o = align_up(o + (size_t)sort_hist_entries(gmax) * 4);
+    L.f_rowtot = o; o = align_up(o + (size_t)sort_rowtot_entries() * 4);
     L.f_block_sums = o; o = align_up(o + (size_t)sb * 4);
     L.f_total = o;
     o = 0;
@@ -260,18 +258,13 @@ BinArgs bin_args(const Layout& L, void* saved, void* ws) {
     a.tile_bits = L.tile_bits;
     a.scan_tmp.block_sums = at<uint32_t>(ws, L.f_block_sums);
     a.sort_tmp.hist = at<uint32_t>(ws, L.f_hist);
-    a.sort_tmp.hist_sums = at<uint32_t>(ws, L.f_hist_sums);
-    a.sort_tmp.grid = L.depth_grid;
+    a.sort_tmp.rowtot = at<uint32_t>(ws, L.f_rowtot);
+    a.depth_grid = L.depth_grid;
+    a.tile_grid = L.tile_grid;
     return a;
 }
 
-// Runs the binning with the depth-sort grid, then the tile-sort grid.
-int run_binning(const Layout& L, BinArgs a, hipStream_t s) {
-    // the two sorts use grids sized for their own maxima; launch_binning uses one grid,
-    // so pick the larger (both fit the histogram buffer)
-    a.sort_tmp.grid = L.depth_grid > L.tile_grid ? L.depth_grid : L.tile_grid;
-    return launch_binning(a, s);
-}
+int run_binning(BinArgs a, hipStream_t s) { return launch_binning(a, s); }
 
 }  // namespace
 
@@ -410,7 +403,7 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     }
     {
         Scope sc(ctx, ST_BINNING, s);
-        run_binning(L, bin_args(L, saved, ws), s);
+        run_binning(bin_args(L, saved, ws), s);
     }
     {
         Scope sc(ctx, ST_RASTER_FWD, s);
@@ -448,7 +441,7 @@ int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, c
                              hipMemcpyDeviceToDevice, s);
     launch_count_from_records(L.vt, records, valid, L.Q, at<uint32_t>(saved, L.s_pair_count),
                               at<uint32_t>(ws, L.f_pair_z), s);
-    run_binning(L, bin_args(L, saved, ws), s);
+    run_binning(bin_args(L, saved, ws), s);
     return hip_status(ctx);
 }
 

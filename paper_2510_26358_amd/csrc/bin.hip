@@ -124,7 +124,7 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     launch_scan_compact(a.pair_count, a.pair_z, Q, a.counters + CNT_V, a.depth_keys[0], a.depth_vals[0],
                         a.scan_tmp, s);
     // 2. stable depth sort of the visible pairs
-    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.sort_tmp, s);
+    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.depth_grid, a.sort_tmp, s);
     const uint32_t* dvals = a.depth_vals[r];
     // 3. intersection offsets in depth order, total K, overflow flag
     launch_scan(a.pair_count, dvals, false, a.emit_off, Q, a.counters + CNT_V, a.counters + CNT_K,
@@ -142,7 +142,8 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};
     uint32_t* tv[2] = {a.tile_vals[first], a.tile_vals[1 - first]};
-    int rt = launch_radix_sort(tk, tv, a.capacity, a.counters + CNT_KEFF, a.tile_bits, a.sort_tmp, s);
+    int rt = launch_radix_sort(tk, tv, a.capacity, a.counters + CNT_KEFF, a.tile_bits, a.tile_grid, a.sort_tmp,
+                               s);
     // 6. per-tile ranges
     const long long n_tiles = a.vt.tile_base[a.vt.n_views];
     launch_fill_u32(a.ranges, 0u, 2 * n_tiles, s);

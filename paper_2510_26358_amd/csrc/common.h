@@ -337,18 +337,20 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
 void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
                          uint32_t* keys, uint32_t* vals, ScanTemp tmp, hipStream_t s);
 
-// LSD radix sort of (key, value) u32 pairs on bits [0, bits), n read from n_dev.
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), n read from n_dev,
+// with `grid` workgroups per pass (sort_grid of the static maximum, at most 256).
 struct SortTemp {
-    uint32_t* hist;         // 256 * grid
-    uint32_t* hist_sums;    // scan_blocks(256 * grid)
-    int grid;
+    uint32_t* hist;         // sort_hist_entries(grid): per-workgroup digit totals, then offsets
+    uint32_t* rowtot;       // sort_rowtot_entries(): per-digit totals
 };
 int sort_grid(long long n_max);
 int sort_passes(int bits);
+long long sort_hist_entries(int grid);
+long long sort_rowtot_entries();
 // keys/vals: [0] = input, [1] = other buffer; returns index of the buffer holding the
 // result (0 or 1).
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
-                      int bits, SortTemp tmp, hipStream_t s);
+                      int bits, int grid, SortTemp tmp, hipStream_t s);
 
 struct BinArgs {
     ViewTable vt;
@@ -369,6 +371,7 @@ struct BinArgs {
     int tile_bits;
     ScanTemp scan_tmp;
     SortTemp sort_tmp;
+    int depth_grid, tile_grid;  // radix-sort workgroups of the two sorts
 };
 void launch_count_from_records(const ViewTable& vt, const float* records, const uint8_t* valid,
                                long long n_pairs, uint32_t* pair_count, uint32_t* pair_z,

@@ -202,14 +202,27 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
 }
 
 // ------------------------------------------------------------------------- radix sort
+// Stable LSD radix sort, up to 8 bits per pass, three kernels per pass (count, scan,
+// scatter).  Workgroup b owns the items [b chunk, (b + 1) chunk) of the live count, chunk a
+// multiple of the 2048-item tile:
+//  1. count: per-workgroup digit totals, stored digit-major (entry d * grid + b).
+//  2. row scan: one workgroup per digit turns its row into exclusive offsets and stores
+//     the row total.
+//  3. scatter: a workgroup starts digit d at (sum of the row totals below d) + its row
+//     offset, then per tile ranks the items by digit in LDS (stable: ballots inside a
+//     wave, per-(sub-tile, wave) counts across waves), regroups the tile by digit in LDS
+//     and writes each digit's run to consecutive addresses.
+// Item order inside a digit is preserved, so the passes compose into a stable sort.
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortMaxGrid = 1024;
+constexpr int kSortItems = 8;                            // items per thread per tile
+constexpr int kSortTile = kSortThreads * kSortItems;     // 2048
+constexpr int kSortMaxGrid = 4 * kSortThreads;           // row scan: 4 entries per thread
 
-// Workgroups per radix pass: about 8k items each, between 64 and 1024.
+// Workgroups per radix pass: about 8k items each, between 16 and 1024.
 int sort_grid(long long n_max) {
     long long g = (n_max + 8191) / 8192;
-    return (int)(g < 64 ? 64 : (g > kSortMaxGrid ? kSortMaxGrid : g));
+    return (int)(g < 16 ? 16 : (g > kSortMaxGrid ? kSortMaxGrid : g));
 }
 int sort_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
@@ -230,15 +243,38 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
 }
 
 __device__ __forceinline__ void chunk_of_block(long long n, int grid, long long& start, long long& end) {
-    long long chunk = (n + grid - 1) / grid;
+    const long long chunk = ((n + grid - 1) / grid + kSortTile - 1) / kSortTile * kSortTile;
     start = (long long)blockIdx.x * chunk;
-    end = start + chunk;
-    if (end > n) end = n;
+    end = start + chunk < n ? start + chunk : n;
+    if (start > n) start = n;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
-    const uint32_t* keys, long long n_max, const uint32_t* n_dev, int shift, int dbits,
-    uint32_t* hist, int grid) {
+// Exclusive scan of one value per thread over a kSortThreads workgroup; total returned.
+__device__ __forceinline__ uint32_t sort_block_scan(uint32_t v, uint32_t* wtot, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int x = 0; x < kSortWaves; ++x) {
+        const uint32_t y = wtot[x];
+        before += x < wv ? y : 0u;
+        total += y;
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
+    const uint32_t* keys, long long n_max, const uint32_t* n_dev, int shift, int dbits, uint32_t* hist,
+    int grid) {
     __shared__ uint32_t h[256];
     const long long n = live_count(n_max, n_dev);
     long long start, end;
@@ -246,79 +282,152 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t mask = (1u << dbits) - 1u;
-    for (long long base = start; base < end; base += kSortThreads) {
-        long long i = base + threadIdx.x;
-        bool act = i < end;
-        uint32_t dig = act ? (keys[i] >> shift) & mask : 0u;
-        unsigned long long active = __ballot(act);
-        unsigned long long m = match_digit(dig, dbits, active);
-        if (act && lanes_below(m) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
+    for (long long base = start; base < end; base += kSortTile) {
+        uint32_t kv[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const long long i = base + k * kSortThreads + threadIdx.x;
+            kv[k] = i < end ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const bool act = base + k * kSortThreads + threadIdx.x < end;
+            const uint32_t dig = (kv[k] >> shift) & mask;
+            const unsigned long long m = match_digit(dig, dbits, __ballot(act));
+            if (act && lanes_below(m) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
+        }
     }
     __syncthreads();
     hist[(long long)threadIdx.x * grid + blockIdx.x] = h[threadIdx.x];
 }
 
+// Workgroup d: exclusive scan of row d (grid <= kSortMaxGrid entries, 4 consecutive ones per
+// thread) in place; row total to rowtot[d].
+__global__ __launch_bounds__(kSortThreads) void radix_rowscan_kernel(uint32_t* hist, uint32_t* rowtot,
+                                                                     int grid) {
+    __shared__ uint32_t wtot[kSortWaves];
+    uint32_t* row = hist + (long long)blockIdx.x * grid;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * (int)threadIdx.x + k;
+        v[k] = i < grid ? row[i] : 0u;
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t ex = sort_block_scan(sum, wtot, total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * (int)threadIdx.x + k;
+        if (i < grid) row[i] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) rowtot[blockIdx.x] = total;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-    long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist_scanned,
-    int grid) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kSortWaves][256];
+    long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
+    const uint32_t* rowtot, int grid) {
+    __shared__ uint32_t run[256];                             // global cursor per digit
+    __shared__ uint32_t cnt[kSortItems][kSortWaves][256];     // counts, then rank bases
+    __shared__ uint32_t tstart[256];                          // digit start inside the tile
+    __shared__ uint32_t ttot[256];                            // digit count of the tile
+    __shared__ uint32_t skey[kSortTile], sval[kSortTile];
+    __shared__ uint32_t wtot[kSortWaves];
     const long long n = live_count(n_max, n_dev);
     long long start, end;
     chunk_of_block(n, grid, start, end);
-    const int wave = threadIdx.x >> 6;
-    run[threadIdx.x] = hist_scanned[(long long)threadIdx.x * grid + blockIdx.x];
+    const int t = threadIdx.x, w = t >> 6;
+    {
+        uint32_t total;
+        const uint32_t base = sort_block_scan(rowtot[t], wtot, total);
+        run[t] = base + hist[(long long)t * grid + blockIdx.x];
+    }
     const uint32_t mask = (1u << dbits) - 1u;
-    for (long long base = start; base < end; base += kSortThreads) {
+    for (long long base = start; base < end; base += kSortTile) {
+        const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
+        uint32_t kv[kSortItems], vv[kSortItems], dig[kSortItems], below[kSortItems];
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) wcnt[w][threadIdx.x] = 0;
+        for (int k = 0; k < kSortItems; ++k) {
+            const int l = k * kSortThreads + t;
+            kv[k] = l < nt ? keys_in[base + l] : 0u;
+            vv[k] = l < nt ? vals_in[base + l] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k)
+#pragma unroll
+            for (int x = 0; x < kSortWaves; ++x) cnt[k][x][t] = 0;
         __syncthreads();
-        long long i = base + threadIdx.x;
-        bool act = i < end;
-        uint32_t key = act ? keys_in[i] : 0u;
-        uint32_t val = act ? vals_in[i] : 0u;
-        uint32_t dig = (key >> shift) & mask;
-        unsigned long long active = __ballot(act);
-        unsigned long long m = match_digit(dig, dbits, active);
-        uint32_t below = lanes_below(m);
-        if (act && below == 0) wcnt[wave][dig] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (act) {
-            uint32_t r = run[dig] + below;
-            for (int w = 0; w < wave; ++w) r += wcnt[w][dig];
-            keys_out[r] = key;
-            vals_out[r] = val;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const bool act = k * kSortThreads + t < nt;
+            dig[k] = (kv[k] >> shift) & mask;
+            const unsigned long long m = match_digit(dig[k], dbits, __ballot(act));
+            below[k] = lanes_below(m);
+            if (act && below[k] == 0) cnt[k][w][dig[k]] = (uint32_t)__popcll(m);
         }
         __syncthreads();
-        uint32_t add = 0;
+        // thread t = digit: rank bases in (sub-tile, wave) order, then the digit starts
+        uint32_t r = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) add += wcnt[w][threadIdx.x];
-        run[threadIdx.x] += add;
+        for (int k = 0; k < kSortItems; ++k)
+#pragma unroll
+            for (int x = 0; x < kSortWaves; ++x) {
+                const uint32_t c = cnt[k][x][t];
+                cnt[k][x][t] = r;
+                r += c;
+            }
+        uint32_t total;
+        const uint32_t ds = sort_block_scan(r, wtot, total);
+        tstart[t] = ds;
+        ttot[t] = r;
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            if (k * kSortThreads + t < nt) {
+                const uint32_t pos = tstart[dig[k]] + cnt[k][w][dig[k]] + below[k];
+                skey[pos] = kv[k];
+                sval[pos] = vv[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int p = k * kSortThreads + t;
+            if (p < nt) {
+                const uint32_t key = skey[p];
+                const uint32_t d = (key >> shift) & mask;
+                const uint32_t dst = run[d] + (uint32_t)p - tstart[d];
+                keys_out[dst] = key;
+                vals_out[dst] = sval[p];
+            }
+        }
+        __syncthreads();
+        run[t] += ttot[t];
     }
 }
 
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
-                      int bits, SortTemp tmp, hipStream_t s) {
+                      int bits, int grid, SortTemp tmp, hipStream_t s) {
     const int passes = sort_passes(bits);
     if (passes == 0) return 0;
     const int dbits = (bits + passes - 1) / passes;
-    const int grid = tmp.grid;
     int cur = 0;
-    ScanTemp st{tmp.hist_sums};
     for (int p = 0; p < passes; ++p) {
         const int shift = p * dbits;
         const int db = (shift + dbits > bits) ? bits - shift : dbits;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], n_max,
-                           n_dev, shift, db, tmp.hist, grid);
-        launch_scan(tmp.hist, nullptr, false, tmp.hist, 256LL * grid, nullptr, nullptr, st, s);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur],
-                           vals[cur], keys[1 - cur], vals[1 - cur], n_max, n_dev, shift, db, tmp.hist,
-                           grid);
+        hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], n_max, n_dev,
+                           shift, db, tmp.hist, grid);
+        hipLaunchKernelGGL(radix_rowscan_kernel, dim3(256), dim3(kSortThreads), 0, s, tmp.hist, tmp.rowtot, grid);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
+                           keys[1 - cur], vals[1 - cur], n_max, n_dev, shift, db, tmp.hist, tmp.rowtot, grid);
         cur = 1 - cur;
     }
     return cur;
 }
+
+long long sort_hist_entries(int grid) { return 256LL * grid; }
+long long sort_rowtot_entries() { return 256; }
 
 }  // namespace ags
