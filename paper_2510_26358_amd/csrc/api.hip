@@ -147,7 +147,7 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.f_dvals0 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_dvals1 = o; o = align_up(o + (size_t)Qs * 4);
     L.f_emit_off = o; o = align_up(o + (size_t)Qs * 4);
-    L.f_block_first = o; o = align_up(o + (size_t)(caps / 256 + 2) * 4);
+    L.f_block_first = o; o = align_up(o + (size_t)(caps / kEmitSlots + 2) * 4);
     L.f_tkeys0 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tkeys1 = o; o = align_up(o + (size_t)caps * 4);
     L.f_tvals1 = o; o = align_up(o + (size_t)caps * 4);

@@ -13,71 +13,71 @@
 
 namespace ags {
 
-__global__ void finalize_counts_kernel(uint32_t* counters, long long capacity) {
-    uint32_t k = counters[CNT_K];
-    bool over = (long long)k > capacity;
-    counters[CNT_OVERFLOW] = over ? 1u : 0u;
-    counters[CNT_KEFF] = over ? (uint32_t)capacity : k;
-}
+// Emission.  Output slot k belongs to the last pair j (depth order) with emit_off[j] <= k and
+// is slot k - emit_off[j] of that pair's tile rectangle (row-major).  A workgroup fills
+// kEmitSlots consecutive slots; since every visible pair owns >= 1 slot, they belong to at
+// most kEmitSlots consecutive pairs starting at block_first[workgroup].  Their offsets, and
+// for each pair the tile id of its rectangle's first tile, its width and the row pitch, are
+// staged in LDS (one thread per pair), and each slot binary-searches there.  Balanced
+// however unequal the footprints are, and the writes are coalesced.
+constexpr int kEmitThreads = 256;
 
-// For every emission workgroup (256 output slots) the depth-ordered pair that owns its
-// first slot: pair j owns slots [emit_off[j], emit_off[j] + count), every count >= 1, so
-// each workgroup boundary lies in exactly one pair's range.
-__global__ void block_first_kernel(const uint32_t* pair_count, const uint32_t* depth_vals,
-                                   const uint32_t* emit_off, const uint32_t* counters, long long capacity,
-                                   long long n_max, uint32_t* block_first) {
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nv = counters[CNT_V];
-    if (j >= nv || j >= n_max) return;
-    long long keff = counters[CNT_KEFF];
-    if (keff > capacity) keff = capacity;
-    const long long o = emit_off[j];
-    const long long e = o + pair_count[depth_vals[j]];
-    for (long long m = (o + 255) / 256 * 256; m < e && m < keff; m += 256) block_first[m / 256] = (uint32_t)j;
-}
-
-// One thread per output slot k: the owning pair is the last j (depth order) with
-// emit_off[j] <= k; slot k - emit_off[j] of that pair's tile rectangle (row-major) gives
-// the tile.  Every visible pair owns >= 1 slot, so the 256 slots of a workgroup belong to at
-// most 256 consecutive pairs starting at block_first[workgroup]; their 257 offsets are
-// staged in LDS and each thread binary-searches there.  Balanced however unequal the
-// footprints are, and the writes are coalesced.
-__global__ __launch_bounds__(256) void emit_kernel(ViewTable vt, const float* records,
-                                                   const uint32_t* depth_vals, const uint32_t* emit_off,
-                                                   const uint32_t* block_first, const uint32_t* counters,
-                                                   long long capacity, uint32_t* tile_keys,
-                                                   uint32_t* tile_vals) {
-    __shared__ uint32_t s_off[257];
-    const long long k0 = (long long)blockIdx.x * 256;
+__global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const float* records,
+                                                            const uint32_t* depth_vals, const uint32_t* emit_off,
+                                                            const uint32_t* block_first, const uint32_t* counters,
+                                                            long long capacity, uint32_t* tile_keys,
+                                                            uint32_t* tile_vals) {
+    constexpr int S = kEmitSlots, PT = S / kEmitThreads;
+    __shared__ uint32_t s_off[S];
+    __shared__ uint32_t s_q[S], s_first[S], s_w[S], s_pitch[S];
+    const long long k0 = (long long)blockIdx.x * S;
     long long keff = counters[CNT_KEFF];
     if (keff > capacity) keff = capacity;
     const long long nv = counters[CNT_V];
     if (k0 >= keff || nv == 0) return;  // uniform per workgroup
     const long long j0 = block_first[blockIdx.x];
-    for (int t = threadIdx.x; t < 257; t += 256) {
-        const long long j = j0 + t;
-        s_off[t] = j < nv ? emit_off[j] : 0xFFFFFFFFu;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        const long long j = j0 + c * kEmitThreads + t;
+        s_off[c * kEmitThreads + t] = j < nv ? emit_off[j] : 0xFFFFFFFFu;
     }
     __syncthreads();
-    const long long k = k0 + threadIdx.x;
-    if (k >= keff) return;
-    int lo = 0, hi = 256;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((long long)s_off[mid] <= k) lo = mid;
-        else hi = mid - 1;
+    // pairs starting at or beyond the workgroup's last slot are not needed
+    const long long kend = k0 + S < keff ? k0 + S : keff;
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        const int l = c * kEmitThreads + t;
+        if ((long long)s_off[l] < kend) {
+            const uint32_t q = depth_vals[j0 + l];
+            const int b = view_of_pair(vt, q);
+            const float4* rec = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
+            const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+            int tx0 = 0, ty0 = 0, tx1 = 0, ty1 = 0;
+            tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1);
+            s_q[l] = q;
+            s_first[l] = (uint32_t)(vt.tile_base[b] + ty0 * vt.ntx[b] + tx0);
+            s_w[l] = (uint32_t)(tx1 - tx0 + 1);
+            s_pitch[l] = (uint32_t)vt.ntx[b];
+        }
     }
-    const long long r = k - (long long)s_off[lo];
-    const uint32_t q = depth_vals[j0 + lo];
-    const int b = view_of_pair(vt, q);
-    const float4* rec = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
-    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-    int tx0 = 0, ty0 = 0, tx1 = 0, ty1 = 0;
-    tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1);
-    const int w = tx1 - tx0 + 1;
-    const int tx = tx0 + (int)(r % w), ty = ty0 + (int)(r / w);
-    tile_keys[k] = (uint32_t)(vt.tile_base[b] + ty * vt.ntx[b] + tx);
-    tile_vals[k] = q;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        const long long k = k0 + c * kEmitThreads + t;
+        if (k >= keff) break;
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((long long)s_off[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t r = (uint32_t)(k - (long long)s_off[lo]);
+        const uint32_t w = s_w[lo];
+        const uint32_t row = r / w;
+        tile_keys[k] = s_first[lo] + row * s_pitch[lo] + (r - row * w);
+        tile_vals[k] = s_q[lo];
+    }
 }
 
 __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* counters, long long n_max,
@@ -119,25 +119,27 @@ void launch_count_from_records(const ViewTable& vt, const float* records, const 
 
 int launch_binning(BinArgs& a, hipStream_t s) {
     const long long Q = a.n_pairs;
-    const unsigned qgrid = (unsigned)((Q + 255) / 256 > 0 ? (Q + 255) / 256 : 1);
     // 1. visible pairs, compacted in pair order with their depth keys
     launch_scan_compact(a.pair_count, a.pair_z, Q, a.counters + CNT_V, a.depth_keys[0], a.depth_vals[0],
                         a.scan_tmp, s);
     // 2. stable depth sort of the visible pairs
-    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.depth_grid, a.sort_tmp, s);
+    //    (its last pass also lays out the pairs' tile counts in depth order, in emit_off)
+    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.depth_grid, a.sort_tmp, s,
+                              a.pair_count, a.emit_off);
     const uint32_t* dvals = a.depth_vals[r];
-    // 3. intersection offsets in depth order, total K, overflow flag
-    launch_scan(a.pair_count, dvals, false, a.emit_off, Q, a.counters + CNT_V, a.counters + CNT_K,
-                a.scan_tmp, s);
-    hipLaunchKernelGGL(finalize_counts_kernel, dim3(1), dim3(1), 0, s, a.counters, a.capacity);
+    // 3. intersection offsets in depth order (in place), total K, overflow flag, first pair
+    //    of each emission workgroup
+    launch_emit_scan(a.emit_off, nullptr, a.emit_off, Q, a.counters + CNT_V, a.counters, a.capacity,
+                     a.block_first, a.scan_tmp, s);
     // 4. emit (tile id, pair id) in depth order into the buffer from which an even/odd
     //    number of tile-sort passes ends in final_vals
     const int tp = sort_passes(a.tile_bits);
     const int first = (a.final_vals == a.tile_vals[0]) ? (tp % 2) : 1 - (tp % 2);
     const unsigned kgrid = (unsigned)((a.capacity + 255) / 256 > 0 ? (a.capacity + 255) / 256 : 1);
-    hipLaunchKernelGGL(block_first_kernel, dim3(qgrid), dim3(256), 0, s, a.pair_count, dvals, a.emit_off,
-                       a.counters, a.capacity, Q, a.block_first);
-    hipLaunchKernelGGL(emit_kernel, dim3(kgrid), dim3(256), 0, s, a.vt, a.records, dvals, a.emit_off,
+    const unsigned egrid = (unsigned)((a.capacity + kEmitSlots - 1) / kEmitSlots > 0
+                                          ? (a.capacity + kEmitSlots - 1) / kEmitSlots
+                                          : 1);
+    hipLaunchKernelGGL(emit_kernel, dim3(egrid), dim3(kEmitThreads), 0, s, a.vt, a.records, dvals, a.emit_off,
                        a.block_first, a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first]);
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};

@@ -332,6 +332,17 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
                  long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
                  hipStream_t s);
 
+// Output slots per emission workgroup.
+constexpr int kEmitSlots = 1024;
+
+// Exclusive scan of counts[order[i]] (counts[i] when order is null; out may then be
+// counts itself) over i < *n_dev into out, for the intersection
+// emission: also sets counters[CNT_K / CNT_OVERFLOW / CNT_KEFF] against `capacity` and, for
+// each kEmitSlots-slot emission workgroup below capacity, the item owning its first slot.
+void launch_emit_scan(const uint32_t* counts, const uint32_t* order, uint32_t* out, long long n_max,
+                      const uint32_t* n_dev, uint32_t* counters, long long capacity, uint32_t* block_first,
+                      ScanTemp tmp, hipStream_t s);
+
 // Order-preserving compaction: (payload[i], i) for every i < n with src[i] != 0, count to
 // *total.
 void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
@@ -348,9 +359,11 @@ int sort_passes(int bits);
 long long sort_hist_entries(int grid);
 long long sort_rowtot_entries();
 // keys/vals: [0] = input, [1] = other buffer; returns index of the buffer holding the
-// result (0 or 1).
+// result (0 or 1).  With gather_out, the last pass also writes gather_out[i] =
+// gather_src[sorted value i].
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
-                      int bits, int grid, SortTemp tmp, hipStream_t s);
+                      int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src = nullptr,
+                      uint32_t* gather_out = nullptr);
 
 struct BinArgs {
     ViewTable vt;
@@ -363,7 +376,7 @@ struct BinArgs {
     uint32_t* depth_keys[2]; // [n_pairs]
     uint32_t* depth_vals[2];
     uint32_t* emit_off;      // [n_pairs] scan of tile counts in depth order
-    uint32_t* block_first;   // [capacity / 256 + 1] first depth-ordered pair of each emit workgroup
+    uint32_t* block_first;   // [capacity / kEmitSlots + 1] first depth-ordered pair of each emit workgroup
     uint32_t* tile_keys[2];  // [capacity]
     uint32_t* tile_vals[2];
     uint32_t* ranges;        // [n_tiles][2]

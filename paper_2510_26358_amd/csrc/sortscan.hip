@@ -187,6 +187,89 @@ void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long
                        tmp.block_sums, keys, vals);
 }
 
+// Scan of the tile counts in depth order (value i = counts[order[i]], i < *n_dev) that also
+// publishes the intersection total: counters[CNT_K] = K, counters[CNT_OVERFLOW] = K >
+// capacity, counters[CNT_KEFF] = min(K, capacity).
+__global__ __launch_bounds__(kScanThreads) void emit_blocksums_kernel(uint32_t* block_sums, long long nb,
+                                                                      uint32_t* counters, long long capacity) {
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    uint32_t carry = 0;
+    for (long long base = 0; base < nb; base += kScanTile) {
+        uint32_t v[kScanItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            long long i = base + (long long)threadIdx.x * kScanItems + k;
+            v[k] = i < nb ? block_sums[i] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
+        uint32_t run = carry + incl - s;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            long long i = base + (long long)threadIdx.x * kScanItems + k;
+            if (i < nb) block_sums[i] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const bool over = (long long)carry > capacity;
+        counters[CNT_K] = carry;
+        counters[CNT_OVERFLOW] = over ? 1u : 0u;
+        counters[CNT_KEFF] = over ? (uint32_t)capacity : carry;
+    }
+}
+
+// Apply phase: out[i] = offset of item i; for every multiple m of kEmitSlots inside item
+// i's range [out[i], out[i] + value) with m < capacity, block_first[m / kEmitSlots] = i (the
+// item owning the first slot of that emission workgroup; every value is >= 1).
+__global__ __launch_bounds__(kScanThreads) void emit_apply_kernel(
+    const uint32_t* counts, const uint32_t* order, uint32_t* out, long long n_max, const uint32_t* n_dev,
+    const uint32_t* block_sums, long long capacity, uint32_t* block_first) {
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    const long long n = live_count(n_max, n_dev);
+    const long long base = (long long)blockIdx.x * kScanTile;
+    if (base >= n) return;  // uniform per block
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        long long i = base + (long long)threadIdx.x * kScanItems + k;
+        v[k] = i < n ? (order ? counts[order[i]] : counts[i]) : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
+    uint32_t run = block_sums[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        long long i = base + (long long)threadIdx.x * kScanItems + k;
+        if (i < n) {
+            out[i] = run;  // out may alias counts: this thread has read its items
+            const long long e = (long long)run + v[k];
+            for (long long m = ((long long)run + kEmitSlots - 1) / kEmitSlots * kEmitSlots; m < e && m < capacity;
+                 m += kEmitSlots)
+                block_first[m / kEmitSlots] = (uint32_t)i;
+        }
+        run += v[k];
+    }
+}
+
+void launch_emit_scan(const uint32_t* counts, const uint32_t* order, uint32_t* out, long long n_max,
+                      const uint32_t* n_dev, uint32_t* counters, long long capacity, uint32_t* block_first,
+                      ScanTemp tmp, hipStream_t s) {
+    long long nb = scan_blocks(n_max);
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, order, false,
+                       n_max, n_dev, tmp.block_sums);
+    hipLaunchKernelGGL(emit_blocksums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp.block_sums, nb, counters,
+                       capacity);
+    hipLaunchKernelGGL(emit_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, order, out, n_max,
+                       n_dev, tmp.block_sums, capacity, block_first);
+}
+
 void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32_t* out,
                  long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
                  hipStream_t s) {
@@ -328,7 +411,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_rowscan_kernel(uint32_t* h
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
     long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
-    const uint32_t* rowtot, int grid) {
+    const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out) {
     __shared__ uint32_t run[256];                             // global cursor per digit
     __shared__ uint32_t cnt[kSortItems][kSortWaves][256];     // counts, then rank bases
     __shared__ uint32_t tstart[256];                          // digit start inside the tile
@@ -399,8 +482,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
                 const uint32_t key = skey[p];
                 const uint32_t d = (key >> shift) & mask;
                 const uint32_t dst = run[d] + (uint32_t)p - tstart[d];
+                const uint32_t val = sval[p];
                 keys_out[dst] = key;
-                vals_out[dst] = sval[p];
+                vals_out[dst] = val;
+                if (gather_out) gather_out[dst] = gather_src[val];
             }
         }
         __syncthreads();
@@ -409,7 +494,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 }
 
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
-                      int bits, int grid, SortTemp tmp, hipStream_t s) {
+                      int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src,
+                      uint32_t* gather_out) {
     const int passes = sort_passes(bits);
     if (passes == 0) return 0;
     const int dbits = (bits + passes - 1) / passes;
@@ -421,7 +507,8 @@ int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, con
                            shift, db, tmp.hist, grid);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3(256), dim3(kSortThreads), 0, s, tmp.hist, tmp.rowtot, grid);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
-                           keys[1 - cur], vals[1 - cur], n_max, n_dev, shift, db, tmp.hist, tmp.rowtot, grid);
+                           keys[1 - cur], vals[1 - cur], n_max, n_dev, shift, db, tmp.hist, tmp.rowtot, grid,
+                           p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr);
         cur = 1 - cur;
     }
     return cur;
