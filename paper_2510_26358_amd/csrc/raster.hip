@@ -213,18 +213,20 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                 // r1.w = log2(alpha_min / o): below it alpha cannot reach alpha_min
                 const bool keep = p2 <= 0.f && p2 >= r1.w && alpha >= amin;
                 if (keep) {
-                    const float4 rc = r.m;
-                    const float tn = Tr[k] * (1.f - alpha);
-                    const bool stop = tn < tmin;
-                    const float w = stop ? 0.f : alpha * Tr[k];
-                    C0[k] += w * rc.y;
-                    C1[k] += w * rc.z;
-                    C2[k] += w * rc.w;
-                    D[k] += w * r1.z;
-                    A[k] += w;
-                    Tr[k] = stop ? Tr[k] : tn;
-                    last[k] = stop ? last[k] : e - start + 1;
-                    cx[k] = stop ? kStopped : cx[k];
+                    // stop (once per pixel) before a Gaussian that would take T below t_min
+                    const bool go = Tr[k] * (1.f - alpha) >= tmin;
+                    cx[k] += go ? 0.f : kStopped;  // +inf marks the pixel stopped
+                    if (go) {
+                        const float4 rc = r.m;
+                        const float w = alpha * Tr[k];
+                        C0[k] += w * rc.y;
+                        C1[k] += w * rc.z;
+                        C2[k] += w * rc.w;
+                        D[k] += w * r1.z;
+                        A[k] += w;
+                        Tr[k] = __builtin_fmaf(-alpha, Tr[k], Tr[k]);  // T (1 - alpha), one rounding
+                        last[k] = e - start + 1;
+                    }
                 }
             }
         }
