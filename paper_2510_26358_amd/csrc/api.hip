@@ -58,7 +58,7 @@ struct Layout {
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
     // bwd ws
-    size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_total;
+    size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_vis, b_total;
     long long n_partials;
 };
 
@@ -160,8 +160,9 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
     L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
     L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
-    L.b_pose_part = o; o = align_up(o + (size_t)(project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
+    L.b_pose_part = o; o = align_up(o + (size_t)2 * (project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
                                          views->n_views * 6 * 4);
+    L.b_vis = o; o = align_up(o + (size_t)(n > 0 ? n : 1) * 4);
     L.b_total = o;
     return AGS_OK;
 }
@@ -554,6 +555,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.sh = g->sh;
         pa.cams = cams;
         pa.pair_count = at<uint32_t>(saved, L.s_pair_count);
+        pa.records = at<float>(saved, L.s_records);
         pa.grad2d = grad2d;
         pa.g_means = grads->means;
         pa.g_log_scales = grads->log_scales;
@@ -563,6 +565,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.g_pose = grads->pose;
         pa.accumulate = grads->accumulate;
         pa.pose_partials = at<float>(ws, L.b_pose_part);
+        pa.vis_mask = at<uint32_t>(ws, L.b_vis);
         launch_project_bwd(pa, s);
     }
     if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);

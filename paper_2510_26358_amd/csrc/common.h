@@ -197,11 +197,6 @@ __device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, 
 }
 
 // Wave-wide sum of one float (64 lanes); every lane gets the total.
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -216,6 +211,20 @@ __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 64-lane wave, returned in every lane: lane halves and row pairs through the
+// gfx950 lane swaps, then rotations inside each 16-lane row.
+__device__ __forceinline__ float wave_sum(float v) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    v += dpp_mov<0x128>(v);  // row_ror:8
+    v += dpp_mov<0x124>(v);  // row_ror:4
+    v += dpp_mov<0x122>(v);  // row_ror:2
+    v += dpp_mov<0x121>(v);  // row_ror:1
+    return v;
 }
 
 __device__ __forceinline__ float wave_transpose_sum16(const float (&v)[16]) {
@@ -454,9 +463,11 @@ struct ProjectBwdArgs {
     const float *means, *log_scales, *quats, *logits, *sh;
     const ags_camera* cams;
     const uint32_t* pair_count;
-    float* grad2d;  // read; slots 6..8 overwritten with the clamp-masked colour adjoint
+    const float* records;   // the forward's records (stored colour: the clamp mask)
+    const float* grad2d;
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
-    float* pose_partials;  // [project_bwd_blocks(n)][n_views][6]
+    float* pose_partials;  // [2 project_bwd_blocks(n)][n_views][6]: geometry, then colour
+    uint32_t* vis_mask;    // [n]: views keeping each Gaussian (geometry kernel -> colour kernel)
     int accumulate;
 };
 int project_bwd_blocks(int n);

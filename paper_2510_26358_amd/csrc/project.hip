@@ -11,6 +11,10 @@
 //   (the box outside which alpha < 1/255), the tile rectangle and its tile count.
 // Culled pairs (z < z_near, det <= 0, o < alpha_min, empty rectangle) get count 0 and no
 // record.
+// The SH coefficients (48 of the 59 floats at degree 3) are read once per Gaussian that
+// some view keeps: a first pass over the views writes the geometry part of each record, a
+// second pass over the views that keep the Gaussian evaluates the colour.  (Reading them in
+// the view loop fetched each cache line once per view.)
 #include "common.h"
 
 namespace ags {
@@ -44,6 +48,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
     const float S22 = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
     const float lnterm = 2.f * __logf(255.f * o);
 
+    uint32_t vis = 0;  // views that keep this Gaussian (at most 32)
     for (int b = 0; b < vt.n_views; ++b) {
         if (i < vt.g_begin[b] || i >= vt.g_end[b]) continue;
         const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
@@ -86,33 +91,50 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
                 int tx0, ty0, tx1, ty1;
                 if (tile_rect(u, v, ex, ey, W, H, vt.tile, tx0, ty0, tx1, ty1)) {
                     cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-                    // camera centre C = -R^T t; direction d = (mu - C) / |mu - C|
-                    const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
-                    const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
-                    const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
-                    float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
-                    const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
-                    dx *= il; dy *= il; dz *= il;
-                    float Y[16];
-                    sh_basis(DEG, dx, dy, dz, Y);
-                    // coefficients are streamed (a second visible view hits the cache)
-                    const float* shp = opaque_ptr(a.sh);
-                    float col[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) col[c] += Y[k] * sh_row(shp, n, k * 3 + c)[(uint32_t)i];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) col[c] = fmaxf(col[c] + 0.5f, 0.f);
                     float4* rec = reinterpret_cast<float4*>(a.records + q * kRecFloats);
                     rec[0] = make_float4(u, v, cc * idet, -cb * idet);
                     rec[1] = make_float4(ca * idet, o, z, ex);
-                    rec[2] = make_float4(ey, col[0], col[1], col[2]);
+                    a.records[q * kRecFloats + 8] = ey;
                     a.pair_z[q] = __float_as_uint(z);
+                    vis |= 1u << b;
                 }
             }
         }
         a.pair_count[q] = cnt;
+    }
+    if (vis == 0u) return;
+
+    // colour: the coefficients once (the lanes of the wave that need them load together),
+    // then each view that keeps the Gaussian
+    float f[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[k][c] = sh_row(a.sh, n, k * 3 + c)[(uint32_t)i];
+    while (vis) {
+        const int b = __builtin_ctz(vis);
+        vis &= vis - 1u;
+        const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
+        const ags_camera cam = a.cams[b];
+        const float* R = cam.R;
+        // camera centre C = -R^T t; direction d = (mu - C) / |mu - C|
+        const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
+        const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
+        const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
+        float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+        const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= il; dy *= il; dz *= il;
+        float Y[16];
+        sh_basis(DEG, dx, dy, dz, Y);
+        float col[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) col[c] += Y[k] * f[k][c];
+        float* rc = a.records + q * kRecFloats + 9;
+        rc[0] = fmaxf(col[0] + 0.5f, 0.f);
+        rc[1] = fmaxf(col[1] + 0.5f, 0.f);
+        rc[2] = fmaxf(col[2] + 0.5f, 0.f);
     }
 }
 

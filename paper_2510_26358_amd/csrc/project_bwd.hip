@@ -3,19 +3,23 @@
 //
 // One thread per Gaussian loops over the views that see it (the same splat set is shared
 // by all cameras, so its gradient is the sum over views), reads the pair's ten 2D adjoints
-// (u, v, conic a b c, opacity, rgb, depth), recomputes the forward quantities and chains:
+// (u, v, conic a b c, opacity, depth), recomputes the forward quantities and chains:
 //   conic -> Sigma':     G' = -K G_K K, G_K = [[ga, gb/2], [gb/2, gc]]
 //   Sigma' = T Sigma T^T with T = J R_b:  G_Sigma += T^T G' T,  G_T = 2 G' T Sigma
 //   T -> J -> x_c (x/z, y/z clamp: zero through the clamped coordinate), (u, v) -> x_c,
-//   depth z -> x_c; colour: Y(d) for the coefficients, grad Y projected on the sphere for
-//   the direction d = (mu - C_b) / |mu - C_b|;  mu <- R_b^T g_xc + direction term.
+//   depth z -> x_c;  mu <- R_b^T g_xc.
 // Pose, left perturbation W_b <- Exp(delta) W_b with delta = (rho, phi):
-//   g_rho += g_xc + R_b g_dir (the camera centre moves by -R_b^T rho),
-//   g_phi += x_c x g_xc + (N_12 - N_21, N_20 - N_02, N_01 - N_10), N = R_b G_T^T J.
-// The per-view pose sums are reduced over the wave (transposing butterfly), then over the
-// workgroup in LDS, into one partial per workgroup and view; a second kernel adds the
-// partials in a fixed order (deterministic, and no contention on the 6 B floats).  Shared-Gaussian terms (Sigma -> scale, rotation;
-// opacity -> logit) are chained once after the view loop.
+//   g_rho += g_xc,  g_phi += x_c x g_xc + (N_12 - N_21, N_20 - N_02, N_01 - N_10),
+//   N = R_b G_T^T J.
+// The colour part runs in a second kernel that reads the SH coefficients once per
+// Gaussian: the clamp-masked colour adjoint (the mask is the forward's stored colour > 0),
+// Y(d) for the coefficients, and grad Y projected on the sphere for the direction
+// d = (mu - C_b) / |mu - C_b|, which adds to mu and, through the camera centre moving by
+// -R_b^T rho, g_rho += R_b g_dir.
+// The per-view pose sums are reduced over the wave, then over the workgroup in LDS, into
+// one partial per workgroup and view (both kernels); a third kernel adds the partials in a
+// fixed order (deterministic, and no contention on the 6 B floats).  Shared-Gaussian terms
+// (Sigma -> scale, rotation; opacity -> logit) are chained once after the view loop.
 #include "common.h"
 
 namespace ags {
@@ -62,11 +66,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
+    uint32_t vmask = 0;  // views keeping this Gaussian, for the colour kernel
 
     for (int b = 0; b < vt.n_views; ++b) {
         const bool in_range = active && i >= vt.g_begin[b] && i < vt.g_end[b];
         const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
         const bool vis = in_range && a.pair_count[q] != 0u;
+        vmask |= vis ? 1u << b : 0u;
         float pose[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) pose[k] = 0.f;
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             // slots 0..4 hold pixel moments of dL/dpower = o h (h = dL/do per pixel) without
             // the factor o: sum h dx, h dy, h dx^2, h dx dy, h dy^2 (dx, dy = centre - pixel)
             const float M1 = o * g2[0], M2 = o * g2[1], M3 = o * g2[2], M4 = o * g2[3], M5 = o * g2[4];
-            const float g_o = g2[5], g_r = g2[6], g_g = g2[7], g_bl = g2[8], g_zd = g2[9];
+            const float g_o = g2[5], g_zd = g2[9];
             const ags_camera cam = opaque_ptr(a.cams)[b];
             const float* R = cam.R;
             const float x = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
@@ -159,61 +165,15 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             } else {
                 gz += cam.fy * tyz * rz2 * GJ[1][2];
             }
-            // colour
-            const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
-            const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
-            const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
-            float dvx = mx - Cx, dvy = my - Cy, dvz = mz - Cz;
-            const float il = rsqrtf(dvx * dvx + dvy * dvy + dvz * dvz);
-            const float dx = dvx * il, dy = dvy * il, dz = dvz * il;
-            float Y[16];
-            sh_basis(DEG, dx, dy, dz, Y);
-            const float grgb[3] = {g_r, g_g, g_bl};
-            // One pass over the coefficients per channel gives the raw colour and its
-            // gradient in the direction, G_c = sum_k f_kc grad Y_k; then g_dir = sum_c gcol_c G_c.
-            const float* shp = opaque_ptr(a.sh);
-            float raw[3], G[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float w[16];
-#pragma unroll
-                for (int k = 0; k < K; ++k) w[k] = sh_row(shp, n, k * 3 + c)[(uint32_t)i];
-                float acc = 0.5f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) acc += Y[k] * w[k];
-                raw[c] = acc;
-                sh_grad_dot(DEG, dx, dy, dz, w, G[c]);
-            }
-            float gcol[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gcol[c] = raw[c] >= 0.f ? grgb[c] : 0.f;
-            // the clamp-masked colour adjoint, for the SH-coefficient pass
-            float* g2w = opaque_ptr(a.grad2d) + q * kGrad2dStride;
-            g2w[6] = gcol[0];
-            g2w[7] = gcol[1];
-            g2w[8] = gcol[2];
-            float gdir[3] = {0.f, 0.f, 0.f};
-            if (DEG > 0) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    gdir[0] += gcol[c] * G[c][0];
-                    gdir[1] += gcol[c] * G[c][1];
-                    gdir[2] += gcol[c] * G[c][2];
-                }
-                const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
-                gdir[0] = (gdir[0] - dd * dx) * il;
-                gdir[1] = (gdir[1] - dd * dy) * il;
-                gdir[2] = (gdir[2] - dd * dz) * il;
-            }
             // mean
-            gmu[0] += R[0] * gx + R[3] * gy + R[6] * gz + gdir[0];
-            gmu[1] += R[1] * gx + R[4] * gy + R[7] * gz + gdir[1];
-            gmu[2] += R[2] * gx + R[5] * gy + R[8] * gz + gdir[2];
+            gmu[0] += R[0] * gx + R[3] * gy + R[6] * gz;
+            gmu[1] += R[1] * gx + R[4] * gy + R[7] * gz;
+            gmu[2] += R[2] * gx + R[5] * gy + R[8] * gz;
             go += g_o;
             // pose
-            pose[0] = gx + R[0] * gdir[0] + R[1] * gdir[1] + R[2] * gdir[2];
-            pose[1] = gy + R[3] * gdir[0] + R[4] * gdir[1] + R[5] * gdir[2];
-            pose[2] = gz + R[6] * gdir[0] + R[7] * gdir[1] + R[8] * gdir[2];
+            pose[0] = gx;
+            pose[1] = gy;
+            pose[2] = gz;
             pose[3] = (y * gz - z * gy) + (N12 - N21);
             pose[4] = (z * gx - x * gz) + (N20 - N02);
             pose[5] = (x * gy - y * gx) + (N01 - N10);
@@ -231,6 +191,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3];
     }
     if (!active) return;
+    a.vis_mask[i] = vmask;
 
     // Sigma = M M^T, M = Rq diag(s): G_M = 2 G_Sigma M (G_Sigma symmetrised)
     float Rq[9];
@@ -285,50 +246,124 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     }
 }
 
-// SH-coefficient adjoint: dL/df_kc = sum over visible views of Y_k(d_b) gcol_b,c, with
-// gcol the clamp-masked colour adjoint the geometry pass left in the pair's slots 6..8.
-// One thread per Gaussian; the K x 3 sums stay in registers and are written once.
+// Colour adjoint through the SH evaluation: dL/df_kc = sum over the views keeping the
+// Gaussian of Y_k(d_b) gcol_b,c, with gcol the colour adjoint of the pair masked where the
+// forward clamped the colour at 0 (stored colour == 0); and the direction term
+// g_dir = P_d (sum_c gcol_c sum_k f_kc grad Y_k(d)) / |mu - C_b| (P_d the projection on the
+// tangent plane of the unit sphere), added to dL/dmu and, as R_b g_dir, to the view's
+// dL/drho.  One thread per Gaussian; its K x 3 coefficients are read once, the K x 3 sums
+// stay in registers and are written once.
 template <int DEG>
 __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    const bool active = i < a.n;
     const int n = a.n;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const ViewTable& vt = a.vt;
-    const float mx = a.means[i], my = a.means[n + i], mz = a.means[2 * n + i];
+    __shared__ float spose[kMaxViews][3][4];
+    // second half of the partials: this kernel's grid equals the geometry kernel's
+    float* partials = a.pose_partials + (long long)gridDim.x * vt.n_views * 6;
+
+    float mx = 0.f, my = 0.f, mz = 0.f;
+    uint32_t vis = 0;
+    if (active) {
+        mx = a.means[i]; my = a.means[n + i]; mz = a.means[2 * n + i];
+        vis = a.vis_mask[i];
+    }
+    float f[K][3];
+    if (DEG > 0 && vis) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[k][c] = sh_row(a.sh, n, k * 3 + c)[(uint32_t)i];
+    }
     float acc[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.f;
+    float gm[3] = {0.f, 0.f, 0.f};
     for (int b = 0; b < vt.n_views; ++b) {
-        if (i < vt.g_begin[b] || i >= vt.g_end[b]) continue;
-        const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
-        if (a.pair_count[q] == 0u) continue;
-        const float* g2 = a.grad2d + q * kGrad2dStride;
-        const float gc0 = g2[6], gc1 = g2[7], gc2 = g2[8];
-        const ags_camera cam = a.cams[b];
-        const float* R = cam.R;
-        const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
-        const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
-        const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
-        float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
-        const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= il; dy *= il; dz *= il;
-        float Y[16];
-        sh_basis(DEG, dx, dy, dz, Y);
+        const bool on = (vis >> b) & 1u;
+        float pr[3] = {0.f, 0.f, 0.f};
+        if (on) {
+            const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
+            // both reads issued together (vector loads), then the mask
+            const float4 rc = reinterpret_cast<const float4*>(a.records + q * kRecFloats)[2];  // ey, r, g, b
+            const float2* g2 = reinterpret_cast<const float2*>(a.grad2d + q * kGrad2dStride);
+            const float2 g67 = g2[3], g89 = g2[4];
+            const float gcol[3] = {rc.y > 0.f ? g67.x : 0.f, rc.z > 0.f ? g67.y : 0.f, rc.w > 0.f ? g89.x : 0.f};
+            const ags_camera cam = a.cams[b];
+            const float* R = cam.R;
+            const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
+            const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
+            const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
+            float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+            const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= il; dy *= il; dz *= il;
+            float Y[16];
+            sh_basis(DEG, dx, dy, dz, Y);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            acc[k][0] += Y[k] * gc0;
-            acc[k][1] += Y[k] * gc1;
-            acc[k][2] += Y[k] * gc2;
+            for (int k = 0; k < K; ++k) {
+                acc[k][0] += Y[k] * gcol[0];
+                acc[k][1] += Y[k] * gcol[1];
+                acc[k][2] += Y[k] * gcol[2];
+            }
+            if (DEG > 0) {
+                // sum_c gcol_c grad(sum_k f_kc Y_k) = grad(sum_k w_k Y_k), w_k = sum_c gcol_c f_kc
+                float w[16], gdir[3];
+#pragma unroll
+                for (int k = 0; k < K; ++k) w[k] = gcol[0] * f[k][0] + gcol[1] * f[k][1] + gcol[2] * f[k][2];
+                sh_grad_dot(DEG, dx, dy, dz, w, gdir);
+                const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
+                gdir[0] = (gdir[0] - dd * dx) * il;
+                gdir[1] = (gdir[1] - dd * dy) * il;
+                gdir[2] = (gdir[2] - dd * dz) * il;
+                gm[0] += gdir[0];
+                gm[1] += gdir[1];
+                gm[2] += gdir[2];
+                pr[0] = R[0] * gdir[0] + R[1] * gdir[1] + R[2] * gdir[2];
+                pr[1] = R[3] * gdir[0] + R[4] * gdir[1] + R[5] * gdir[2];
+                pr[2] = R[6] * gdir[0] + R[7] * gdir[1] + R[8] * gdir[2];
+            }
+        }
+        if (DEG > 0) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+            if (__ballot(on) != 0ull) {
+                s0 = wave_sum(pr[0]);
+                s1 = wave_sum(pr[1]);
+                s2 = wave_sum(pr[2]);
+            }
+            if (lane == 0) {
+                spose[b][0][wave] = s0;
+                spose[b][1][wave] = s1;
+                spose[b][2][wave] = s2;
+            }
         }
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < vt.n_views * 6; t += 256) {
+        const int b = t / 6, k = t % 6;
+        partials[((long long)blockIdx.x * vt.n_views + b) * 6 + k] =
+            (DEG > 0 && k < 3) ? spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3] : 0.f;
+    }
+    if (!active) return;
+    if (a.accumulate) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float* dst = sh_row(a.g_sh, n, k * 3 + c) + (uint32_t)i;
-            *dst = a.accumulate ? *dst + acc[k][c] : acc[k][c];
-        }
+            for (int c = 0; c < 3; ++c) sh_row(a.g_sh, n, k * 3 + c)[(uint32_t)i] += acc[k][c];
+    } else {
+        // plain stores (no read of the old values)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh_row(a.g_sh, n, k * 3 + c)[(uint32_t)i] = acc[k][c];
+    }
+    if (DEG > 0) {
+        a.g_means[i] += gm[0];
+        a.g_means[n + i] += gm[1];
+        a.g_means[2 * n + i] += gm[2];
+    }
 }
 
 // Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component).
@@ -361,7 +396,7 @@ void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
         }
     }
     if (nb > 0)
-        hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, nb,
+        hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, 2 * nb,
                            a.vt.n_views, a.g_pose, a.accumulate);
     else if (!a.accumulate)
         launch_fill_f32(a.g_pose, 0.f, 6LL * a.vt.n_views, s);
