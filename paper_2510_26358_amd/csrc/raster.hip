@@ -86,8 +86,10 @@ __device__ __forceinline__ void pixel_of(int t, int k, int& x, int& y) {
 }
 
 // Bit w set when the record's pixel footprint box (the binning rectangle, clamped to the
-// image) intersects wave w's block of the tile at (px0, py0).
-template <int T, int PPT>
+// image) intersects the pixels of wave w in the tile at (px0, py0): its block (BLOCKS) or
+// its rows (row strips).  (The forward does not use it: testing it per entry cost more
+// than the skipped entries saved there.)
+template <int T, int PPT, bool BLOCKS>
 __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float ey, int W, int H, int px0,
                                               int py0) {
     using G = WaveGrid<T, PPT>;
@@ -101,10 +103,19 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
     const int y0 = (int)fminf(fmaxf(fy0 - (float)py0, -1.f), (float)T);
     const int y1 = (int)fminf(fmaxf(fy1 - (float)py0, -1.f), (float)T);
     uint32_t m = 0;
+    if (BLOCKS) {
 #pragma unroll
-    for (int w = 0; w < G::NW; ++w) {
-        const int bx0 = (w % G::COLS) * G::BW, by0 = (w / G::COLS) * G::BH;
-        if (x0 <= bx0 + G::BW - 1 && x1 >= bx0 && y0 <= by0 + G::BH - 1 && y1 >= by0) m |= 1u << w;
+        for (int w = 0; w < G::NW; ++w) {
+            const int bx0 = (w % G::COLS) * G::BW, by0 = (w / G::COLS) * G::BH;
+            if (x0 <= bx0 + G::BW - 1 && x1 >= bx0 && y0 <= by0 + G::BH - 1 && y1 >= by0) m |= 1u << w;
+        }
+    } else {
+        constexpr int RW = 64 * PPT / T;  // rows per wave (>= T: one wave holds the tile)
+        if (x0 <= T - 1 && x1 >= 0) {
+#pragma unroll
+            for (int w = 0; w < G::NW; ++w)
+                if (y0 <= w * RW + RW - 1 && y1 >= w * RW) m |= 1u << w;
+        }
     }
     (void)W;
     (void)H;
@@ -126,17 +137,27 @@ struct alignas(16) SRec {
     uint32_t q, pad[3];
 };
 
-template <int T, int PPT, bool MASK>
+template <int T, int PPT, bool BLOCKS>
 __device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
                                              int px0, int py0, SRec& dst) {
     const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
     constexpr float kLog2e = 1.4426950408889634f;
-    const uint32_t m = MASK ? wave_mask<T, PPT>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : 0xFFFFFFFFu;
+    const uint32_t m = BLOCKS ? wave_mask<T, PPT, BLOCKS>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : ~0u;
     dst.m = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
     dst.g0 = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
     dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
     dst.q = q;
+}
+
+// Makes the record's fields live at this point, so all of its LDS reads are issued together
+// (one round trip) instead of being deferred past the wave-uniform tests that use them.
+__device__ __forceinline__ void use_record(const float4& a, const float4& b) {
+    asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(b.x), "v"(b.y), "v"(b.z), "v"(b.w));
+}
+__device__ __forceinline__ void use_record(const float4& a, const float4& b, const float4& c) {
+    use_record(a, b);
+    asm volatile("" ::"v"(c.x), "v"(c.y), "v"(c.z), "v"(c.w));
 }
 
 // Keeps a value in a vector register from here on, so an LDS address derived from it is
@@ -204,6 +225,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
             if (__ballot(live) == 0ull) break;  // wave-uniform: every pixel has stopped
             const SRec& r = *reinterpret_cast<const SRec*>(sbase + off);
             const float4 r0 = r.g0, r1 = r.g1;
+            use_record(r0, r1);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 // one predicate, one branch: the exp is cheap next to divergent control
@@ -357,9 +379,9 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         in_vgpr(e);
         for (int j = jtop - 1; j >= lo; --j, --e) {
             const SRec& r = srec[e];
-            const float4 rm = r.m;
+            const float4 rm = r.m, r0 = r.g0, r1 = r.g1;
+            use_record(rm, r0, r1);
             if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) continue;  // wave-uniform
-            const float4 r0 = r.g0, r1 = r.g1;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
             // passes (a lane passes exactly when it can keep this Gaussian, up to rounding of
             // the threshold, and keeps are re-tested on alpha below)
