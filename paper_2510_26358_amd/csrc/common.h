@@ -466,7 +466,7 @@ struct ProjectBwdArgs {
     const float* records;   // the forward's records (stored colour: the clamp mask)
     const float* grad2d;
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
-    float* pose_partials;  // [2 project_bwd_blocks(n)][n_views][6]: geometry, then colour
+    float* pose_partials;  // [n_views * 6][2 project_bwd_blocks(n)]: geometry, then colour
     uint32_t* vis_mask;    // [n]: views keeping each Gaussian (geometry kernel -> colour kernel)
     int accumulate;
 };

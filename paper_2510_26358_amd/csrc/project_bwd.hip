@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     __syncthreads();
     for (int t = threadIdx.x; t < vt.n_views * 6; t += 256) {
         const int b = t / 6, k = t % 6;
-        a.pose_partials[((long long)blockIdx.x * vt.n_views + b) * 6 + k] =
+        a.pose_partials[(long long)(b * 6 + k) * (2 * gridDim.x) + blockIdx.x] =
             spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3];
     }
     if (!active) return;
@@ -262,8 +262,8 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const ViewTable& vt = a.vt;
     __shared__ float spose[kMaxViews][3][4];
-    // second half of the partials: this kernel's grid equals the geometry kernel's
-    float* partials = a.pose_partials + (long long)gridDim.x * vt.n_views * 6;
+    // second half of each partials row: this kernel's grid equals the geometry kernel's
+    float* partials = a.pose_partials + gridDim.x;
 
     float mx = 0.f, my = 0.f, mz = 0.f;
     uint32_t vis = 0;
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     __syncthreads();
     for (int t = threadIdx.x; t < vt.n_views * 6; t += 256) {
         const int b = t / 6, k = t % 6;
-        partials[((long long)blockIdx.x * vt.n_views + b) * 6 + k] =
+        partials[(long long)(b * 6 + k) * (2 * gridDim.x) + blockIdx.x] =
             (DEG > 0 && k < 3) ? spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3] : 0.f;
     }
     if (!active) return;
@@ -366,13 +366,24 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     }
 }
 
-// Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component).
+// Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component),
+// whose partials form one contiguous row of n_blocks values.
 __global__ __launch_bounds__(256) void pose_reduce_kernel(const float* partials, int n_blocks, int n_views,
                                                          float* pose, int accumulate) {
     __shared__ float sred[4];
     const int bk = blockIdx.x;  // b * 6 + k
-    float s = 0.f;
-    for (int g = threadIdx.x; g < n_blocks; g += 256) s += partials[(long long)g * n_views * 6 + bk];
+    const float* row = partials + (long long)bk * n_blocks;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int g = threadIdx.x;
+    for (; g + 768 < n_blocks; g += 1024) {
+        s0 += row[g];
+        s1 += row[g + 256];
+        s2 += row[g + 512];
+        s3 += row[g + 768];
+    }
+    for (; g < n_blocks; g += 256) s0 += row[g];
+    float s = (s0 + s1) + (s2 + s3);
+    (void)n_views;
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
     __syncthreads();
