@@ -20,9 +20,12 @@ Compositing at pixel (px, py), centre (px + 0.5, py + 0.5), over *all* surviving
     outputs C + T bg, D (expected depth, unnormalised), A, T_final.
 
 Loss (Sec. III-C), summed over views b:
-    w_l1 / (3 n_b) sum_{p in mask} sum_ch |C - C_gt|
+    w_l1 [(1 - lambda_s) / (3 n_b) sum_{p in mask} sum_ch |C - C_gt|
+          + lambda_s / (3 n_b) sum_{p in mask} sum_ch (1 - ssim_ch(p))]
   + lambda_L / |Omega_b| sum_{u in Omega_b} KL(N(D_L(u), sigma_L^2) || N(mu_u, sigma_u^2)),
-    mu_u = D(u), sigma_u = sigma_L (fixed-variance reading).
+    mu_u = D(u), sigma_u = sigma_L (fixed-variance reading); lambda_s weighs the D-SSIM
+    part of L_3DGS (0: L1 only), ssim the map of `oracle.ssim` over the whole rendered
+    image (zero-padded windows), averaged over the mask.
 
 Gradients: torch float64 autograd through projection and compositing with every discrete
 decision (kept sets, order, stop index, alpha clamp) frozen from the forward pass; the pose
@@ -39,6 +42,7 @@ import torch
 from .geometry import covariance_3d, se3_exp_torch
 from .settings import RenderSettings
 from .sh import real_sh
+from .ssim import ssim_map, window_radius
 
 DT = torch.float64
 
@@ -257,10 +261,27 @@ def render(scene, s: RenderSettings = None, pixels=None, p=None):
     return out
 
 
+def _dilate(cam, pix, r):
+    """Pixels within Chebyshev distance r of `pix` (flat indices), inside the image."""
+    img = np.zeros((cam.height, cam.width), bool)
+    px, py = _pixel_coords(cam, pix)
+    img[py, px] = True
+    out = np.zeros_like(img)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            ys = slice(max(0, dy), cam.height + min(0, dy))
+            yd = slice(max(0, -dy), cam.height + min(0, -dy))
+            xs = slice(max(0, dx), cam.width + min(0, dx))
+            xd = slice(max(0, -dx), cam.width + min(0, -dx))
+            out[yd, xd] |= img[ys, xs]
+    return np.flatnonzero(out.ravel())
+
+
 def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=None,
                    w_l1: float = 1.0, lam: float = 1.0, upstream=None, sign_margin=1e-5,
-                   frozen=None, deltas=None):
-    """Loss of Sec. III-C (L1 part + LiDAR KL term) and its float64 gradients.
+                   frozen=None, deltas=None, ssim_w: float = 0.0):
+    """Loss of Sec. III-C (L1 and D-SSIM parts of L_3DGS + LiDAR KL term) and its float64
+    gradients.
 
     masks: per view flat pixel indices where the L1 term applies (None = whole image).
     lidar: per view dict(pix, depth, sigma) (defaults to scene.lidar); its pixels are
@@ -288,6 +309,8 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
             l1_pix = np.arange(HW) if masks is None or masks[b] is None else np.asarray(masks[b], np.int64)
             lp = np.asarray(lidar[b]["pix"], np.int64) if lidar and len(lidar[b]["pix"]) else np.zeros(0, np.int64)
             eval_pix = np.union1d(l1_pix, lp)
+            if ssim_w > 0.0:  # the SSIM windows of the mask pixels
+                eval_pix = np.union1d(eval_pix, _dilate(cam, l1_pix, window_radius()))
         px, py = _pixel_coords(cam, eval_pix)
         proj = project(p, cam, p["pose_delta"][b], s, scene.sh_degree)
         if frozen is not None:
@@ -309,9 +332,16 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
             if len(l1_pix):
                 tgt = torch.tensor(np.asarray(gt[b], np.float64).reshape(3, -1).T[l1_pix])
                 diff = rgb[sel] - tgt
-                total = total + w_l1 / (3.0 * len(l1_pix)) * diff.abs().sum()
+                total = total + (1.0 - ssim_w) * w_l1 / (3.0 * len(l1_pix)) * diff.abs().sum()
                 close = (diff.detach().abs() < sign_margin).any(1).numpy()
                 amb_pix[sel.numpy()[close]] = True
+                if ssim_w > 0.0:
+                    img = torch.zeros(3, cam.height * cam.width, dtype=DT)
+                    img[:, torch.tensor(eval_pix)] = rgb.T
+                    smap = ssim_map(img.view(3, cam.height, cam.width),
+                                    torch.tensor(np.asarray(gt[b], np.float64)))
+                    s_sel = smap.reshape(3, -1)[:, torch.tensor(l1_pix)]
+                    total = total + ssim_w * w_l1 / (3.0 * len(l1_pix)) * (1.0 - s_sel).sum()
             if lidar and len(lidar[b]["pix"]):
                 li = torch.tensor([pos[int(q)] for q in lidar[b]["pix"]], dtype=torch.long)
                 dl = torch.tensor(np.asarray(lidar[b]["depth"], np.float64))
@@ -333,11 +363,11 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
 
 
 def frozen_objective(scene, decisions, s: RenderSettings = None, masks=None, lidar=None,
-                     gt=None, w_l1=1.0, lam=1.0, upstream=None, deltas=None):
+                     gt=None, w_l1=1.0, lam=1.0, upstream=None, deltas=None, ssim_w=0.0):
     """The same objective as `loss_and_grads` evaluated with given frozen decisions and no
     gradient (used by finite differences)."""
     s = s or RenderSettings()
     with torch.enable_grad():
         r = loss_and_grads(scene, s, masks, lidar, gt, w_l1, lam, upstream, frozen=decisions,
-                           deltas=deltas)
+                           deltas=deltas, ssim_w=ssim_w)
     return r["loss"]
