@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define AGS_ABI_VERSION 1
+#define AGS_ABI_VERSION 2
 #define AGS_MAX_VIEWS 32
 
 enum {
@@ -137,11 +137,13 @@ typedef struct ags_upstream {
     const float* d_alpha;
 } ags_upstream;
 
-/* Fused loss, summed over views b:
- *   w_l1 / (3 n_b) sum_{p in mask_b} sum_c |rgb - gt_rgb|
+/* Fused loss (Sec. III-C: photometric L_3DGS plus L_LiDAR), summed over views b:
+ *   w_l1 [(1 - ssim_weight) / (3 n_b) sum_{p in mask_b} sum_c |rgb - gt_rgb|
+ *         + ssim_weight / (3 n_b) sum_{p in mask_b} sum_c (1 - ssim_c(p))]
  * + lambda_lidar / |Omega_b| sum_{j in Omega_b} KL(N(D_j, s_j^2) || N(depth(p_j), s_j^2))
  * (equal variances: (depth - D_j)^2 / (2 s_j^2)).  n_b = l1_count[b] if mask is given,
- * else W_b H_b; the sign of 0 is 0.  Repeated target pixels simply add their terms. */
+ * else W_b H_b; the sign of 0 is 0.  Repeated target pixels simply add their terms.
+ * ssim_c(p) uses the whole rendered view (zero outside it), also outside the mask. */
 typedef struct ags_loss {
     const float* gt_rgb;          /* device, rgb layout */
     const uint8_t* mask;          /* device [P] (1 = pixel enters the L1 term) or NULL */
@@ -153,6 +155,12 @@ typedef struct ags_loss {
                                      [depth_offsets[b], depth_offsets[b+1]) */
     float w_l1;
     float lambda_lidar;
+    float ssim_weight;            /* lambda of L_3DGS = (1 - lambda) L1 + lambda D-SSIM (Sec. III-C),
+                                     in [0, 1]; 0 = L1 only.  D-SSIM = 1 - SSIM with an 11 x 11
+                                     Gaussian window (sigma 1.5, zero padding), C1 = 0.01^2,
+                                     C2 = 0.03^2, per channel, averaged over the same pixels as
+                                     the L1 term (the whole view, or the mask); both parts carry
+                                     w_l1. */
 } ags_loss;
 
 /* Buffer sizes and the layout of the `saved` buffer (byte offsets), for a batch shape. */

@@ -65,7 +65,7 @@ class Loss(C.Structure):
                 ("l1_count", C.POINTER(C.c_int64)), ("depth_pix", C.c_void_p),
                 ("depth_val", C.c_void_p), ("depth_sigma", C.c_void_p),
                 ("depth_offsets", C.POINTER(C.c_int64)), ("w_l1", C.c_float),
-                ("lambda_lidar", C.c_float)]
+                ("lambda_lidar", C.c_float), ("ssim_weight", C.c_float)]
 
 
 class Sizes(C.Structure):
@@ -85,6 +85,8 @@ class Adam(C.Structure):
                 ("eps", C.c_float)]
 
 
+ABI_VERSION = 2  # include/agsplat.h AGS_ABI_VERSION
+
 _lib = None
 
 
@@ -97,6 +99,9 @@ def load(path: str = LIB_PATH):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                           " (no CPU fallback exists)")
     lib = C.CDLL(path)
+    lib.ags_version.restype = C.c_int
+    if lib.ags_version() != ABI_VERSION:
+        raise ImportError(f"{path} implements ABI {lib.ags_version()}, this binding expects {ABI_VERSION}: rebuild it")
     P = C.POINTER
     vp = C.c_void_p
     lib.ags_version.restype = C.c_int

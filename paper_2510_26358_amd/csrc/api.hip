@@ -25,11 +25,12 @@ enum Stage {
     ST_CLEAR,
     ST_ADAM,
     ST_POSE,
+    ST_SSIM,
     ST_COUNT
 };
 static const char* kStageNames[ST_COUNT] = {"project_fwd", "binning",     "raster_fwd",
                                              "lidar_adjoint", "raster_bwd", "project_bwd",
-                                             "clear",       "adam",        "pose_step"};
+                                             "clear",       "adam",        "pose_step", "ssim"};
 
 struct ags_ctx {
     int device;
@@ -58,8 +59,8 @@ struct Layout {
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
     // bwd ws
-    size_t b_grad2d, b_ddepth, b_partials, b_pose_part, b_vis, b_total;
-    long long n_partials;
+    size_t b_grad2d, b_ddepth, b_dssim, b_partials, b_pose_part, b_vis, b_total;
+    long long n_partials, n_ssim;
 };
 
 int check_views(const ags_views* v) {
@@ -156,9 +157,11 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.f_block_sums = o; o = align_up(o + (size_t)sb * 4);
     L.f_total = o;
     o = 0;
-    L.n_partials = tiles + lidar_blocks(0);  // raster blocks, then LiDAR blocks
+    L.n_ssim = ssim_blocks(vt);
+    L.n_partials = tiles + lidar_blocks(0) + L.n_ssim;  // raster, LiDAR, then D-SSIM blocks
     L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
     L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
+    L.b_dssim = o; o = align_up(o + (size_t)(pix > 0 ? 3 * pix : 1) * 4);
     L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
     L.b_pose_part = o; o = align_up(o + (size_t)2 * (project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
                                          views->n_views * 6 * 4);
@@ -466,6 +469,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     if (loss) {
         if (!fwd || !fwd->rgb || !fwd->depth || !loss->gt_rgb) return AGS_ERR_INVALID_ARG;
         if (loss->mask && !loss->l1_count) return AGS_ERR_INVALID_ARG;
+        if (!(loss->ssim_weight >= 0.f && loss->ssim_weight <= 1.f)) return AGS_ERR_INVALID_ARG;
         if (loss->depth_offsets) {
             if (loss->depth_offsets[0] != 0) return AGS_ERR_INVALID_ARG;
             for (int b = 0; b < views->n_views; ++b)
@@ -485,7 +489,9 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         Scope sc(ctx, ST_CLEAR, s);
         launch_fill_f32(grad2d, 0.f, L.Q * kGrad2dStride, s);
         if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
-        if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, L.n_partials - L.n_tiles, s);
+        if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, lidar_blocks(0), s);
+        if (loss && !(loss->ssim_weight > 0.f))
+            launch_fill_f32(partials + L.n_tiles + lidar_blocks(0), 0.f, L.n_ssim, s);
     }
     RasterBwdArgs ra;
     memset(&ra, 0, sizeof(ra));
@@ -502,10 +508,25 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         ra.rgb = fwd->rgb;
         ra.gt_rgb = loss->gt_rgb;
         ra.mask = loss->mask;
+        const double ls = loss->ssim_weight > 0.f ? (double)loss->ssim_weight : 0.0;
+        SsimArgs sa;
+        memset(&sa, 0, sizeof(sa));
         for (int b = 0; b < views->n_views; ++b) {
             const double nb = loss->mask ? (double)loss->l1_count[b]
                                          : (double)views->width[b] * (double)views->height[b];
-            ra.l1_scale[b] = nb > 0 ? (float)(loss->w_l1 / (3.0 * nb)) : 0.f;
+            ra.l1_scale[b] = nb > 0 ? (float)((1.0 - ls) * loss->w_l1 / (3.0 * nb)) : 0.f;
+            sa.scale[b] = nb > 0 ? (float)(ls * loss->w_l1 / (3.0 * nb)) : 0.f;
+        }
+        if (ls > 0.0) {
+            Scope sc(ctx, ST_SSIM, s);
+            sa.vt = L.vt;
+            sa.rgb = fwd->rgb;
+            sa.gt_rgb = loss->gt_rgb;
+            sa.mask = loss->mask;
+            sa.d_rgb = at<float>(ws, L.b_dssim);
+            sa.partials = partials + L.n_tiles + lidar_blocks(0);
+            launch_ssim(sa, s);
+            ra.d_rgb = sa.d_rgb;
         }
         ra.loss_partials = partials;
         ra.d_depth = n_targets > 0 ? ddepth : nullptr;

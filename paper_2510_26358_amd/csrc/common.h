@@ -428,17 +428,32 @@ struct RasterBwdArgs {
     const float* d_rgb;
     const float* d_depth;
     const float* d_alpha;
-    // loss mode (fused L1 prologue); d_depth then points at the scattered LiDAR adjoint
+    // loss mode (fused L1 prologue); d_depth then points at the scattered LiDAR adjoint and
+    // d_rgb (or null) at the adjoint of the D-SSIM part, both added to the pixel's adjoints
     int loss_mode;
     const float* rgb;
     const float* gt_rgb;
     const uint8_t* mask;
-    float l1_scale[kMaxViews];   // w_l1 / (3 n_b)
+    float l1_scale[kMaxViews];   // (1 - lambda_ssim) w_l1 / (3 n_b)
     float* loss_partials;        // one per block (loss mode)
     float* grad2d;               // [n_pairs][10]
 };
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
 int raster_blocks(const ViewTable& vt);
+
+struct SsimArgs {
+    ViewTable vt;
+    const float* rgb;            // rendered colour (rgb layout)
+    const float* gt_rgb;         // target colour (rgb layout)
+    const uint8_t* mask;         // [P] or null
+    float scale[kMaxViews];      // lambda w_l1 / (3 n_b)
+    float* d_rgb;                // out: adjoint of the D-SSIM part (rgb layout)
+    float* partials;             // out: one loss partial per workgroup (ssim_blocks)
+    int tile_base[kMaxViews + 1];  // filled by the launcher
+    float w[11];                   // window weights, filled by the launcher
+};
+long long ssim_blocks(const ViewTable& vt);
+void launch_ssim(SsimArgs a, hipStream_t s);
 
 struct LidarArgs {
     ViewTable vt;

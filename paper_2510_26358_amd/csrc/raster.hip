@@ -324,6 +324,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                     gC2[k] = d2 > 0.f ? sc : (d2 < 0.f ? -sc : 0.f);
                     loss_part += sc * (fabsf(d0) + fabsf(d1) + fabsf(d2));
                 }
+                if (a.d_rgb) {  // D-SSIM adjoint (already zero outside the mask)
+                    const float* g = a.d_rgb + 3 * tc.pix0;
+                    gC0[k] += g[p];
+                    gC1[k] += g[plane + p];
+                    gC2[k] += g[2 * plane + p];
+                }
                 if (a.d_depth) gD[k] = a.d_depth[gp];
             } else {
                 if (a.d_rgb) {

@@ -128,10 +128,11 @@ class LossTargets:
     depth_offsets: list
     w_l1: float = 1.0
     lambda_lidar: float = 1.0
+    ssim_weight: float = 0.0          # lambda of the D-SSIM part of L_3DGS (0: L1 only)
 
     @classmethod
     def from_scene(cls, scene, views: ViewSpec, device="cuda", masks=None, lidar=None, gt=None,
-                   w_l1=1.0, lambda_lidar=1.0):
+                   w_l1=1.0, lambda_lidar=1.0, ssim_weight=0.0):
         gt = scene.gt_rgb if gt is None else gt
         lidar = scene.lidar if lidar is None else lidar
         flat = np.concatenate([np.asarray(g, np.float32).reshape(-1) for g in gt])
@@ -157,7 +158,7 @@ class LossTargets:
         while len(offs) < views.n_views + 1:
             offs.append(offs[-1])
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
-        return cls(dev(flat), mask_t, counts, dev(pix), dev(val), dev(sig), offs, w_l1, lambda_lidar)
+        return cls(dev(flat), mask_t, counts, dev(pix), dev(val), dev(sig), offs, w_l1, lambda_lidar, ssim_weight)
 
     def c(self):
         self._keep = (_i64(self.l1_count), _i64(self.depth_offsets))
@@ -165,7 +166,7 @@ class LossTargets:
                       self._keep[0], self.depth_pix.data_ptr() if self.depth_pix.numel() else None,
                       self.depth_val.data_ptr() if self.depth_val.numel() else None,
                       self.depth_sigma.data_ptr() if self.depth_sigma.numel() else None,
-                      self._keep[1], float(self.w_l1), float(self.lambda_lidar))
+                      self._keep[1], float(self.w_l1), float(self.lambda_lidar), float(self.ssim_weight))
 
 
 class Buffers:

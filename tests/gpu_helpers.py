@@ -46,9 +46,11 @@ def saved_arrays(buf, views: ViewSpec):
             "tile_keys": keys.astype(np.int64) & 0xFFFFFFFF}
 
 
-def run_loss_backward(scene, ras: Rasterizer, masks=None, w_l1=1.0, lam=1.0, capacity=None):
+def run_loss_backward(scene, ras: Rasterizer, masks=None, w_l1=1.0, lam=1.0, capacity=None, ssim_w=0.0,
+                      gt=None):
     res, (p, cams, views, out, buf) = run_forward(scene, ras, capacity)
-    tg = LossTargets.from_scene(scene, views, masks=masks, w_l1=w_l1, lambda_lidar=lam)
+    tg = LossTargets.from_scene(scene, views, masks=masks, w_l1=w_l1, lambda_lidar=lam, ssim_weight=ssim_w,
+                                gt=gt)
     grads = p.zeros_like()
     pose = torch.zeros(views.n_views, 6, device="cuda")
     loss = torch.zeros(1, device="cuda")
