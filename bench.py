@@ -35,6 +35,10 @@ FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic FLOP per (pixel, Gaussian) pair evaluated (scope table): forward ~20 + 1 exp,
 # backward ~60 + 1 exp; the exp is counted as one FLOP.
 FLOP_PER_PAIR = {"raster_fwd": 21, "raster_bwd": 61}
+# Algorithmic FLOP of the D-SSIM term per pixel and colour channel (no halo recomputation):
+# five window moments by two 11-tap passes (220), s and its three partial derivatives (~40),
+# three 11-tap passes back (132), the final combination (~8).
+SSIM_FLOP_PER_PIXEL_CHANNEL = 400
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -172,6 +176,39 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload)
     return rf, info
 
 
+def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms):
+    """Every stage against its bound from the per-stage HIP-event times: algorithmic bytes
+    (HBM-bound stages) or FLOP (raster) per launch, as listed in the design doc; plus the whole
+    step's algorithmic bytes over its time (the HBM fraction of the step)."""
+    F = 11 + 3 * sh_k
+    byts = {
+        "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V,
+        "binning": 4 * Q + 72 * V + 44 * K,
+        "lidar_adjoint": 16 * n_targets,
+        "project_bwd": 8 * 4 * F * N + 56 * V + 24 * N,
+        "clear": 40 * Q + 4 * P,
+        "raster_fwd": 28 * P,
+        "raster_bwd": 44 * P,
+    }
+    out = {}
+    for name, ms in stage_ms.items():
+        if ms <= 0:
+            continue
+        if name in FLOP_PER_PAIR:
+            a = evals * FLOP_PER_PAIR[name] / (ms * 1e-3) / 1e12
+            out[name] = {"ms": ms, "bound": "alu", "achieved": round(a, 2), "unit": "TFLOP/s",
+                         "frac": round(a / FP32_PEAK_TFLOPS, 3)}
+        elif name in byts:
+            a = byts[name] / (ms * 1e-3) / 1e9
+            out[name] = {"ms": ms, "bound": "hbm", "achieved": round(a, 1), "unit": "GB/s",
+                         "frac": round(a / HBM_PEAK_GBS, 3)}
+    total = sum(byts.values())
+    out["step"] = {"ms": round(step_ms, 4), "bound": "hbm", "algorithmic_bytes": int(total),
+                   "achieved": round(total / (step_ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+                   "frac": round(total / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    return out
+
+
 def cpu_baseline(sc, sample_px=8192, seed=5):
     """The FP64 oracle (unmodified) timed on the host: fwd + bwd of the same loss on a seeded
     sample of view 0's pixels (L1 mask = the sample, LiDAR targets inside it)."""
@@ -211,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
+    ap.add_argument("--ssim", type=float, default=0.2,
+                    help="also time the step with the D-SSIM part of L_3DGS at this weight (0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -302,6 +341,46 @@ def main():
         roof, info = dominant_roofline(prof, views, over_buf, over_buf.sizes, args.steps, p.n,
                                        (p.sh_degree + 1) ** 2, args.workload)
         info["stage_ms"] = stage_ms
+        info["stages"] = stage_rooflines(stage_ms, info["pairs_evaluated"], P, p.n, (p.sh_degree + 1) ** 2,
+                                         over_buf.sizes.n_pairs, info["V"], info["K"],
+                                         int(tg.depth_pix.numel()), t_b * 1e3)
+
+    # the same step with the D-SSIM part of the photometric loss switched on
+    with_ssim = None
+    if args.ssim > 0 and refiner is None:
+        tg.ssim_weight = args.ssim
+        if not args.no_graph:
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            graph_s = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph_s):
+                step()
+            timed_s = graph_s.replay
+        else:
+            timed_s = step
+        t_s = time_steps(timed_s, args.steps, args.warmup)
+        with_ssim = {"ssim_weight": args.ssim, "ms_per_step": round(t_s * 1e3, 4),
+                     "value": round(P / t_s / 1e6, 2), "loss": round(loss.item(), 6)}
+        if not args.no_profile:
+            ras.profile(True)
+            ras.profile_reset()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            pr = ras.profile_read()
+            ras.profile(False)
+            if pr.get("ssim", (0, 0))[1]:
+                ms = pr["ssim"][0] / pr["ssim"][1]
+                achieved = SSIM_FLOP_PER_PIXEL_CHANNEL * 3 * P / (ms * 1e-3) / 1e12
+                with_ssim["ssim_stage_ms"] = round(ms, 4)
+                with_ssim["ssim_roofline"] = {
+                    "bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_PEAK_TFLOPS, 2),
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "work": f"{3 * P} pixel-channels x {SSIM_FLOP_PER_PIXEL_CHANNEL} FLOP"}
+        log(f"[bench] with D-SSIM (weight {args.ssim}): {t_s * 1e3:.3f} ms/step, {P / t_s / 1e6:.1f} Mpixel/s, "
+            f"{with_ssim}")
+        tg.ssim_weight = 0.0
 
     loop = None
     if not args.no_loop and views.n_views > 1 and refiner is None:
@@ -354,6 +433,7 @@ def main():
                    "autotuned": None if tuned is None else tuned["ms"],
                    "visible_pairs": V, "intersections": K},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
+        "with_ssim": with_ssim,
     }
     print(json.dumps(rec), flush=True)
 
