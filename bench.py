@@ -185,7 +185,7 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms):
         "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V,
         "binning": 4 * Q + 72 * V + 44 * K,
         "lidar_adjoint": 16 * n_targets,
-        "project_bwd": 8 * 4 * F * N + 56 * V + 24 * N,
+        "project_bwd": 2 * 4 * F * N + 56 * V + 24 * N,
         "clear": 40 * Q + 4 * P,
         "raster_fwd": 28 * P,
         "raster_bwd": 44 * P,

@@ -26,7 +26,7 @@ constexpr int kSsimTO = 32;                     // output tile edge
 constexpr int kSsimR = 5;                       // window radius
 constexpr int kSsimIn = kSsimTO + 4 * kSsimR;   // 52: inputs with the double halo
 constexpr int kSsimMid = kSsimTO + 2 * kSsimR;  // 42: moments / D with the single halo
-constexpr int kSsimThreads = 256;
+constexpr int kSsimThreads = 512;
 constexpr float kSsimC1 = 0.01f * 0.01f;
 constexpr float kSsimC2 = 0.03f * 0.03f;
 
@@ -40,11 +40,23 @@ long long ssim_blocks(const ViewTable& vt) {
     return 3 * t;
 }
 
+// LDS: the inputs (steps 1-2) share their space with D (steps 3-4), which is why step 5
+// reads x and y of the tile again from global memory (cache hits); 65 KB lets two
+// workgroups share a CU.
+union SsimFront {
+    struct {
+        float x[kSsimIn][kSsimIn], y[kSsimIn][kSsimIn];
+    } in;
+    float d[3][kSsimMid][kSsimMid];
+};
+
 __global__ __launch_bounds__(kSsimThreads) void ssim_kernel(SsimArgs a) {
-    __shared__ float sX[kSsimIn][kSsimIn], sY[kSsimIn][kSsimIn];
+    __shared__ SsimFront front;
     __shared__ float hbuf[5][kSsimIn][kSsimMid];  // row-blurred moments; later the row-blurred D
-    __shared__ float sD[3][kSsimMid][kSsimMid];
     __shared__ float sred[kSsimThreads / 64];
+    auto& sX = front.in.x;
+    auto& sY = front.in.y;
+    auto& sD = front.d;
     const ViewTable& vt = a.vt;
     const int tid = threadIdx.x;
     const int c = blockIdx.y;  // colour channel
@@ -62,14 +74,29 @@ __global__ __launch_bounds__(kSsimThreads) void ssim_kernel(SsimArgs a) {
 #pragma unroll
     for (int k = 0; k < 2 * kSsimR + 1; ++k) w[k] = a.w[k];
 
-    // 1. inputs over [ox - 2R, ox + TO + 2R)^2, zero outside the image
-    for (int i = tid; i < kSsimIn * kSsimIn; i += kSsimThreads) {
-        const int r = i / kSsimIn, q = i % kSsimIn;
-        const int y = oy - 2 * kSsimR + r, x = ox - 2 * kSsimR + q;
-        const bool in = x >= 0 && x < W && y >= 0 && y < H;
-        const long long p = (long long)y * W + x;
-        sX[r][q] = in ? X[p] : 0.f;
-        sY[r][q] = in ? Y[p] : 0.f;
+    // 1. inputs over [ox - 2R, ox + TO + 2R)^2, zero outside the image; all loads issued
+    //    before the first store
+    {
+        constexpr int kN = (kSsimIn * kSsimIn + kSsimThreads - 1) / kSsimThreads;
+        float vx[kN], vy[kN];
+#pragma unroll
+        for (int j = 0; j < kN; ++j) {
+            const int i = tid + j * kSsimThreads;
+            const int r = i / kSsimIn, q = i % kSsimIn;
+            const int y = oy - 2 * kSsimR + r, x = ox - 2 * kSsimR + q;
+            const bool in = i < kSsimIn * kSsimIn && x >= 0 && x < W && y >= 0 && y < H;
+            const long long p = (long long)y * W + x;
+            vx[j] = in ? X[p] : 0.f;
+            vy[j] = in ? Y[p] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kN; ++j) {
+            const int i = tid + j * kSsimThreads;
+            if (i < kSsimIn * kSsimIn) {
+                sX[i / kSsimIn][i % kSsimIn] = vx[j];
+                sY[i / kSsimIn][i % kSsimIn] = vy[j];
+            }
+        }
     }
     __syncthreads();
 
@@ -131,13 +158,14 @@ __global__ __launch_bounds__(kSsimThreads) void ssim_kernel(SsimArgs a) {
             const float A2 = 2.f * (mom[4][o] - mx * my) + kSsimC2;
             const float B1 = mx * mx + my * my + kSsimC1;
             const float B2 = (mom[2][o] - mx * mx) + (mom[3][o] - my * my) + kSsimC2;
-            const float iB = 1.f / (B1 * B2);
+            const float rB1 = __builtin_amdgcn_rcpf(B1), rB2 = __builtin_amdgcn_rcpf(B2);
+            const float iB = rB1 * rB2;
             const float s = A1 * A2 * iB;
             bool on = x >= 0 && x < W && y >= 0 && y < H;
             if (on && a.mask) on = a.mask[vt.pix_base[b] + (long long)y * W + x] != 0;
             const float m = on ? mscale : 0.f;
-            sD[0][r][q] = m * (2.f * my * (A2 - A1) * iB + 2.f * mx * s * (1.f / B2 - 1.f / B1));
-            sD[1][r][q] = m * (-s / B2);
+            sD[0][r][q] = m * (2.f * my * (A2 - A1) * iB + 2.f * mx * s * (rB2 - rB1));
+            sD[1][r][q] = m * (-s * rB2);
             sD[2][r][q] = m * (2.f * A1 * iB);
             if (r >= kSsimR && r < kSsimR + kSsimTO && q >= kSsimR && q < kSsimR + kSsimTO) part += m * (1.f - s);
         }
@@ -145,51 +173,57 @@ __global__ __launch_bounds__(kSsimThreads) void ssim_kernel(SsimArgs a) {
     __syncthreads();
 
     // 4. row pass of m D over the 42 rows onto the 32 tile columns (into hbuf), 8 outputs per item
-    for (int it = tid; it < kSsimMid * 4; it += kSsimThreads) {
-        const int r = it / 4, c0 = (it % 4) * 8;
+    //    (one map per item: 3 x 42 x 4 items)
+    for (int it = tid; it < 3 * kSsimMid * 4; it += kSsimThreads) {
+        const int m = it / (kSsimMid * 4), rem = it % (kSsimMid * 4);
+        const int r = rem / 4, c0 = (rem % 4) * 8;
+        float row[18];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            float row[18];
+        for (int k = 0; k < 18; ++k) row[k] = sD[m][r][c0 + k];
 #pragma unroll
-            for (int k = 0; k < 18; ++k) row[k] = sD[m][r][c0 + k];
+        for (int o = 0; o < 8; ++o) {
+            float acc = 0.f;
 #pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                float acc = 0.f;
-#pragma unroll
-                for (int k = 0; k < 2 * kSsimR + 1; ++k) acc += w[k] * row[o + k];
-                hbuf[m][r][c0 + o] = acc;
-            }
+            for (int k = 0; k < 2 * kSsimR + 1; ++k) acc += w[k] * row[o + k];
+            hbuf[m][r][c0 + o] = acc;
         }
     }
     __syncthreads();
 
-    // 5. column pass onto the tile; combine with x and y
-    for (int it = tid; it < kSsimTO * 4; it += kSsimThreads) {
-        const int q = it % kSsimTO, r0 = (it / kSsimTO) * 8;
-        float g[3][8];
+    // 5. column pass onto the tile; combine with x and y (read again: their LDS now holds D)
+    //    (4 rows per item: 32 x 8 items)
+    for (int it = tid; it < kSsimTO * 8; it += kSsimThreads) {
+        const int q = it % kSsimTO, r0 = (it / kSsimTO) * 4;
+        const int x = ox + q;
+        float xv[4], yv[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int y = oy + r0 + o;
+            const bool in = x < W && y < H;
+            const long long p = (long long)y * W + x;
+            xv[o] = in ? X[p] : 0.f;
+            yv[o] = in ? Y[p] : 0.f;
+        }
+        float g[3][4];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            float col[18];
+            float col[14];
 #pragma unroll
-            for (int k = 0; k < 18; ++k) col[k] = hbuf[m][r0 + k][q];
+            for (int k = 0; k < 14; ++k) col[k] = hbuf[m][r0 + k][q];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) {
+            for (int o = 0; o < 4; ++o) {
                 float acc = 0.f;
 #pragma unroll
                 for (int k = 0; k < 2 * kSsimR + 1; ++k) acc += w[k] * col[o + k];
                 g[m][o] = acc;
             }
         }
-        const int x = ox + q;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
+        for (int o = 0; o < 4; ++o) {
             const int y = oy + r0 + o;
-            if (x < W && y < H) {
-                const float xv = sX[2 * kSsimR + r0 + o][2 * kSsimR + q];
-                const float yv = sY[2 * kSsimR + r0 + o][2 * kSsimR + q];
+            if (x < W && y < H)
                 a.d_rgb[3 * vt.pix_base[b] + c * plane + (long long)y * W + x] =
-                    -(g[0][o] + 2.f * xv * g[1][o] + yv * g[2][o]);
-            }
+                    -(g[0][o] + 2.f * xv[o] * g[1][o] + yv[o] * g[2][o]);
         }
     }
 
