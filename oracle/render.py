@@ -17,13 +17,15 @@ Compositing at pixel (px, py), centre (px + 0.5, py + 0.5), over *all* surviving
     alpha = min(alpha_max, o e^power); kept if power <= 0 and alpha >= alpha_min
     kept Gaussians ordered by (float32(z), i); T = 1; for each: T' = T (1 - alpha);
     if T' < t_min stop (this one excluded); w = alpha T; C += w rgb; D += w z; A += w; T = T'
-    outputs C + T bg, D (expected depth, unnormalised), A, T_final.
+    outputs C + T bg, D (expected depth, unnormalised), A, T_final, and D2 = sum w z^2.
 
 Loss (Sec. III-C), summed over views b:
     w_l1 [(1 - lambda_s) / (3 n_b) sum_{p in mask} sum_ch |C - C_gt|
           + lambda_s / (3 n_b) sum_{p in mask} sum_ch (1 - ssim_ch(p))]
   + lambda_L / |Omega_b| sum_{u in Omega_b} KL(N(D_L(u), sigma_L^2) || N(mu_u, sigma_u^2)),
-    mu_u = D(u), sigma_u = sigma_L (fixed-variance reading); lambda_s weighs the D-SSIM
+    mu_u = D(u), sigma_u = sigma_L (fixed-variance reading) or, in the rendered-variance
+    reading, sigma_u^2 = D2(u) - mu_u^2 + floor with D2 = sum w z^2 composited like the
+    depth (the variance of the rendered depth distribution); lambda_s weighs the D-SSIM
     part of L_3DGS (0: L1 only), ssim the map of `oracle.ssim` over the whole rendered
     image (zero-padded windows), averaged over the mask.
 
@@ -231,9 +233,11 @@ def composite_eval(proj, px, py, dec: Decisions, s: RenderSettings):
     T_final = T_after[:, -1]
     bg = torch.tensor(s.bg, dtype=DT)
     rgb = (w[..., None] * proj["rgb"][idx]).sum(1) + T_final[:, None] * bg
-    depth = (w * proj["z"][idx]).sum(1)
+    z = proj["z"][idx]
+    depth = (w * z).sum(1)
     acc = w.sum(1)
-    return rgb, depth, acc, T_final
+    depth2 = (w * z * z).sum(1)
+    return rgb, depth, acc, T_final, depth2
 
 
 def _pixel_coords(cam, pix):
@@ -254,8 +258,9 @@ def render(scene, s: RenderSettings = None, pixels=None, p=None):
             px, py = _pixel_coords(cam, pix)
             proj = project(p, cam, p["pose_delta"][b], s, scene.sh_degree)
             dec = composite_decisions(proj, px, py, s)
-            rgb, depth, acc, T = composite_eval(proj, px, py, dec, s)
+            rgb, depth, acc, T, depth2 = composite_eval(proj, px, py, dec, s)
             out.append({"rgb": rgb.numpy(), "depth": depth.numpy(), "alpha": acc.numpy(),
+                        "depth2": depth2.numpy(),
                         "T": T.numpy(), "count": dec.count, "ambiguous": dec.ambiguous,
                         "pix": pix, "proj": proj, "dec": dec})
     return out
@@ -279,7 +284,8 @@ def _dilate(cam, pix, r):
 
 def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=None,
                    w_l1: float = 1.0, lam: float = 1.0, upstream=None, sign_margin=1e-5,
-                   frozen=None, deltas=None, ssim_w: float = 0.0):
+                   frozen=None, deltas=None, ssim_w: float = 0.0, sigma_mode: str = "fixed",
+                   sigma_floor: float = 1e-4):
     """Loss of Sec. III-C (L1 and D-SSIM parts of L_3DGS + LiDAR KL term) and its float64
     gradients.
 
@@ -318,7 +324,7 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
         else:
             dec = composite_decisions(proj, px, py, s)
         decisions.append(dec)
-        rgb, depth, acc, T = composite_eval(proj, px, py, dec, s)
+        rgb, depth, acc, T, depth2 = composite_eval(proj, px, py, dec, s)
         pos = {int(q): k for k, q in enumerate(eval_pix)}
         amb_pix = dec.ambiguous.copy()
         if upstream is not None:
@@ -347,7 +353,12 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
                 dl = torch.tensor(np.asarray(lidar[b]["depth"], np.float64))
                 sl = torch.tensor(np.asarray(lidar[b]["sigma"], np.float64))
                 mu_u = depth[li]
-                kl = kl_normal(dl, sl, mu_u, sl)
+                if sigma_mode == "rendered":
+                    # sigma_u^2 = sum w z^2 - mu_u^2 + floor (the rendered depth variance)
+                    su = torch.sqrt(depth2[li] - mu_u * mu_u + sigma_floor)
+                else:
+                    su = sl
+                kl = kl_normal(dl, sl, mu_u, su)
                 total = total + lam / len(li) * kl.sum()
         for r in np.nonzero(amb_pix)[0]:
             amb_gauss[cam.g_begin + dec.touched[r]] = True
@@ -363,11 +374,12 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
 
 
 def frozen_objective(scene, decisions, s: RenderSettings = None, masks=None, lidar=None,
-                     gt=None, w_l1=1.0, lam=1.0, upstream=None, deltas=None, ssim_w=0.0):
+                     gt=None, w_l1=1.0, lam=1.0, upstream=None, deltas=None, ssim_w=0.0,
+                     sigma_mode="fixed", sigma_floor=1e-4):
     """The same objective as `loss_and_grads` evaluated with given frozen decisions and no
     gradient (used by finite differences)."""
     s = s or RenderSettings()
     with torch.enable_grad():
         r = loss_and_grads(scene, s, masks, lidar, gt, w_l1, lam, upstream, frozen=decisions,
-                           deltas=deltas, ssim_w=ssim_w)
+                           deltas=deltas, ssim_w=ssim_w, sigma_mode=sigma_mode, sigma_floor=sigma_floor)
     return r["loss"]
