@@ -128,6 +128,12 @@ typedef struct ags_fwd_out {
     float* rgb;
     float* depth;
     float* alpha;
+    float* depth_var; /* [P] or NULL: variance of the rendered depth distribution,
+                         sum_k w_k z_k^2 - (sum_k w_k z_k)^2 (needed by the rendered-variance
+                         LiDAR term), written when non-null; accumulated as the scatter about
+                         the running weighted mean plus A T m^2 (A = sum w, T = final
+                         transmittance, m = mean), which avoids the cancellation of the
+                         difference of moments in float32 */
 } ags_fwd_out;
 
 /* Upstream gradients dL/d(rgb, depth, alpha) in the output layouts; each may be NULL (0). */
@@ -140,10 +146,14 @@ typedef struct ags_upstream {
 /* Fused loss (Sec. III-C: photometric L_3DGS plus L_LiDAR), summed over views b:
  *   w_l1 [(1 - ssim_weight) / (3 n_b) sum_{p in mask_b} sum_c |rgb - gt_rgb|
  *         + ssim_weight / (3 n_b) sum_{p in mask_b} sum_c (1 - ssim_c(p))]
- * + lambda_lidar / |Omega_b| sum_{j in Omega_b} KL(N(D_j, s_j^2) || N(depth(p_j), s_j^2))
- * (equal variances: (depth - D_j)^2 / (2 s_j^2)).  n_b = l1_count[b] if mask is given,
+ * + lambda_lidar / |Omega_b| sum_{j in Omega_b} KL(N(D_j, s_j^2) || N(depth(p_j), su_j^2))
+ * with su_j = s_j (AGS_SIGMA_FIXED; the KL is then (depth - D_j)^2 / (2 s_j^2)) or
+ * su_j^2 = depth_var(p_j) + sigma_floor (AGS_SIGMA_RENDERED: the variance of the rendered
+ * depth distribution; the backward then needs fwd->depth_var).  n_b = l1_count[b] if mask is given,
  * else W_b H_b; the sign of 0 is 0.  Repeated target pixels simply add their terms.
  * ssim_c(p) uses the whole rendered view (zero outside it), also outside the mask. */
+enum { AGS_SIGMA_FIXED = 0, AGS_SIGMA_RENDERED = 1 };
+
 typedef struct ags_loss {
     const float* gt_rgb;          /* device, rgb layout */
     const uint8_t* mask;          /* device [P] (1 = pixel enters the L1 term) or NULL */
@@ -155,6 +165,8 @@ typedef struct ags_loss {
                                      [depth_offsets[b], depth_offsets[b+1]) */
     float w_l1;
     float lambda_lidar;
+    int32_t sigma_mode;           /* AGS_SIGMA_FIXED or AGS_SIGMA_RENDERED */
+    float sigma_floor;            /* m^2 added to the rendered variance (> 0 in RENDERED mode) */
     float ssim_weight;            /* lambda of L_3DGS = (1 - lambda) L1 + lambda D-SSIM (Sec. III-C),
                                      in [0, 1]; 0 = L1 only.  D-SSIM = 1 - SSIM with an 11 x 11
                                      Gaussian window (sigma 1.5, zero padding), C1 = 0.01^2,

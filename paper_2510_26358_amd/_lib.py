@@ -53,7 +53,7 @@ class Grads(C.Structure):
 
 
 class FwdOut(C.Structure):
-    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p)]
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("depth_var", C.c_void_p)]
 
 
 class Upstream(C.Structure):
@@ -65,7 +65,10 @@ class Loss(C.Structure):
                 ("l1_count", C.POINTER(C.c_int64)), ("depth_pix", C.c_void_p),
                 ("depth_val", C.c_void_p), ("depth_sigma", C.c_void_p),
                 ("depth_offsets", C.POINTER(C.c_int64)), ("w_l1", C.c_float),
-                ("lambda_lidar", C.c_float), ("ssim_weight", C.c_float)]
+                ("lambda_lidar", C.c_float), ("sigma_mode", C.c_int32), ("sigma_floor", C.c_float),
+                ("ssim_weight", C.c_float)]
+
+SIGMA_FIXED, SIGMA_RENDERED = 0, 1
 
 
 class Sizes(C.Structure):

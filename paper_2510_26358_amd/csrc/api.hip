@@ -59,7 +59,7 @@ struct Layout {
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
     // bwd ws
-    size_t b_grad2d, b_ddepth, b_dssim, b_partials, b_pose_part, b_vis, b_total;
+    size_t b_grad2d, b_ddepth, b_ddepth2, b_dssim, b_partials, b_pose_part, b_vis, b_total;
     long long n_partials, n_ssim;
 };
 
@@ -161,6 +161,7 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.n_partials = tiles + lidar_blocks(0) + L.n_ssim;  // raster, LiDAR, then D-SSIM blocks
     L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
     L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
+    L.b_ddepth2 = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
     L.b_dssim = o; o = align_up(o + (size_t)(pix > 0 ? 3 * pix : 1) * 4);
     L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
     L.b_pose_part = o; o = align_up(o + (size_t)2 * (project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
@@ -420,6 +421,7 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         ra.rgb = out->rgb;
         ra.depth = out->depth;
         ra.alpha = out->alpha;
+        ra.depth_var = out->depth_var;
         ra.t_final = at<float>(saved, L.s_t_final);
         ra.last = at<uint32_t>(saved, L.s_last);
         rc = launch_raster_fwd(ra, ctx->cfg.tile, ctx->cfg.batch, ctx->cfg.px_per_thread, s);
@@ -470,6 +472,9 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         if (!fwd || !fwd->rgb || !fwd->depth || !loss->gt_rgb) return AGS_ERR_INVALID_ARG;
         if (loss->mask && !loss->l1_count) return AGS_ERR_INVALID_ARG;
         if (!(loss->ssim_weight >= 0.f && loss->ssim_weight <= 1.f)) return AGS_ERR_INVALID_ARG;
+        if (loss->sigma_mode != AGS_SIGMA_FIXED && loss->sigma_mode != AGS_SIGMA_RENDERED) return AGS_ERR_INVALID_ARG;
+        if (loss->sigma_mode == AGS_SIGMA_RENDERED && (!fwd->depth_var || !(loss->sigma_floor > 0.f)))
+            return AGS_ERR_INVALID_ARG;
         if (loss->depth_offsets) {
             if (loss->depth_offsets[0] != 0) return AGS_ERR_INVALID_ARG;
             for (int b = 0; b < views->n_views; ++b)
@@ -484,11 +489,14 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     const Settings st = settings_of(ctx->cfg);
     float* grad2d = at<float>(ws, L.b_grad2d);
     float* ddepth = at<float>(ws, L.b_ddepth);
+    float* ddepth2 = at<float>(ws, L.b_ddepth2);
+    const bool rendered_var = loss && loss->sigma_mode == AGS_SIGMA_RENDERED;
     float* partials = at<float>(ws, L.b_partials);
     {
         Scope sc(ctx, ST_CLEAR, s);
         launch_fill_f32(grad2d, 0.f, L.Q * kGrad2dStride, s);
         if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
+        if (rendered_var && n_targets > 0) launch_fill_f32(ddepth2, 0.f, L.P, s);
         if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, lidar_blocks(0), s);
         if (loss && !(loss->ssim_weight > 0.f))
             launch_fill_f32(partials + L.n_tiles + lidar_blocks(0), 0.f, L.n_ssim, s);
@@ -530,12 +538,16 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         }
         ra.loss_partials = partials;
         ra.d_depth = n_targets > 0 ? ddepth : nullptr;
+        ra.d_depth2 = (n_targets > 0 && rendered_var) ? ddepth2 : nullptr;
         if (n_targets > 0) {
             Scope sc(ctx, ST_LIDAR, s);
             LidarArgs la;
             memset(&la, 0, sizeof(la));
             la.vt = L.vt;
             la.depth = fwd->depth;
+            la.depth_var = rendered_var ? fwd->depth_var : nullptr;
+            la.sigma_floor = loss->sigma_floor;
+            la.d_depth2 = ddepth2;
             la.pix = loss->depth_pix;
             la.val = loss->depth_val;
             la.sigma = loss->depth_sigma;

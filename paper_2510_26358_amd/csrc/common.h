@@ -411,6 +411,7 @@ struct RasterArgs {
     float* rgb;
     float* depth;
     float* alpha;
+    float* depth_var;  // or null: rendered depth variance per pixel
     float* t_final;
     uint32_t* last;
 };
@@ -429,8 +430,10 @@ struct RasterBwdArgs {
     const float* d_depth;
     const float* d_alpha;
     // loss mode (fused L1 prologue); d_depth then points at the scattered LiDAR adjoint and
-    // d_rgb (or null) at the adjoint of the D-SSIM part, both added to the pixel's adjoints
+    // d_rgb (or null) at the adjoint of the D-SSIM part, both added to the pixel's adjoints;
+    // d_depth2 (or null) at the LiDAR adjoint of the second depth moment (rendered variance)
     int loss_mode;
+    const float* d_depth2;
     const float* rgb;
     const float* gt_rgb;
     const uint8_t* mask;
@@ -458,6 +461,9 @@ void launch_ssim(SsimArgs a, hipStream_t s);
 struct LidarArgs {
     ViewTable vt;
     const float* depth;
+    const float* depth_var;      // rendered variance mode: rendered depth variance, else null
+    float sigma_floor;
+    float* d_depth2;             // rendered variance mode: dense [P] adjoint (zeroed before)
     const int32_t* pix;
     const float* val;
     const float* sigma;

@@ -1,10 +1,15 @@
 // LiDAR depth-consistency adjoint (Sec. III-C, probabilistic depth term).
 //
 // Each LiDAR return j of view b at pixel p_j is N(D_j, s_j^2); the renderer's depth
-// distribution there is N(mu, s_j^2) with mu the composited expected depth (fixed
-// variance reading, sigma_u = sigma_L).  The term lambda / |Omega_b| KL(.||.) equals
-// lambda / |Omega_b| (mu - D_j)^2 / (2 s_j^2); its adjoint lambda / |Omega_b| (mu - D_j) / s_j^2
-// is added into a dense per-pixel depth adjoint that the raster backward reads.
+// distribution there is N(mu, v) with mu the composited expected depth and
+//   v = s_j^2 (fixed-variance reading: the term is (mu - D_j)^2 / (2 s_j^2), adjoint
+//       (mu - D_j) / s_j^2), or
+//   v = M2 - mu^2 + floor, M2 = sum w z^2 (rendered variance, from the forward's variance
+//       output): with e = D_j - mu and
+//       K = KL(N(D_j, s^2) || N(mu, v)) = ln(sqrt(v) / s) + (s^2 + e^2) / (2 v) - 1/2,
+//       dK/dv = 1 / (2 v) - (s^2 + e^2) / (2 v^2), dK/dM2 = dK/dv, dK/dmu = -e / v - 2 mu dK/dv.
+// Each term is scaled by lambda / |Omega_b|; the adjoints go into dense per-pixel buffers
+// (depth, and second moment) that the raster backward reads.
 #include "common.h"
 
 namespace ags {
@@ -28,9 +33,19 @@ __global__ __launch_bounds__(kLidarThreads) void lidar_adjoint_kernel(LidarArgs 
         const float mu = a.depth[gp];
         const float s = a.sigma[j];
         const float r = mu - a.val[j];
-        const float is2 = 1.f / (s * s);
-        atomicAdd(a.d_depth + gp, a.scale[b] * r * is2);
-        part += a.scale[b] * 0.5f * r * r * is2;
+        if (a.depth_var) {
+            const float v = a.depth_var[gp] + a.sigma_floor;
+            const float iv = 1.f / v;
+            const float q = s * s + r * r;
+            const float dv = 0.5f * iv - 0.5f * q * iv * iv;
+            atomicAdd(a.d_depth + gp, a.scale[b] * (r * iv - 2.f * mu * dv));
+            atomicAdd(a.d_depth2 + gp, a.scale[b] * dv);
+            part += a.scale[b] * (0.5f * __logf(v / (s * s)) + 0.5f * q * iv - 0.5f);
+        } else {
+            const float is2 = 1.f / (s * s);
+            atomicAdd(a.d_depth + gp, a.scale[b] * r * is2);
+            part += a.scale[b] * 0.5f * r * r * is2;
+        }
     }
     part = wave_sum(part);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = part;

@@ -131,10 +131,12 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 // Gaussian) pair has alpha < alpha_min, so the result is the same as evaluating it.
 // LDS layout (64 B, read at non-negative offsets from one per-lane address):
 //   [0] = (wave mask bits, r, g, b), [1] = (u, v, -a/2 log2e, -b log2e),
-//   [2] = (-c/2 log2e, o, z, log2(alpha_min/o)), [3] = (pair id, -, -, -).
+//   [2] = (-c/2 log2e, o, z, log2(alpha_min/o)), [3] = (pair id, z^2, -, -).
 struct alignas(16) SRec {
     float4 m, g0, g1;
-    uint32_t q, pad[3];
+    uint32_t q;
+    float z2;
+    uint32_t pad[2];
 };
 
 template <int T, int PPT, bool BLOCKS>
@@ -148,6 +150,7 @@ __device__ __forceinline__ void stage_record(const float* records, uint32_t q, f
     dst.g0 = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
     dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
     dst.q = q;
+    dst.z2 = r1.z * r1.z;
 }
 
 // Makes the record's fields live at this point, so all of its LDS reads are issued together
@@ -171,7 +174,11 @@ __device__ __forceinline__ float power_of(const float4& r0, const float4& r1, fl
     return dx * (r0.z * dx + r0.w * dy) + r1.x * dy * dy;
 }
 
-template <int T, int PPT, int M>
+// S2: also output the rendered depth variance sum w z^2 - (sum w z)^2 (rendered-variance
+// LiDAR term), accumulated without cancellation: the weighted scatter S about the running
+// normalised mean m (A' = A + w, m' = m + (z - m) w / A', S' = S + w (z - m)(z - m')), then
+// sum w z^2 - (A m)^2 = S + A (1 - A) m^2 with 1 - A = the final transmittance.
+template <int T, int PPT, int M, bool S2>
 __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ SRec srec[M];
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     // then -inf (or NaN), below every threshold, so it keeps no further Gaussian without a
     // separate flag test.
     constexpr float kStopped = __builtin_huge_valf();
-    float cx[PPT], cy[PPT], Tr[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], A[PPT];
+    float cx[PPT], cy[PPT], Tr[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], A[PPT], Mn[PPT], Sc[PPT];
     uint32_t last[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         cx[k] = (px < tc.W && py < tc.H) ? (float)px + 0.5f : kStopped;
         cy[k] = (float)py + 0.5f;
         Tr[k] = 1.f;
-        C0[k] = C1[k] = C2[k] = D[k] = A[k] = 0.f;
+        C0[k] = C1[k] = C2[k] = D[k] = A[k] = Mn[k] = Sc[k] = 0.f;
         last[k] = 0;
     }
     const float amin = a.st.alpha_min, tmin = a.st.t_min;
@@ -246,6 +253,11 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                         C2[k] += w * rc.w;
                         D[k] += w * r1.z;
                         A[k] += w;
+                        if (S2) {
+                            const float dz = r1.z - Mn[k];
+                            Mn[k] += dz * (w * __builtin_amdgcn_rcpf(A[k]));
+                            Sc[k] += w * dz * (r1.z - Mn[k]);
+                        }
                         Tr[k] = __builtin_fmaf(-alpha, Tr[k], Tr[k]);  // T (1 - alpha), one rounding
                         last[k] = e - start + 1;
                     }
@@ -267,6 +279,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         rgb[plane + p] = C1[k] + Tr[k] * a.st.bg1;
         rgb[2 * plane + p] = C2[k] + Tr[k] * a.st.bg2;
         a.depth[gp] = D[k];
+        if (S2) a.depth_var[gp] = Sc[k] + A[k] * Tr[k] * Mn[k] * Mn[k];
         a.alpha[gp] = A[k];
         a.t_final[gp] = Tr[k];
         a.last[gp] = last[k];
@@ -274,7 +287,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
 }
 
 // GA: the upstream adjoint has an alpha term (dL/dA); the fused loss never has one.
-template <int T, int PPT, int M, bool GA>
+// S2: the loss has an adjoint for the second depth moment sum w z^2 (rendered variance).
+template <int T, int PPT, int M, bool GA, bool S2>
 __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ SRec srec[M];
@@ -289,7 +303,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const float amin = a.st.alpha_min;
 
     // U = T_final gC.bg + sum over later contributors j of w_j (gC.c_j + gD z_j + gA)
-    float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], U[PPT];
+    float cx[PPT], cy[PPT], Tr[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gM[PPT], U[PPT];
     uint32_t last[PPT];
     float loss_part = 0.f;
     uint32_t mylast = 0;
@@ -301,7 +315,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         const int px = tc.px0 + lx, py = tc.py0 + ly;
         cx[k] = (float)px + 0.5f;
         cy[k] = (float)py + 0.5f;
-        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = 0.f;
+        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gM[k] = 0.f;
         Tr[k] = 1.f;
         last[k] = 0;
         U[k] = 0.f;
@@ -331,6 +345,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                     gC2[k] += g[2 * plane + p];
                 }
                 if (a.d_depth) gD[k] = a.d_depth[gp];
+                if (S2) gM[k] = a.d_depth2[gp];
             } else {
                 if (a.d_rgb) {
                     const float* g = a.d_rgb + 3 * tc.pix0;
@@ -388,6 +403,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             const float4 rm = r.m, r0 = r.g0, r1 = r.g1;
             use_record(rm, r0, r1);
             if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) continue;  // wave-uniform
+            const float z2 = S2 ? r.z2 : 0.f;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
             // passes (a lane passes exactly when it can keep this Gaussian, up to rounding of
             // the threshold, and keeps are re-tested on alpha below)
@@ -419,6 +435,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 const float w = ak * Tk;
                 float qv = gC0[k] * rm.y + gC1[k] * rm.z + gC2[k] * rm.w + gD[k] * r1.z;
                 if (GA) qv += gA[k];
+                if (S2) qv += gM[k] * z2;
                 const float ga = Tk * qv - U[k] * rom;  // dL/dalpha
                 U[k] += w * qv;
                 Tr[k] = Tk;
@@ -428,8 +445,10 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 // h dy^2); it turns them into the centre and conic adjoints
                 const float h = (keep && araw <= amax) ? ga * G : 0.f;
                 const float t1 = h * dx, t2 = h * dy;
+                // depth adjoint: d(w z)/dz = w, d(w z^2)/dz = 2 w z
+                const float gz = S2 ? gD[k] + 2.f * r1.z * gM[k] : gD[k];
                 const float c[10] = {t1, t2, t1 * dx, t1 * dy, t2 * dy, h,
-                                     w * gC0[k], w * gC1[k], w * gC2[k], w * gD[k]};
+                                     w * gC0[k], w * gC1[k], w * gC2[k], w * gz};
 #pragma unroll
                 for (int s = 0; s < 10; ++s) g[s] = k == 0 ? c[s] : g[s] + c[s];
             }
@@ -458,7 +477,10 @@ int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_
     if (nb <= 0) return 0;
 #define X(t_, p_, m_)                                                                              \
     if (T == t_ && ppt == p_ && batch == m_) {                                                     \
-        hipLaunchKernelGGL((raster_fwd_kernel<t_, p_, m_>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        if (a.depth_var)                                                                           \
+            hipLaunchKernelGGL((raster_fwd_kernel<t_, p_, m_, true>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((raster_fwd_kernel<t_, p_, m_, false>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
         return 0;                                                                                  \
     }
     AGS_RASTER_CONFIGS(X)
@@ -470,12 +492,15 @@ int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStre
     const int nb = raster_blocks(a.vt);
     if (nb <= 0) return 0;
     const bool ga = !a.loss_mode && a.d_alpha != nullptr;
+    const bool m2 = a.loss_mode && a.d_depth2 != nullptr;
 #define X(t_, p_, m_)                                                                                      \
     if (T == t_ && ppt == p_ && batch == m_) {                                                             \
         if (ga)                                                                                            \
-            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, true>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a);  \
+            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, true, false>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+        else if (m2)                                                                                       \
+            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, false, true>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
         else                                                                                               \
-            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, false>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
+            hipLaunchKernelGGL((raster_bwd_kernel<t_, p_, m_, false, false>), dim3(nb), dim3(t_ * t_ / p_), 0, s, a); \
         return 0;                                                                                          \
     }
     AGS_RASTER_CONFIGS(X)

@@ -20,6 +20,12 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def _fwd_out(out):
+    """ags_fwd_out for (rgb, depth, alpha[, depth variance])."""
+    return L.FwdOut(out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                    out[3].data_ptr() if len(out) > 3 else None)
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -129,10 +135,12 @@ class LossTargets:
     w_l1: float = 1.0
     lambda_lidar: float = 1.0
     ssim_weight: float = 0.0          # lambda of the D-SSIM part of L_3DGS (0: L1 only)
+    sigma_mode: str = "fixed"         # LiDAR KL: "fixed" (sigma_u = sigma_L) or "rendered"
+    sigma_floor: float = 1e-4         # m^2 added to the rendered depth variance
 
     @classmethod
     def from_scene(cls, scene, views: ViewSpec, device="cuda", masks=None, lidar=None, gt=None,
-                   w_l1=1.0, lambda_lidar=1.0, ssim_weight=0.0):
+                   w_l1=1.0, lambda_lidar=1.0, ssim_weight=0.0, sigma_mode="fixed", sigma_floor=1e-4):
         gt = scene.gt_rgb if gt is None else gt
         lidar = scene.lidar if lidar is None else lidar
         flat = np.concatenate([np.asarray(g, np.float32).reshape(-1) for g in gt])
@@ -158,7 +166,8 @@ class LossTargets:
         while len(offs) < views.n_views + 1:
             offs.append(offs[-1])
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
-        return cls(dev(flat), mask_t, counts, dev(pix), dev(val), dev(sig), offs, w_l1, lambda_lidar, ssim_weight)
+        return cls(dev(flat), mask_t, counts, dev(pix), dev(val), dev(sig), offs, w_l1, lambda_lidar, ssim_weight,
+                   sigma_mode, sigma_floor)
 
     def c(self):
         self._keep = (_i64(self.l1_count), _i64(self.depth_offsets))
@@ -166,7 +175,9 @@ class LossTargets:
                       self._keep[0], self.depth_pix.data_ptr() if self.depth_pix.numel() else None,
                       self.depth_val.data_ptr() if self.depth_val.numel() else None,
                       self.depth_sigma.data_ptr() if self.depth_sigma.numel() else None,
-                      self._keep[1], float(self.w_l1), float(self.lambda_lidar), float(self.ssim_weight))
+                      self._keep[1], float(self.w_l1), float(self.lambda_lidar),
+                      L.SIGMA_RENDERED if self.sigma_mode == "rendered" else L.SIGMA_FIXED,
+                      float(self.sigma_floor), float(self.ssim_weight))
 
 
 class Buffers:
@@ -234,16 +245,18 @@ class Rasterizer:
     def buffers(self, views: ViewSpec, n: int, sh_degree: int, capacity: int) -> Buffers:
         return Buffers(self.sizes(views, n, sh_degree, capacity), capacity, self.device)
 
-    def outputs(self, views: ViewSpec):
+    def outputs(self, views: ViewSpec, depth_var: bool = False):
+        """(rgb, depth, alpha) buffers, plus the rendered depth variance when `depth_var`
+        (needed by the rendered-variance LiDAR term)."""
         P = views.n_pixels
-        return (torch.empty(3 * P, device=self.device), torch.empty(P, device=self.device),
-                torch.empty(P, device=self.device))
+        out = (torch.empty(3 * P, device=self.device), torch.empty(P, device=self.device),
+               torch.empty(P, device=self.device))
+        return out + (torch.empty(P, device=self.device),) if depth_var else out
 
     # ------------------------------------------------------------------ calls
     def forward_into(self, params: SplatParams, cams: torch.Tensor, views: ViewSpec, buf: Buffers,
                      out):
-        rgb, depth, alpha = out
-        fo = L.FwdOut(rgb.data_ptr(), depth.data_ptr(), alpha.data_ptr())
+        fo = _fwd_out(out)
         g = params.c()
         rc = self.lib.ags_render_fwd(self.ctx, C.byref(views.c), C.byref(g), _ptr(cams),
                                      buf.capacity, C.byref(fo), _ptr(buf.saved), _ptr(buf.fwd_ws),
@@ -253,8 +266,7 @@ class Rasterizer:
     def backward_into(self, params: SplatParams, cams, views: ViewSpec, buf: Buffers, out, grads,
                       pose_grad, upstream=None, loss: LossTargets | None = None, loss_out=None,
                       accumulate=False):
-        rgb, depth, alpha = out
-        fo = L.FwdOut(rgb.data_ptr(), depth.data_ptr(), alpha.data_ptr())
+        fo = _fwd_out(out)
         g = params.c()
         gr = L.Grads(*[t.data_ptr() for t in grads.tensors()], pose_grad.data_ptr(), int(accumulate))
         up = None
@@ -280,14 +292,14 @@ class Rasterizer:
         L.check(rc, "ags_bin_records", self.ctx)
 
     def render(self, params: SplatParams, cams, views: ViewSpec, capacity: int | None = None,
-               buf: Buffers | None = None):
+               buf: Buffers | None = None, depth_var: bool = False):
         """Forward with automatic capacity growth (synchronises to read the counters).
         Returns (out, buffers)."""
         cap = capacity or (buf.capacity if buf is not None else max(1 << 16, 8 * views.n_pixels // 16))
         while True:
             if buf is None or buf.capacity < cap:
                 buf = self.buffers(views, params.n, params.sh_degree, cap)
-            out = self.outputs(views)
+            out = self.outputs(views, depth_var)
             self.forward_into(params, cams, views, buf, out)
             k, v, over, keff = buf.counters()
             if not over:

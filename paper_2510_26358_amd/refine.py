@@ -38,7 +38,7 @@ class Refiner:
             capacity = int(b.counters()[0] * headroom) + 4096
             del b
         self.buf = ras.buffers(views, params.n, params.sh_degree, capacity)
-        self.out = ras.outputs(views)
+        self.out = ras.outputs(views, depth_var=targets.sigma_mode == "rendered")
         self.grads = params.zeros_like()
         self.m = params.zeros_like()
         self.v = params.zeros_like()

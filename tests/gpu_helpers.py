@@ -19,15 +19,19 @@ TOL_DEPTH_REL = 1e-4
 TOL_GRAD = 1e-3
 
 
-def run_forward(scene, ras: Rasterizer, capacity=None):
+def run_forward(scene, ras: Rasterizer, capacity=None, depth_var=False):
     views = ViewSpec.from_scene(scene)
     p = SplatParams.from_scene(scene)
     cams = cameras_tensor(scene.cameras)
-    out, buf = ras.render(p, cams, views, capacity=capacity)
+    out, buf = ras.render(p, cams, views, capacity=capacity, depth_var=depth_var)
     torch.cuda.synchronize()
     res = []
-    for b, (rgb, d, a) in enumerate(split_views(*out, views)):
+    for b, (rgb, d, a) in enumerate(split_views(*out[:3], views)):
         res.append({"rgb": rgb.cpu().numpy(), "depth": d.cpu().numpy(), "alpha": a.cpu().numpy()})
+    if depth_var:
+        pb = views.pix_base
+        for b in range(views.n_views):
+            res[b]["depth_var"] = out[3][pb[b]:pb[b + 1]].cpu().numpy().reshape(views.heights[b], views.widths[b])
     return res, (p, cams, views, out, buf)
 
 
@@ -47,10 +51,10 @@ def saved_arrays(buf, views: ViewSpec):
 
 
 def run_loss_backward(scene, ras: Rasterizer, masks=None, w_l1=1.0, lam=1.0, capacity=None, ssim_w=0.0,
-                      gt=None):
-    res, (p, cams, views, out, buf) = run_forward(scene, ras, capacity)
+                      gt=None, sigma_mode="fixed", sigma_floor=1e-4):
+    res, (p, cams, views, out, buf) = run_forward(scene, ras, capacity, depth_var=sigma_mode == "rendered")
     tg = LossTargets.from_scene(scene, views, masks=masks, w_l1=w_l1, lambda_lidar=lam, ssim_weight=ssim_w,
-                                gt=gt)
+                                gt=gt, sigma_mode=sigma_mode, sigma_floor=sigma_floor)
     grads = p.zeros_like()
     pose = torch.zeros(views.n_views, 6, device="cuda")
     loss = torch.zeros(1, device="cuda")
