@@ -250,6 +250,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
     ap.add_argument("--ssim", type=float, default=0.2,
                     help="also time the step with the D-SSIM part of L_3DGS at this weight (0: skip)")
+    ap.add_argument("--rendered-variance", type=float, default=1e-4, metavar="FLOOR",
+                    help="also time the step with the rendered-variance LiDAR term (this variance floor, "
+                         "m^2; 0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -382,6 +385,32 @@ def main():
             f"{with_ssim}")
         tg.ssim_weight = 0.0
 
+    # the same step with the rendered-variance reading of the LiDAR term
+    with_rv = None
+    if args.rendered_variance > 0 and refiner is None:
+        out_v = ras.outputs(views, depth_var=True)
+        tg.sigma_mode, tg.sigma_floor = "rendered", args.rendered_variance
+
+        def step_v():
+            ras.forward_into(p, cams, views, buf, out_v)
+            ras.backward_into(p, cams, views, buf, out_v, grads, pose, loss=tg, loss_out=loss)
+
+        timed_v = step_v
+        if not args.no_graph:
+            for _ in range(args.warmup):
+                step_v()
+            torch.cuda.synchronize()
+            graph_v = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph_v):
+                step_v()
+            timed_v = graph_v.replay
+        t_v = time_steps(timed_v, args.steps, args.warmup)
+        with_rv = {"sigma_floor": args.rendered_variance, "ms_per_step": round(t_v * 1e3, 4),
+                   "value": round(P / t_v / 1e6, 2), "loss": round(loss.item(), 6)}
+        log(f"[bench] with the rendered-variance LiDAR term: {t_v * 1e3:.3f} ms/step, {P / t_v / 1e6:.1f} Mpixel/s")
+        tg.sigma_mode = "fixed"
+        del out_v
+
     loop = None
     if not args.no_loop and views.n_views > 1 and refiner is None:
         from paper_2510_26358_amd.rasterizer import LossTargets
@@ -433,7 +462,7 @@ def main():
                    "autotuned": None if tuned is None else tuned["ms"],
                    "visible_pairs": V, "intersections": K},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
-        "with_ssim": with_ssim,
+        "with_ssim": with_ssim, "with_rendered_variance": with_rv,
     }
     print(json.dumps(rec), flush=True)
 
