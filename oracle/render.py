@@ -285,7 +285,7 @@ def _dilate(cam, pix, r):
 def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=None,
                    w_l1: float = 1.0, lam: float = 1.0, upstream=None, sign_margin=1e-5,
                    frozen=None, deltas=None, ssim_w: float = 0.0, sigma_mode: str = "fixed",
-                   sigma_floor: float = 1e-4):
+                   sigma_floor: float = 1e-4, stats: bool = False):
     """Loss of Sec. III-C (L1 and D-SSIM parts of L_3DGS + LiDAR KL term) and its float64
     gradients.
 
@@ -306,6 +306,7 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
     views = []
     amb_gauss = np.zeros(scene.n, bool)
     decisions = []
+    projs = []
     for b, cam in enumerate(scene.cameras):
         HW = cam.width * cam.height
         if upstream is not None:
@@ -319,6 +320,10 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
                 eval_pix = np.union1d(eval_pix, _dilate(cam, l1_pix, window_radius()))
         px, py = _pixel_coords(cam, eval_pix)
         proj = project(p, cam, p["pose_delta"][b], s, scene.sh_degree)
+        if stats:
+            proj["u"].retain_grad()
+            proj["v"].retain_grad()
+            projs.append(proj)
         if frozen is not None:
             dec = frozen[b]
         else:
@@ -369,8 +374,46 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
     grads = {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
              for k, v in p.items()}
     pose = grads.pop("pose_delta")
-    return {"loss": float(total.detach()), "grads": grads, "pose": pose, "views": views,
-            "amb_gauss": amb_gauss, "decisions": decisions}
+    out = {"loss": float(total.detach()), "grads": grads, "pose": pose, "views": views,
+           "amb_gauss": amb_gauss, "decisions": decisions}
+    if stats:
+        out["stats"] = image_gradient_stats(scene, projs)
+    return out
+
+
+def image_gradient_stats(scene, projs, margin=1e-4):
+    """Densification statistics (Sec. III-B, lifecycle operations: the image-space gradient
+    magnitude at the projected splat centre): per Gaussian, the sum over the views that see
+    it of |dL/d(u, v)| (pixel units) and the number of those views.  A view sees a Gaussian
+    when it survives culling and its footprint rectangle meets the image; `ambiguous` marks
+    Gaussians whose rectangle edge lies within `margin` px of flipping that test."""
+    n = scene.n
+    acc = np.zeros(n)
+    cnt = np.zeros(n, np.int64)
+    amb = np.zeros(n, bool)
+    for cam, proj in zip(scene.cameras, projs):
+        g0 = proj["g0"]
+        gu = proj["u"].grad
+        gv = proj["v"].grad
+        gu = np.zeros(len(proj["u"])) if gu is None else gu.numpy()
+        gv = np.zeros(len(proj["v"])) if gv is None else gv.numpy()
+        u = proj["u"].detach().numpy()
+        v = proj["v"].detach().numpy()
+        ex, ey = proj["ext"][:, 0].numpy(), proj["ext"][:, 1].numpy()
+        valid = proj["valid"].numpy()
+        lo_x, hi_x = u - ex - 0.5, u + ex - 0.5
+        lo_y, hi_y = v - ey - 0.5, v + ey - 0.5
+        x0, x1 = np.clip(np.floor(lo_x), 0, cam.width), np.clip(np.ceil(hi_x), -1, cam.width - 1)
+        y0, y1 = np.clip(np.floor(lo_y), 0, cam.height), np.clip(np.ceil(hi_y), -1, cam.height - 1)
+        seen = valid & (x0 <= x1) & (y0 <= y1)
+        near = lambda t: np.abs(t - np.round(t)) < margin
+        edge = (near(hi_x) & (np.abs(np.ceil(hi_x)) <= 1)) | (near(lo_x) & (np.abs(np.floor(lo_x) - cam.width) <= 1)) | \
+               (near(hi_y) & (np.abs(np.ceil(hi_y)) <= 1)) | (near(lo_y) & (np.abs(np.floor(lo_y) - cam.height) <= 1))
+        idx = np.arange(g0, g0 + len(u))
+        acc[idx] += np.where(seen, np.hypot(gu, gv), 0.0)
+        cnt[idx] += seen
+        amb[idx] |= valid & edge
+    return {"grad_accum": acc, "count": cnt, "ambiguous": amb}
 
 
 def frozen_objective(scene, decisions, s: RenderSettings = None, masks=None, lidar=None,
