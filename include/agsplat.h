@@ -120,6 +120,12 @@ typedef struct ags_grads {
     float* sh;
     float* pose;
     int32_t accumulate;
+    /* Densification statistic (Sec. III-B lifecycle), each [n] or NULL: for every view in
+     * which Gaussian i's footprint rectangle meets the image, stat_grad[i] += |dL/d(u, v)|
+     * (the loss gradient at the projected centre, pixel units) and stat_count[i] += 1.
+     * Always accumulated (never overwritten); the caller zeroes them after densifying. */
+    float* stat_grad;
+    float* stat_count;
 } ags_grads;
 
 /* Forward outputs (device float32): rgb [3 * P], depth [P] (expected depth: sum of
@@ -263,6 +269,47 @@ int ags_profile_enable(ags_ctx* ctx, int enable);
 int ags_profile_read(ags_ctx* ctx, int n_max, const char** names, double* total_ms,
                      int64_t* launches, int* n_out);
 int ags_profile_reset(ags_ctx* ctx);
+
+/* Gaussian-splat lifecycle operations (Sec. III-B "Gaussian Splats Lifecycle Operations"):
+ * pruning, gradient-driven densification and opacity reset.  With s_i = exp(max log-scale)
+ * (largest axis), o_i = sigmoid(logit), g_i = stat_grad[i] / max(stat_count[i], 1):
+ *   prune (do_prune)    if o_i < tau_opa or s_i > s_max or s_i < s_min;
+ *   split (do_densify)  else if stat_count[i] > 0, g_i > grad_threshold and s_i > kappa: two
+ *                       children at mu + R(q) diag(s) eps_k (eps = split_noise[i][k][0..2],
+ *                       standard normals supplied by the caller), log-scales minus
+ *                       ln(split_scale), quaternion / opacity / SH copied;
+ *   duplicate           else if that gradient test holds and s_i <= 2 s_init: the original and
+ *                       an exact copy;
+ *   opacity reset (do_reset) if not pruned, tau_opa <= o_i < tau_reset and s_min <= s_i <= s_max:
+ *                       the logit of every output of i becomes logit(tau_reset).
+ * Decisions are taken in float32.  Outputs keep input order (a Gaussian's outputs are
+ * consecutive); the Adam moments of copies and children are 0, survivors keep theirs. */
+typedef struct ags_lifecycle {
+    int32_t do_prune, do_densify, do_reset;
+    float tau_opa;          /* 0.01 (the paper's value) */
+    float s_min, s_max;     /* 5e-5, 0.3 (the paper's values) */
+    float grad_threshold;   /* gamma_g, pixel units */
+    float kappa;            /* split above this size */
+    float s_init;           /* duplicate at or below 2 s_init */
+    float tau_reset;        /* reset band upper bound and reset value, in (tau_opa, 1) */
+    float split_scale;      /* 1.6 */
+} ags_lifecycle;
+
+/* Scratch bytes ags_lifecycle_step needs for n Gaussians. */
+int ags_lifecycle_workspace(int64_t n, size_t* bytes);
+
+/* One lifecycle pass over `in` (+ its Adam moments in_m, in_v, same layout), writing to
+ * `out` / `out_m` / `out_v` (distinct buffers, same sh_degree, room for out_capacity >= 2 n
+ * Gaussians: their `n` fields give the capacity).  stat_grad / stat_count: the statistic
+ * above, device float[n] each; split_noise: device float[n][2][3]; all three are required
+ * when do_densify != 0 and n > 0, and ignored otherwise.  Writes the new count to *n_out_dev (device int32) and, if non-null, the action of
+ * each input to actions_dev[n] (0 keep, 1 prune, 2 duplicate, 3 split).  No host sync, no
+ * allocation.  INVALID_ARG for bad pointers, sizes or thresholds, WORKSPACE_TOO_SMALL. */
+int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in,
+                       const ags_gaussians* in_m, const ags_gaussians* in_v, const float* stat_grad,
+                       const float* stat_count, const float* split_noise, ags_gaussians* out,
+                       ags_gaussians* out_m, ags_gaussians* out_v, int32_t* n_out_dev,
+                       uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,8 @@ EXPORTED = [
     "ags_version", "ags_error_string", "ags_last_hip_error", "ags_config_default",
     "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
     "ags_render_fwd", "ags_render_bwd", "ags_bin_records", "ags_adam_step", "ags_pose_step",
-    "ags_profile_enable", "ags_profile_read", "ags_profile_reset",
+    "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
+    "ags_lifecycle_step",
 ]
 
 
@@ -49,7 +50,14 @@ class Gaussians(C.Structure):
 class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("pose", C.c_void_p),
-                ("accumulate", C.c_int32)]
+                ("accumulate", C.c_int32), ("stat_grad", C.c_void_p), ("stat_count", C.c_void_p)]
+
+
+class Lifecycle(C.Structure):
+    _fields_ = [("do_prune", C.c_int32), ("do_densify", C.c_int32), ("do_reset", C.c_int32),
+                ("tau_opa", C.c_float), ("s_min", C.c_float), ("s_max", C.c_float),
+                ("grad_threshold", C.c_float), ("kappa", C.c_float), ("s_init", C.c_float),
+                ("tau_reset", C.c_float), ("split_scale", C.c_float)]
 
 
 class FwdOut(C.Structure):
@@ -128,6 +136,9 @@ def load(path: str = LIB_PATH):
     lib.ags_profile_enable.argtypes = [vp, C.c_int]
     lib.ags_profile_read.argtypes = [vp, C.c_int, P(C.c_char_p), P(C.c_double), P(C.c_int64), P(C.c_int)]
     lib.ags_profile_reset.argtypes = [vp]
+    lib.ags_lifecycle_workspace.argtypes = [C.c_int64, P(C.c_size_t)]
+    lib.ags_lifecycle_step.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp,
+                                       P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, C.c_size_t, vp]
     for name in EXPORTED:
         if lib.ags_version and not hasattr(lib, name):
             raise ImportError(f"libagsplat.so lacks {name}")

@@ -467,6 +467,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                      !grads->sh))
         return AGS_ERR_INVALID_ARG;
     if (!grads->pose) return AGS_ERR_INVALID_ARG;
+    if ((grads->stat_grad == nullptr) != (grads->stat_count == nullptr)) return AGS_ERR_INVALID_ARG;
     long long n_targets = 0;
     if (loss) {
         if (!fwd || !fwd->rgb || !fwd->depth || !loss->gt_rgb) return AGS_ERR_INVALID_ARG;
@@ -599,6 +600,8 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.accumulate = grads->accumulate;
         pa.pose_partials = at<float>(ws, L.b_pose_part);
         pa.vis_mask = at<uint32_t>(ws, L.b_vis);
+        pa.stat_grad = grads->stat_grad;
+        pa.stat_count = grads->stat_count;
         launch_project_bwd(pa, s);
     }
     if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);
@@ -640,6 +643,82 @@ int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* p, const ags_
     a.step = step;
     Scope sc(ctx, ST_ADAM, s);
     launch_adam(a, s);
+    return hip_status(ctx);
+}
+
+int ags_lifecycle_workspace(int64_t n, size_t* bytes) {
+    if (n < 0 || n > 0x7fffffffLL || !bytes) return AGS_ERR_INVALID_ARG;
+    const long long ns = n > 0 ? n : 1;
+    *bytes = align_up((size_t)ns * 4) * 2 + align_up((size_t)scan_blocks(ns) * 4);
+    return AGS_OK;
+}
+
+int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in, const ags_gaussians* in_m,
+                       const ags_gaussians* in_v, const float* stat_grad, const float* stat_count,
+                       const float* split_noise, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
+                       int32_t* n_out_dev, uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !lp || !in || !in_m || !in_v || !out || !out_m || !out_v || !n_out_dev || !ws)
+        return AGS_ERR_INVALID_ARG;
+    if (check_gaussians(in) || check_gaussians(in_m) || check_gaussians(in_v) || check_gaussians(out) ||
+        check_gaussians(out_m) || check_gaussians(out_v))
+        return AGS_ERR_INVALID_ARG;
+    const int deg = in->sh_degree;
+    if (in_m->n != in->n || in_v->n != in->n || out_m->n != out->n || out_v->n != out->n)
+        return AGS_ERR_INVALID_ARG;
+    if (in_m->sh_degree != deg || in_v->sh_degree != deg || out->sh_degree != deg || out_m->sh_degree != deg ||
+        out_v->sh_degree != deg)
+        return AGS_ERR_INVALID_ARG;
+    if ((long long)out->n < 2LL * in->n) return AGS_ERR_INVALID_ARG;
+    if (lp->do_densify && in->n > 0 && (!stat_grad || !stat_count || !split_noise)) return AGS_ERR_INVALID_ARG;
+    if (!(lp->tau_opa >= 0.f && lp->tau_opa < 1.f && lp->s_min >= 0.f && lp->s_max > lp->s_min))
+        return AGS_ERR_INVALID_ARG;
+    if (lp->do_reset && !(lp->tau_reset > lp->tau_opa && lp->tau_reset < 1.f)) return AGS_ERR_INVALID_ARG;
+    if (lp->do_densify && !(lp->split_scale > 0.f)) return AGS_ERR_INVALID_ARG;
+    size_t need = 0;
+    ags_lifecycle_workspace(in->n, &need);
+    if (ws_bytes < need) return AGS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    LifecycleArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = in->n;
+    a.k3 = 3 * (deg + 1) * (deg + 1);
+    a.cap = out->n;
+    const ags_gaussians* ins[3] = {in, in_m, in_v};
+    ags_gaussians* outs[3] = {out, out_m, out_v};
+    for (int t = 0; t < 3; ++t) {
+        const float* src[5] = {ins[t]->means, ins[t]->log_scales, ins[t]->quats, ins[t]->opacity_logits,
+                               ins[t]->sh};
+        float* dst[5] = {outs[t]->means, outs[t]->log_scales, outs[t]->quats, outs[t]->opacity_logits,
+                         outs[t]->sh};
+        for (int f = 0; f < 5; ++f) {
+            a.in[t][f] = src[f];
+            a.out[t][f] = dst[f];
+        }
+    }
+    a.stat_grad = stat_grad;
+    a.stat_count = stat_count;
+    a.noise = split_noise;
+    a.do_prune = lp->do_prune != 0;
+    a.do_densify = lp->do_densify != 0;
+    a.do_reset = lp->do_reset != 0;
+    a.tau_opa = lp->tau_opa;
+    a.s_min = lp->s_min;
+    a.s_max = lp->s_max;
+    a.grad_threshold = lp->grad_threshold;
+    a.kappa = lp->kappa;
+    a.two_s_init = 2.f * lp->s_init;
+    a.tau_reset = lp->tau_reset;
+    a.reset_logit = lp->do_reset ? (float)std::log((double)lp->tau_reset / (1.0 - (double)lp->tau_reset)) : 0.f;
+    a.log_split = lp->do_densify ? (float)std::log((double)lp->split_scale) : 0.f;
+    const long long ns = in->n > 0 ? in->n : 1;
+    char* w = static_cast<char*>(ws);
+    a.counts = reinterpret_cast<uint32_t*>(w);
+    a.offsets = reinterpret_cast<uint32_t*>(w + align_up((size_t)ns * 4));
+    a.scan_tmp.block_sums = reinterpret_cast<uint32_t*>(w + 2 * align_up((size_t)ns * 4));
+    a.actions = actions_dev;
+    a.n_out = n_out_dev;
+    launch_lifecycle(a, s);
     return hip_status(ctx);
 }
 

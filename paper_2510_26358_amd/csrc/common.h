@@ -489,10 +489,31 @@ struct ProjectBwdArgs {
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
     float* pose_partials;  // [n_views * 6][2 project_bwd_blocks(n)]: geometry, then colour
     uint32_t* vis_mask;    // [n]: views keeping each Gaussian (geometry kernel -> colour kernel)
+    float* stat_grad;      // [n] or null: += |dL/d(u, v)| per view seeing the Gaussian
+    float* stat_count;     // [n] or null: += number of those views
     int accumulate;
 };
 int project_bwd_blocks(int n);
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
+
+struct LifecycleArgs {
+    int n, k3;                     // inputs, SH floats per Gaussian (3 K)
+    long long cap;                 // output capacity (row stride of the outputs)
+    const float* in[3][5];         // [params, m, v][means, log_scales, quats, logits, sh]
+    float* out[3][5];
+    const float* stat_grad;
+    const float* stat_count;
+    const float* noise;            // [n][2][3]
+    int do_prune, do_densify, do_reset;
+    float tau_opa, s_min, s_max, grad_threshold, kappa, two_s_init, tau_reset;
+    float reset_logit, log_split;
+    uint32_t* counts;              // [n] outputs per input (scratch)
+    uint32_t* offsets;             // [n] first output slot (scratch)
+    uint8_t* actions;              // [n] or null
+    int32_t* n_out;
+    ScanTemp scan_tmp;
+};
+void launch_lifecycle(const LifecycleArgs& a, hipStream_t s);
 
 struct AdamArgs {
     int n, sh_k;

@@ -67,6 +67,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
     uint32_t vmask = 0;  // views keeping this Gaussian, for the colour kernel
+    float stat_g = 0.f, stat_c = 0.f;  // densification statistic (|dL/d(u, v)| per view)
 
     for (int b = 0; b < vt.n_views; ++b) {
         const bool in_range = active && i >= vt.g_begin[b] && i < vt.g_end[b];
@@ -114,6 +115,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
             const float KA = cc * idet, KB = -cb * idet, KC = ca * idet;
             // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 with conic (a, b, c) = (KA, KB, KC)
             const float g_u = -(KA * M1 + KB * M2), g_v = -(KB * M1 + KC * M2);
+            stat_g += sqrtf(g_u * g_u + g_v * g_v);
+            stat_c += 1.f;
             const float g_a = -0.5f * M3, g_b = -M4, g_c = -0.5f * M5;
             // G' = -K G_K K
             const float p = g_a, r2 = 0.5f * g_b, s = g_c;
@@ -192,6 +195,10 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     }
     if (!active) return;
     a.vis_mask[i] = vmask;
+    if (a.stat_grad) {
+        a.stat_grad[i] += stat_g;
+        a.stat_count[i] += stat_c;
+    }
 
     // Sigma = M M^T, M = Rq diag(s): G_M = 2 G_Sigma M (G_Sigma symmetrised)
     float Rq[9];

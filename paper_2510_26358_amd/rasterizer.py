@@ -104,6 +104,16 @@ class SplatParams:
     def zeros_like(self):
         return SplatParams(*[torch.zeros_like(t) for t in self.tensors()], self.sh_degree)
 
+    @classmethod
+    def empty(cls, n: int, sh_degree: int, device="cuda"):
+        K = (sh_degree + 1) ** 2
+        e = lambda *shape: torch.empty(*shape, device=device)
+        return cls(e(3, n), e(3, n), e(4, n), e(n), e(K, 3, n), sh_degree)
+
+    def narrow(self, k: int):
+        """The first k Gaussians, as contiguous tensors."""
+        return SplatParams(*[t[..., :k].contiguous() for t in self.tensors()], self.sh_degree)
+
     def clone(self):
         return SplatParams(*[t.clone() for t in self.tensors()], self.sh_degree)
 
@@ -121,6 +131,27 @@ def cameras_tensor(cameras, device="cuda"):
         rows.append(np.concatenate([np.asarray(c.R, np.float64).reshape(9), np.asarray(c.t, np.float64),
                                     [c.fx, c.fy, c.cx, c.cy]]))
     return torch.tensor(np.array(rows), dtype=torch.float32, device=device)
+
+
+@dataclass
+class LifecycleParams:
+    """Thresholds of the lifecycle operations (see ags_lifecycle in include/agsplat.h)."""
+    do_prune: bool = True
+    do_densify: bool = True
+    do_reset: bool = False
+    tau_opa: float = 0.01
+    s_min: float = 5e-5
+    s_max: float = 0.3
+    grad_threshold: float = 0.02
+    kappa: float = 0.01
+    s_init: float = 0.005
+    tau_reset: float = 0.05
+    split_scale: float = 1.6
+
+    def c(self):
+        return L.Lifecycle(int(self.do_prune), int(self.do_densify), int(self.do_reset), self.tau_opa, self.s_min,
+                           self.s_max, self.grad_threshold, self.kappa, self.s_init, self.tau_reset,
+                           self.split_scale)
 
 
 @dataclass
@@ -265,10 +296,13 @@ class Rasterizer:
 
     def backward_into(self, params: SplatParams, cams, views: ViewSpec, buf: Buffers, out, grads,
                       pose_grad, upstream=None, loss: LossTargets | None = None, loss_out=None,
-                      accumulate=False):
+                      accumulate=False, stats=None):
+        """stats: optional (grad, count) float tensors [N] accumulating the densification
+        statistic (|dL/d(u, v)| and the number of views seeing each Gaussian)."""
         fo = _fwd_out(out)
         g = params.c()
-        gr = L.Grads(*[t.data_ptr() for t in grads.tensors()], pose_grad.data_ptr(), int(accumulate))
+        st = (None, None) if stats is None else (stats[0].data_ptr(), stats[1].data_ptr())
+        gr = L.Grads(*[t.data_ptr() for t in grads.tensors()], pose_grad.data_ptr(), int(accumulate), *st)
         up = None
         lc = None
         if upstream is not None:
@@ -283,6 +317,32 @@ class Rasterizer:
                                      C.byref(lc) if lc is not None else None, C.byref(gr),
                                      _ptr(loss_out), _ptr(buf.bwd_ws), buf.sizes.bwd_ws_bytes, _stream())
         L.check(rc, "ags_render_bwd", self.ctx)
+
+    def lifecycle(self, params: SplatParams, m: SplatParams, v: SplatParams, lp: "LifecycleParams",
+                  stats=None, noise=None, capacity: int | None = None):
+        """Prune / densify / reset (Sec. III-B lifecycle).  Returns (params, m, v, actions) with
+        the new count; the outputs are fresh tensors (capacity 2 N, trimmed after one host
+        read of the new count)."""
+        n = params.n
+        cap = capacity or max(2 * n, 1)
+        outs = [SplatParams.empty(cap, params.sh_degree, self.device) for _ in range(3)]
+        n_out = torch.zeros(1, dtype=torch.int32, device=self.device)
+        actions = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        nbytes = C.c_size_t()
+        L.check(self.lib.ags_lifecycle_workspace(n, C.byref(nbytes)), "ags_lifecycle_workspace")
+        ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
+        gi, mi, vi = params.c(), m.c(), v.c()
+        go, mo, vo = [o.c() for o in outs]
+        sg = stats[0].data_ptr() if stats is not None else None
+        sc = stats[1].data_ptr() if stats is not None else None
+        lc = lp.c()
+        rc = self.lib.ags_lifecycle_step(self.ctx, C.byref(lc), C.byref(gi), C.byref(mi), C.byref(vi), sg, sc,
+                                         noise.data_ptr() if noise is not None else None, C.byref(go),
+                                         C.byref(mo), C.byref(vo), _ptr(n_out), _ptr(actions), _ptr(ws),
+                                         ws.numel(), _stream())
+        L.check(rc, "ags_lifecycle_step", self.ctx)
+        k = int(n_out.item())
+        return tuple(o.narrow(k) for o in outs) + (actions[:n],)
 
     def bin_records(self, views: ViewSpec, n: int, records: torch.Tensor, valid: torch.Tensor,
                     buf: Buffers):

@@ -51,19 +51,23 @@ def saved_arrays(buf, views: ViewSpec):
 
 
 def run_loss_backward(scene, ras: Rasterizer, masks=None, w_l1=1.0, lam=1.0, capacity=None, ssim_w=0.0,
-                      gt=None, sigma_mode="fixed", sigma_floor=1e-4):
+                      gt=None, sigma_mode="fixed", sigma_floor=1e-4, stats=False):
     res, (p, cams, views, out, buf) = run_forward(scene, ras, capacity, depth_var=sigma_mode == "rendered")
     tg = LossTargets.from_scene(scene, views, masks=masks, w_l1=w_l1, lambda_lidar=lam, ssim_weight=ssim_w,
                                 gt=gt, sigma_mode=sigma_mode, sigma_floor=sigma_floor)
     grads = p.zeros_like()
     pose = torch.zeros(views.n_views, 6, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+    st = (torch.zeros(p.n, device="cuda"), torch.zeros(p.n, device="cuda")) if stats else None
+    ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss, stats=st)
     torch.cuda.synchronize()
     g = grads.to_numpy_aos()
     names = ["means", "log_scales", "quats", "opacity_logits", "sh"]
-    return {"loss": float(loss.item()), "grads": dict(zip(names, g)), "pose": pose.cpu().numpy(),
-            "fwd": res, "buf": buf, "views": views}
+    r = {"loss": float(loss.item()), "grads": dict(zip(names, g)), "pose": pose.cpu().numpy(),
+         "fwd": res, "buf": buf, "views": views}
+    if stats:
+        r["stats"] = {"grad_accum": st[0].cpu().numpy(), "count": st[1].cpu().numpy()}
+    return r
 
 
 def grad_close(gpu, ref, exclude=None, rel=TOL_GRAD, frac=0.999):
