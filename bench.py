@@ -105,6 +105,73 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def measure_lifecycle(ras, p, cams, views, buf, out, grads, pose, tg, loss, args, t_b):
+    """The step with the densification statistic accumulated by the backward, then the
+    lifecycle pass over all Gaussians with that statistic (paper thresholds), timed on its own
+    (HIP events around the pass); the pass is HBM-bound: algorithmic bytes = the parameters and
+    both Adam moments read once per input and written once per output, plus the statistic,
+    the split noise of split parents and the action bytes."""
+    import torch
+    from paper_2510_26358_amd.rasterizer import LifecycleParams, SplatParams
+    n, K = p.n, (p.sh_degree + 1) ** 2
+    stats = (torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
+
+    def step_st():
+        ras.forward_into(p, cams, views, buf, out)
+        ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss, stats=stats)
+
+    timed = step_st
+    if not args.no_graph:
+        for _ in range(args.warmup):
+            step_st()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step_st()
+        timed = g.replay
+    t_st = time_steps(timed, args.steps, args.warmup)
+    log(f"[bench] step accumulating the densification statistic: {t_st * 1e3:.3f} ms/step "
+        f"(+{(t_st - t_b) * 1e6:.1f} us)")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4242)
+    m = SplatParams(*[torch.randn(t.shape, device="cuda", generator=gen) for t in p.tensors()], p.sh_degree)
+    v = SplatParams(*[torch.rand(t.shape, device="cuda", generator=gen) for t in p.tensors()], p.sh_degree)
+    noise = torch.randn(n, 2, 3, device="cuda", generator=gen)
+    outs = [SplatParams.empty(2 * n, p.sh_degree) for _ in range(3)]
+    n_out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    actions = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ras.lifecycle_workspace(n), dtype=torch.uint8, device="cuda")
+    lp = LifecycleParams(do_reset=True)
+
+    def run():
+        ras.lifecycle_into(p, m, v, lp, outs, n_out, actions, ws, stats=stats, noise=noise)
+
+    for _ in range(args.warmup):
+        run()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    k = int(n_out.item())
+    hist = torch.bincount(actions.to(torch.int64), minlength=4).cpu().tolist()
+    row_bytes = 4 * (11 + 3 * K)
+    nbytes = 3 * row_bytes * (n + k) + 8 * n + n + 24 * hist[3]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {"ms_per_step_with_statistic": round(t_st * 1e3, 4),
+           "statistic_overhead_us": round((t_st - t_b) * 1e6, 1),
+           "n_in": n, "n_out": k, "keep": hist[0], "prune": hist[1], "duplicate": hist[2], "split": hist[3],
+           "pass_ms": round(ms, 4),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_pass": nbytes}}
+    log(f"[bench] lifecycle pass over {n} Gaussians -> {k}: {ms:.4f} ms, {gbs:.0f} GB/s ({res})")
+    del outs, m, v
+    return res
+
+
 def _source_digest(stage):
     import hashlib
     src = {"raster_bwd": "raster.hip", "raster_fwd": "raster.hip", "project_bwd": "project_bwd.hip",
@@ -253,6 +320,9 @@ def main():
     ap.add_argument("--rendered-variance", type=float, default=1e-4, metavar="FLOOR",
                     help="also time the step with the rendered-variance LiDAR term (this variance floor, "
                          "m^2; 0: skip)")
+    ap.add_argument("--lifecycle", type=int, default=1,
+                    help="also time the step accumulating the densification statistic and one lifecycle "
+                         "pass (prune / split / duplicate / reset) over the Gaussians (0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -411,6 +481,10 @@ def main():
         tg.sigma_mode = "fixed"
         del out_v
 
+    lifecycle = None
+    if args.lifecycle and refiner is None:
+        lifecycle = measure_lifecycle(ras, p, cams, views, buf, out, grads, pose, tg, loss, args, t_b)
+
     loop = None
     if not args.no_loop and views.n_views > 1 and refiner is None:
         from paper_2510_26358_amd.rasterizer import LossTargets
@@ -462,7 +536,7 @@ def main():
                    "autotuned": None if tuned is None else tuned["ms"],
                    "visible_pairs": V, "intersections": K},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
-        "with_ssim": with_ssim, "with_rendered_variance": with_rv,
+        "with_ssim": with_ssim, "with_rendered_variance": with_rv, "lifecycle": lifecycle,
     }
     print(json.dumps(rec), flush=True)
 

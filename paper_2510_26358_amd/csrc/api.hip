@@ -26,11 +26,13 @@ enum Stage {
     ST_ADAM,
     ST_POSE,
     ST_SSIM,
+    ST_LIFECYCLE,
     ST_COUNT
 };
 static const char* kStageNames[ST_COUNT] = {"project_fwd", "binning",     "raster_fwd",
                                              "lidar_adjoint", "raster_bwd", "project_bwd",
-                                             "clear",       "adam",        "pose_step", "ssim"};
+                                             "clear",       "adam",        "pose_step", "ssim",
+                                             "lifecycle"};
 
 struct ags_ctx {
     int device;
@@ -718,6 +720,7 @@ int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussian
     a.scan_tmp.block_sums = reinterpret_cast<uint32_t*>(w + 2 * align_up((size_t)ns * 4));
     a.actions = actions_dev;
     a.n_out = n_out_dev;
+    Scope sc(ctx, ST_LIFECYCLE, s);
     launch_lifecycle(a, s);
     return hip_status(ctx);
 }

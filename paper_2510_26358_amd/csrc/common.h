@@ -498,6 +498,7 @@ void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
 
 struct LifecycleArgs {
     int n, k3;                     // inputs, SH floats per Gaussian (3 K)
+    int chunks;                    // scatter launch rows per array (set by launch_lifecycle)
     long long cap;                 // output capacity (row stride of the outputs)
     const float* in[3][5];         // [params, m, v][means, log_scales, quats, logits, sh]
     float* out[3][5];

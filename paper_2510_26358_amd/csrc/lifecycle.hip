@@ -6,9 +6,10 @@
 // 1. classify: one thread per Gaussian decides keep / prune / duplicate / split (float32,
 //    the rules of ags_lifecycle in agsplat.h) and its number of outputs (0, 1 or 2);
 // 2. exclusive scan of the output counts -> first output slot, total -> *n_out;
-// 3. scatter: one thread per surviving Gaussian writes its outputs into every row of the
-//    output arrays; split children get mu + R(q) diag(s) eps and log-scales - ln(split_scale),
-//    copies and children zero Adam moments, survivors keep theirs.
+// 3. scatter: a thread per surviving Gaussian and group of rows (of the parameters or one of
+//    the moment arrays) loads the rows, then writes the Gaussian's outputs; split children get
+//    mu + R(q) diag(s) eps and log-scales - ln(split_scale), copies and children zero Adam
+//    moments, survivors keep theirs.
 #include "common.h"
 
 namespace ags {
@@ -36,7 +37,35 @@ __global__ void lifecycle_classify_kernel(LifecycleArgs a) {
     if (a.actions) a.actions[i] = (uint8_t)act;
 }
 
-__global__ void lifecycle_scatter_kernel(LifecycleArgs a) {
+constexpr int kLcRows = 16;  // SH rows one thread moves per launch row
+
+// Split flag of a Gaussian with two outputs (duplicate and split differ only by size).
+__device__ __forceinline__ bool lc_is_split(const LifecycleArgs& a, int i) {
+    const float* ls = a.in[0][1];
+    const int n = a.n;
+    return expf(fmaxf(fmaxf(ls[i], ls[n + i]), ls[2 * n + i])) > a.kappa;
+}
+
+// Copies `rows` rows (row stride n in, cap out) of one field for Gaussian i: all loads are
+// issued before the first store (the row index is clamped, not branched on).
+template <int R>
+__device__ __forceinline__ void lc_copy(const float* __restrict__ src, float* __restrict__ dst, int rows, int n,
+                                        long long cap, int i, long long j0, uint32_t cnt, bool zero0, bool zero1) {
+    float v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[(long long)(r < rows ? r : rows - 1) * n + i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r < rows) {
+            dst[(long long)r * cap + j0] = zero0 ? 0.f : v[r];
+            if (cnt == 2) dst[(long long)r * cap + j0 + 1] = zero1 ? 0.f : v[r];
+        }
+    }
+}
+
+// grid (ceil(n / 256), 3 * lc_chunks): blockIdx.y = array (params, m, v) x chunk, chunk 0 =
+// means / log-scales / quaternion / logit, chunks 1.. = SH rows in groups of kLcRows.
+__global__ __launch_bounds__(256) void lifecycle_scatter_kernel(LifecycleArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const uint32_t cnt = a.counts[i];
@@ -44,45 +73,66 @@ __global__ void lifecycle_scatter_kernel(LifecycleArgs a) {
     const int n = a.n;
     const long long cap = a.cap;
     const long long j0 = a.offsets[i];
-    const float* ls = a.in[0][1];
-    const float o = 1.f / (1.f + expf(-a.in[0][3][i]));
-    const float smax = expf(fmaxf(fmaxf(ls[i], ls[n + i]), ls[2 * n + i]));
-    const bool reset = a.do_reset && o >= a.tau_opa && o < a.tau_reset && smax >= a.s_min && smax <= a.s_max;
-    const float logit = reset ? a.reset_logit : a.in[0][3][i];
-    bool split = false;
-    if (cnt == 2) {  // duplicate or split: the size test tells them apart as in classify
-        split = smax > a.kappa;
-    }
-    // rows: [0] means (3), [1] log_scales (3), [2] quats (4), [3] logits (1), [4] sh (k3)
-    const int rows[5] = {3, 3, 4, 1, a.k3};
-    for (uint32_t c = 0; c < cnt; ++c) {
-        const long long j = j0 + c;
-        const bool fresh = c == 1 || split;  // copies and children start with zero moments
-        for (int f = 0; f < 5; ++f) {
-            for (int r = 0; r < rows[f]; ++r) {
-                float val = a.in[0][f][(long long)r * n + i];
-                if (f == 3) val = logit;
-                a.out[0][f][(long long)r * cap + j] = val;
-                a.out[1][f][(long long)r * cap + j] = fresh ? 0.f : a.in[1][f][(long long)r * n + i];
-                a.out[2][f][(long long)r * cap + j] = fresh ? 0.f : a.in[2][f][(long long)r * n + i];
-            }
-        }
+    const int t = blockIdx.y / a.chunks, c = blockIdx.y % a.chunks;
+    if (t == 0 && c == 0) {
+        // parameters: split children and the opacity reset
+        const float* ls = a.in[0][1];
+        const float* mu = a.in[0][0];
+        const float* q = a.in[0][2];
+        const float l0 = ls[i], l1 = ls[n + i], l2 = ls[2 * n + i];
+        const float m0 = mu[i], m1 = mu[n + i], m2 = mu[2 * n + i];
+        const float qw = q[i], qx = q[n + i], qy = q[2 * n + i], qz = q[3 * n + i];
+        const float lg = a.in[0][3][i];
+        const float o = 1.f / (1.f + expf(-lg));
+        const float smax = expf(fmaxf(fmaxf(l0, l1), l2));
+        const bool reset = a.do_reset && o >= a.tau_opa && o < a.tau_reset && smax >= a.s_min && smax <= a.s_max;
+        const float logit = reset ? a.reset_logit : lg;
+        const bool split = cnt == 2 && smax > a.kappa;
+        float* const* out = a.out[0];
+        float mo[2][3] = {{m0, m1, m2}, {m0, m1, m2}};
+        float lo[3] = {l0, l1, l2};
         if (split) {
-            const float* q = a.in[0][2];
-            float qw = q[i], qx = q[n + i], qy = q[2 * n + i], qz = q[3 * n + i];
             const float qi = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
             float R[9];
             quat_to_rot(qw * qi, qx * qi, qy * qi, qz * qi, R);
-            const float sc[3] = {expf(ls[i]), expf(ls[n + i]), expf(ls[2 * n + i])};
-            const float* e = a.noise + ((long long)i * 2 + c) * 3;
-            const float d[3] = {sc[0] * e[0], sc[1] * e[1], sc[2] * e[2]};
-            for (int r = 0; r < 3; ++r) {
-                a.out[0][0][(long long)r * cap + j] =
-                    a.in[0][0][(long long)r * n + i] + R[3 * r] * d[0] + R[3 * r + 1] * d[1] + R[3 * r + 2] * d[2];
-                a.out[0][1][(long long)r * cap + j] = ls[(long long)r * n + i] - a.log_split;
+            const float sc[3] = {expf(l0), expf(l1), expf(l2)};
+            const float* e = a.noise + (long long)i * 6;
+            for (int k = 0; k < 2; ++k) {
+                const float d[3] = {sc[0] * e[3 * k], sc[1] * e[3 * k + 1], sc[2] * e[3 * k + 2]};
+                for (int r = 0; r < 3; ++r)
+                    mo[k][r] += R[3 * r] * d[0] + R[3 * r + 1] * d[1] + R[3 * r + 2] * d[2];
             }
+            for (int r = 0; r < 3; ++r) lo[r] -= a.log_split;
         }
+        const float qv[4] = {qw, qx, qy, qz};
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const long long j = j0 + k;
+            for (int r = 0; r < 3; ++r) {
+                out[0][r * cap + j] = mo[k][r];
+                out[1][r * cap + j] = lo[r];
+            }
+            for (int r = 0; r < 4; ++r) out[2][r * cap + j] = qv[r];
+            out[3][j] = logit;
+        }
+        return;
     }
+    // copies and children start with zero Adam moments; survivors keep theirs
+    bool zero0 = false, zero1 = false;
+    if (t > 0 && cnt == 2) {
+        zero1 = true;
+        zero0 = lc_is_split(a, i);
+    }
+    if (c == 0) {
+        const int rows[4] = {3, 3, 4, 1};
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            lc_copy<4>(a.in[t][f], a.out[t][f], rows[f], n, cap, i, j0, cnt, zero0, zero1);
+        return;
+    }
+    const int r0 = (c - 1) * kLcRows;
+    const int rows = a.k3 - r0 < kLcRows ? a.k3 - r0 : kLcRows;
+    lc_copy<kLcRows>(a.in[t][4] + (long long)r0 * n, a.out[t][4] + (long long)r0 * cap, rows, n, cap, i, j0, cnt,
+                     zero0, zero1);
 }
 
 void launch_lifecycle(const LifecycleArgs& a, hipStream_t s) {
@@ -94,7 +144,9 @@ void launch_lifecycle(const LifecycleArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(lifecycle_classify_kernel, dim3(grid), dim3(256), 0, s, a);
     launch_scan(a.counts, nullptr, false, a.offsets, a.n, nullptr, reinterpret_cast<uint32_t*>(a.n_out),
                 a.scan_tmp, s);
-    hipLaunchKernelGGL(lifecycle_scatter_kernel, dim3(grid), dim3(256), 0, s, a);
+    LifecycleArgs b = a;
+    b.chunks = 1 + (a.k3 + kLcRows - 1) / kLcRows;
+    hipLaunchKernelGGL(lifecycle_scatter_kernel, dim3(grid, 3 * b.chunks), dim3(256), 0, s, b);
 }
 
 }  // namespace ags

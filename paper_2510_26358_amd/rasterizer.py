@@ -318,6 +318,28 @@ class Rasterizer:
                                      _ptr(loss_out), _ptr(buf.bwd_ws), buf.sizes.bwd_ws_bytes, _stream())
         L.check(rc, "ags_render_bwd", self.ctx)
 
+    def lifecycle_workspace(self, n: int) -> int:
+        nbytes = C.c_size_t()
+        L.check(self.lib.ags_lifecycle_workspace(n, C.byref(nbytes)), "ags_lifecycle_workspace")
+        return int(nbytes.value)
+
+    def lifecycle_into(self, params: SplatParams, m: SplatParams, v: SplatParams, lp: "LifecycleParams",
+                       outs, n_out: torch.Tensor, actions: torch.Tensor | None, ws: torch.Tensor,
+                       stats=None, noise=None):
+        """One lifecycle pass into preallocated outputs (outs: three SplatParams of capacity
+        >= 2 N; n_out: int32 [1]; ws: lifecycle_workspace(N) bytes).  No allocation, no sync."""
+        gi, mi, vi = params.c(), m.c(), v.c()
+        go, mo, vo = [o.c() for o in outs]
+        sg = stats[0].data_ptr() if stats is not None else None
+        sc = stats[1].data_ptr() if stats is not None else None
+        lc = lp.c()
+        rc = self.lib.ags_lifecycle_step(self.ctx, C.byref(lc), C.byref(gi), C.byref(mi), C.byref(vi), sg, sc,
+                                         noise.data_ptr() if noise is not None else None, C.byref(go),
+                                         C.byref(mo), C.byref(vo), _ptr(n_out),
+                                         _ptr(actions) if actions is not None else None, _ptr(ws), ws.numel(),
+                                         _stream())
+        L.check(rc, "ags_lifecycle_step", self.ctx)
+
     def lifecycle(self, params: SplatParams, m: SplatParams, v: SplatParams, lp: "LifecycleParams",
                   stats=None, noise=None, capacity: int | None = None):
         """Prune / densify / reset (Sec. III-B lifecycle).  Returns (params, m, v, actions) with
@@ -328,19 +350,8 @@ class Rasterizer:
         outs = [SplatParams.empty(cap, params.sh_degree, self.device) for _ in range(3)]
         n_out = torch.zeros(1, dtype=torch.int32, device=self.device)
         actions = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
-        nbytes = C.c_size_t()
-        L.check(self.lib.ags_lifecycle_workspace(n, C.byref(nbytes)), "ags_lifecycle_workspace")
-        ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
-        gi, mi, vi = params.c(), m.c(), v.c()
-        go, mo, vo = [o.c() for o in outs]
-        sg = stats[0].data_ptr() if stats is not None else None
-        sc = stats[1].data_ptr() if stats is not None else None
-        lc = lp.c()
-        rc = self.lib.ags_lifecycle_step(self.ctx, C.byref(lc), C.byref(gi), C.byref(mi), C.byref(vi), sg, sc,
-                                         noise.data_ptr() if noise is not None else None, C.byref(go),
-                                         C.byref(mo), C.byref(vo), _ptr(n_out), _ptr(actions), _ptr(ws),
-                                         ws.numel(), _stream())
-        L.check(rc, "ags_lifecycle_step", self.ctx)
+        ws = torch.empty(max(self.lifecycle_workspace(n), 1), dtype=torch.uint8, device=self.device)
+        self.lifecycle_into(params, m, v, lp, outs, n_out, actions, ws, stats=stats, noise=noise)
         k = int(n_out.item())
         return tuple(o.narrow(k) for o in outs) + (actions[:n],)
 
