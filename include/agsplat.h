@@ -280,7 +280,7 @@ int ags_profile_reset(ags_ctx* ctx);
  *                       ln(split_scale), quaternion / opacity / SH copied;
  *   duplicate           else if that gradient test holds and s_i <= 2 s_init: the original and
  *                       an exact copy;
- *   opacity reset (do_reset) if not pruned, tau_opa <= o_i < tau_reset and s_min <= s_i <= s_max:
+ *   opacity reset (do_reset) if not pruned, tau_opa <= o_i < tau_reset and s_min < s_i < s_max:
  *                       the logit of every output of i becomes logit(tau_reset).
  * Decisions are taken in float32.  Outputs keep input order (a Gaussian's outputs are
  * consecutive); the Adam moments of copies and children are 0, survivors keep theirs. */

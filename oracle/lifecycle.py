@@ -11,7 +11,7 @@ s_init, tau_reset and the split rule unstated; the readings (recorded in DESIGN.
   * else, if g_j > gamma_g: split if s_j > kappa (two children at mu + R(q) diag(s) eps_k with
     the given standard-normal eps_k, log-scales reduced by ln(split_scale), the rest copied);
     duplicate if s_j <= 2 s_init (the original and an exact copy);
-  * opacity reset: if tau_opa <= o_j < tau_reset and s_min <= s_j <= s_max, the logit becomes
+  * opacity reset: if tau_opa <= o_j < tau_reset and s_min < s_j < s_max, the logit becomes
     logit(tau_reset) (in every output of j);
   * outputs keep input order (children and copies right after their parent's slot); the
     optimiser moments of new Gaussians (copies, children) are zero, survivors keep theirs.
@@ -66,7 +66,7 @@ def classify(log_scales, logits, grad_accum, count, lp: LifecycleParams):
         act[hot & ~(s > f(lp.kappa)) & (s <= f(2 * lp.s_init))] = CLONE
     reset = np.zeros(len(o), bool)
     if lp.do_reset:
-        reset = (act != PRUNE) & (o >= f(lp.tau_opa)) & (o < f(lp.tau_reset)) & (s >= f(lp.s_min)) & (s <= f(lp.s_max))
+        reset = (act != PRUNE) & (o >= f(lp.tau_opa)) & (o < f(lp.tau_reset)) & (s > f(lp.s_min)) & (s < f(lp.s_max))
     return act, reset
 
 

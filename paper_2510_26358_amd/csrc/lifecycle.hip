@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void lifecycle_scatter_kernel(LifecycleArgs a)
         const float lg = a.in[0][3][i];
         const float o = 1.f / (1.f + expf(-lg));
         const float smax = expf(fmaxf(fmaxf(l0, l1), l2));
-        const bool reset = a.do_reset && o >= a.tau_opa && o < a.tau_reset && smax >= a.s_min && smax <= a.s_max;
+        const bool reset = a.do_reset && o >= a.tau_opa && o < a.tau_reset && smax > a.s_min && smax < a.s_max;
         const float logit = reset ? a.reset_logit : lg;
         const bool split = cnt == 2 && smax > a.kappa;
         float* const* out = a.out[0];
