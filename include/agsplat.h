@@ -302,14 +302,89 @@ int ags_lifecycle_workspace(int64_t n, size_t* bytes);
  * `out` / `out_m` / `out_v` (distinct buffers, same sh_degree, room for out_capacity >= 2 n
  * Gaussians: their `n` fields give the capacity).  stat_grad / stat_count: the statistic
  * above, device float[n] each; split_noise: device float[n][2][3]; all three are required
- * when do_densify != 0 and n > 0, and ignored otherwise.  Writes the new count to *n_out_dev (device int32) and, if non-null, the action of
- * each input to actions_dev[n] (0 keep, 1 prune, 2 duplicate, 3 split).  No host sync, no
+ * when do_densify != 0 and n > 0, and ignored otherwise.  Writes the new count to *n_out_dev
+ * (device int32) and, if non-null, the action of each input to actions_dev[n] (0 keep,
+ * 1 prune, 2 duplicate, 3 split).  No host sync, no
  * allocation.  INVALID_ARG for bad pointers, sizes or thresholds, WORKSPACE_TOO_SMALL. */
 int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in,
                        const ags_gaussians* in_m, const ags_gaussians* in_v, const float* stat_grad,
                        const float* stat_count, const float* split_noise, ags_gaussians* out,
                        ags_gaussians* out_m, ags_gaussians* out_v, int32_t* n_out_dev,
                        uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Voxel-hashed Gaussian map with a bounded GPU-resident set (Sec. III-B "Incremental
+ * Gaussian Mapping": the voxel key equation; "Memory Management": least-recently-used
+ * offload to host memory above a threshold tau, reload when a key is met again).
+ *
+ * Key of a point p: c = floor(p / v) per axis (float32 division and floor), k = (c_x P1 +
+ * c_y P2 + c_z P3) mod 2^64; equal keys are one splat (two voxels whose keys collide are
+ * merged); the key 2^64 - 1 is reserved and becomes 2^64 - 2.  |p / v| must stay below 2^62.
+ * An insertion call takes its points in order: a known key marks its splat used; a new key
+ * makes one splat from the first point carrying it (mean p, log-scales ln s_init, identity
+ * quaternion, logit of o_init, SH DC (rgb - 1/2) / Y_0^0, other SH and Adam moments 0), ids
+ * counting up in that order.  Every splat met by call t gets last_used = t.  The resident set
+ * (the rows the caller renders and optimises) is rebuilt as: the input rows in order, then
+ * the call's new splats (id order), then the splats it met that were offloaded (reloaded from
+ * the host store, id order); while more than tau rows remain, the least recently used
+ * (smallest last_used, ties: earlier row) are offloaded to the host store with their current
+ * values, the others keeping their order. */
+typedef struct ags_map ags_map;
+
+typedef struct ags_map_config {
+    float voxel;           /* v, metres, > 0 */
+    float s_init;          /* new splat: scale (all axes), > 0 */
+    float o_init;          /* new splat: opacity, in (0, 1) */
+    int32_t sh_degree;     /* 0..3 */
+    uint64_t prime[3];     /* P1, P2, P3 */
+    int64_t max_ids;       /* splats the map can ever hold, <= 2^30 */
+    int64_t max_points;    /* points per insertion call, <= 2^28 */
+    int64_t tau;           /* resident-set bound, >= 1 */
+} ags_map_config;
+
+typedef struct ags_map_counts {
+    int64_t n_ids;         /* splats in the map after the call */
+    int64_t n_resident;    /* rows of the output resident set */
+    int64_t n_new, n_reloaded, n_evicted;
+} ags_map_counts;
+
+/* voxel 0.05, s_init 0.005, o_init 0.1, degree 3, primes 73856093, 19349663, 83492791,
+ * max_ids 2^22, max_points 2^20, tau 2^20. */
+int ags_map_config_default(ags_map_config* cfg);
+
+/* Allocates the map on ctx's device: the hash table (open addressing, 2^ceil(log2(2 max_ids))
+ * slots of 16 B), per-id key / last_used / residency (13 B), per-point and per-row scratch,
+ * device and pinned host staging of max_points rows, and the host store (max_ids rows of
+ * 3 x 4 x (11 + 3 (deg+1)^2) bytes, committed as rows are offloaded).  destroy frees it all. */
+int ags_map_create(ags_ctx* ctx, const ags_map_config* cfg, ags_map** out);
+int ags_map_destroy(ags_map* map);
+
+/* One insertion call (number `frame`, non-decreasing over calls, >= 0).  points / colors:
+ * device float[n_points][3] (xyz; rgb in [0, 1]).  in / in_m / in_v / in_ids: the resident set
+ * this map returned last (values may have changed, not rows or order; n = 0 before the
+ * first call; in->n <= tau).  out / out_m / out_v / out_ids: other buffers receiving the new
+ * resident set, packed with row stride counts->n_resident; their `n` gives the capacity in
+ * rows, which must be >= min(in->n + n_points, tau).  point_id: device int32[n_points] (or
+ * NULL): the splat id of each point.  evicted_ids: device int32[n_points] (or NULL): the ids
+ * offloaded by this call, in row order.  Host-synchronous: returns after the stream's work
+ * (two synchronisations: the reload list, then the offloaded rows).  INVALID_ARG for bad
+ * pointers or sizes, CAPACITY when n_ids + n_points > max_ids (nothing changed). */
+int ags_map_insert(ags_map* map, const float* points, const float* colors, int64_t n_points, int32_t frame,
+                   const ags_gaussians* in, const ags_gaussians* in_m, const ags_gaussians* in_v,
+                   const int32_t* in_ids, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
+                   int32_t* out_ids, int32_t* point_id, int32_t* evicted_ids, ags_map_counts* counts,
+                   void* stream);
+
+/* Copies per-id state to host memory (any pointer may be NULL): keys[n_ids], last_used[n_ids],
+ * resident[n_ids] (1 on the GPU, 0 in the host store); and, for table_slots (>= the table's
+ * slot count, reported in *n_slots), the table's keys and ids (empty slot: key 2^64 - 1,
+ * id -1).  Synchronous. */
+int ags_map_export(ags_map* map, uint64_t* keys, int32_t* last_used, uint8_t* resident, uint64_t* table_keys,
+                   int32_t* table_ids, int64_t table_slots, int64_t* n_ids, int64_t* n_slots);
+
+/* Rows of offloaded ids from the host store into host memory rows[n][3 F] (F = 11 + 3 (deg+1)^2:
+ * parameters, then Adam m, then v; each as means 3, log-scales 3, quaternion 4, logit 1,
+ * SH (deg+1)^2 x 3).  INVALID_ARG if an id is out of range or resident. */
+int ags_map_read_store(ags_map* map, const int32_t* ids, int64_t n, float* rows);
 
 #ifdef __cplusplus
 }

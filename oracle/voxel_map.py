@@ -57,16 +57,30 @@ def voxel_key(cell, primes):
     return EMPTY_KEY - 1 if k == EMPTY_KEY else k
 
 
+def voxel_keys(points, vp: VoxelMapParams):
+    """Keys of many points at once (uint64 arithmetic wraps modulo 2^64)."""
+    c = voxel_cells(points, vp.voxel).astype(np.uint64)
+    P = np.asarray(vp.primes, np.uint64)
+    with np.errstate(over="ignore"):
+        k = c[:, 0] * P[0] + c[:, 1] * P[1] + c[:, 2] * P[2]
+    k[k == np.uint64(EMPTY_KEY)] = np.uint64(EMPTY_KEY - 1)
+    return k
+
+
 def new_splat(point, rgb, vp: VoxelMapParams):
-    """Row of a splat instantiated from one point: parameters, Adam moments (zero)."""
+    """Row of a splat instantiated from one point: parameters, Adam moments (zero).  s_init and
+    o_init are taken at float32 (the precision a configuration holds them in), their
+    logarithms in float64 and rounded to float32."""
     f = np.float32
     K = (vp.sh_degree + 1) ** 2
     sh = np.zeros((K, 3), np.float32)
     sh[0] = (np.asarray(rgb, np.float32) - f(0.5)) / f(SH_C0)
+    s0 = float(f(vp.s_init))
+    o0 = float(f(vp.o_init))
     p = {"means": np.asarray(point, np.float32).copy(),
-         "log_scales": np.full(3, np.float32(np.log(vp.s_init)), np.float32),
+         "log_scales": np.full(3, f(np.log(s0)), np.float32),
          "quats": np.array([1, 0, 0, 0], np.float32),
-         "opacity_logits": np.array([np.float32(np.log(vp.o_init / (1 - vp.o_init)))], np.float32),
+         "opacity_logits": np.array([f(np.log(o0 / (1 - o0)))], np.float32),
          "sh": sh}
     zero = {k: np.zeros_like(a) for k, a in p.items()}
     return {"params": p, "m": zero, "v": {k: a.copy() for k, a in zero.items()}}

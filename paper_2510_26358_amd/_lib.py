@@ -24,7 +24,8 @@ EXPORTED = [
     "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
     "ags_render_fwd", "ags_render_bwd", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
-    "ags_lifecycle_step",
+    "ags_lifecycle_step", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
+    "ags_map_export", "ags_map_read_store",
 ]
 
 
@@ -51,6 +52,16 @@ class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("pose", C.c_void_p),
                 ("accumulate", C.c_int32), ("stat_grad", C.c_void_p), ("stat_count", C.c_void_p)]
+
+
+class MapConfig(C.Structure):
+    _fields_ = [("voxel", C.c_float), ("s_init", C.c_float), ("o_init", C.c_float), ("sh_degree", C.c_int32),
+                ("prime", C.c_uint64 * 3), ("max_ids", C.c_int64), ("max_points", C.c_int64), ("tau", C.c_int64)]
+
+
+class MapCounts(C.Structure):
+    _fields_ = [("n_ids", C.c_int64), ("n_resident", C.c_int64), ("n_new", C.c_int64),
+                ("n_reloaded", C.c_int64), ("n_evicted", C.c_int64)]
 
 
 class Lifecycle(C.Structure):
@@ -136,6 +147,13 @@ def load(path: str = LIB_PATH):
     lib.ags_profile_enable.argtypes = [vp, C.c_int]
     lib.ags_profile_read.argtypes = [vp, C.c_int, P(C.c_char_p), P(C.c_double), P(C.c_int64), P(C.c_int)]
     lib.ags_profile_reset.argtypes = [vp]
+    lib.ags_map_config_default.argtypes = [P(MapConfig)]
+    lib.ags_map_create.argtypes = [vp, P(MapConfig), P(vp)]
+    lib.ags_map_destroy.argtypes = [vp]
+    lib.ags_map_insert.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, P(Gaussians), P(Gaussians), P(Gaussians), vp,
+                                   P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, P(MapCounts), vp]
+    lib.ags_map_export.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, P(C.c_int64), P(C.c_int64)]
+    lib.ags_map_read_store.argtypes = [vp, vp, C.c_int64, vp]
     lib.ags_lifecycle_workspace.argtypes = [C.c_int64, P(C.c_size_t)]
     lib.ags_lifecycle_step.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp,
                                        P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, C.c_size_t, vp]

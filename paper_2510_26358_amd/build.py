@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libagsplat.so")
 ARCH = os.environ.get("AGS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "project.hip", "sortscan.hip", "bin.hip", "raster.hip", "loss.hip",
-           "project_bwd.hip", "optim.hip", "ssim.hip", "lifecycle.hip"]
+           "project_bwd.hip", "optim.hip", "ssim.hip", "lifecycle.hip", "map.hip"]
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
           "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result",

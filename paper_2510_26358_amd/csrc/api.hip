@@ -275,6 +275,14 @@ int run_binning(BinArgs a, hipStream_t s) { return launch_binning(a, s); }
 
 }  // namespace
 
+namespace ags {
+int ctx_device(const ags_ctx* ctx) { return ctx->device; }
+int ctx_record_hip(ags_ctx* ctx, hipError_t e) {
+    if (ctx) ctx->last_hip = (int)(e != hipSuccess ? e : hipErrorUnknown);
+    return AGS_ERR_HIP;
+}
+}  // namespace ags
+
 extern "C" {
 
 int ags_version(void) { return AGS_ABI_VERSION; }

@@ -516,6 +516,11 @@ struct LifecycleArgs {
 };
 void launch_lifecycle(const LifecycleArgs& a, hipStream_t s);
 
+// Context access for sources other than the context's own: its device, and recording a
+// failed HIP call (returns AGS_ERR_HIP).
+int ctx_device(const ags_ctx* ctx);
+int ctx_record_hip(ags_ctx* ctx, hipError_t e);
+
 struct AdamArgs {
     int n, sh_k;
     float* p[5];

@@ -1,0 +1,646 @@
+// Voxel-hashed Gaussian map with a bounded GPU-resident set (Sec. III-B, "Incremental
+// Gaussian Mapping": the voxel key equation; "Memory Management": least-recently-used offload
+// to host memory above a threshold, reload when a key is met again).  The rules are stated
+// with ags_map_insert in agsplat.h.
+//
+// Device state: an open-addressing table (linear probing from the MurmurHash3 64-bit
+// finaliser of the key; slots never removed) of 64-bit keys and int32 ids, with an int32
+// claim word per slot; per id its key, last_used call and residency.  One insertion call:
+//   1. probe: key per point, find or claim (64-bit CAS) its slot; points of a key new in
+//      this call take the smallest point index on the slot's claim word (atomicMin);
+//   2. flag + scan: a point is the first of a new key when the slot is unassigned and its
+//      claim holds the point's index; the scan numbers the new keys in point order;
+//   3. assign: new ids, slot values, new-splat sources; touch: point ids, last_used, and a
+//      reload mark for every offloaded id met; the marks are compacted in id order;
+//   4. host: reload rows gathered from the host store through pinned staging;
+//   5. if more than tau rows are listed: stable radix sort of the listed rows by last_used,
+//      the first (listed - tau) rows are offloaded;
+//   6. rebuild: one launch writes the new resident set (packed, row stride = its size) and the
+//      offloaded rows (device staging, then pinned host memory and the host store).
+#include <limits.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+struct ags_map {
+    ags_ctx* ctx;
+    ags_map_config cfg;
+    int device;
+    int F;                         // floats per splat and array (11 + 3 K)
+    long long slots;               // table slots (power of two)
+    long long list_max;            // tau + max_points
+    long long n_ids;
+    int last_frame;
+    float ln_s_init, logit_init;
+    // device
+    unsigned long long* tab_keys;
+    int* tab_vals;
+    int* tab_claim;
+    unsigned long long* id_key;
+    int* id_last;
+    uint8_t* id_res;
+    uint32_t* reload_mark;
+    uint32_t* slot;                // [max_points]
+    uint32_t* newf;                // [max_points]
+    uint32_t* rank;                // [max_points]
+    uint32_t* new_point;           // [max_points]
+    uint32_t* reload_pos;          // [max_ids]
+    uint32_t* reload_list;         // [max_points]
+    uint32_t* keys[2];             // [list_max]
+    uint32_t* vals[2];             // [list_max]
+    uint32_t* evict_flag;          // [list_max]
+    uint32_t* evict_pos;           // [list_max]
+    int32_t* evict_ids;            // [max_points]
+    uint32_t* counters;            // [4]
+    uint32_t* block_sums;
+    uint32_t* hist;
+    uint32_t* rowtot;
+    float* stage_in;               // [max_points][3 F] reloaded rows
+    float* stage_out;              // [max_points][3 F] offloaded rows
+    // host
+    float* pinned;                 // [max_points][3 F]
+    float* store;                  // [max_ids][3 F]
+    std::vector<uint32_t> h_list;
+    std::vector<int32_t> h_evicted;
+};
+
+namespace ags {
+
+constexpr unsigned long long kEmptyKey = ~0ULL;
+constexpr float kShC0 = 0.28209479177387814f;  // Y_0^0 = 1 / (2 sqrt(pi))
+constexpr int kMapThreads = 256;
+constexpr int kMapRows = 16;                   // SH rows per rebuild launch row
+
+struct MapDev {
+    unsigned long long* tab_keys;
+    int* tab_vals;
+    int* tab_claim;
+    unsigned long long mask;
+    unsigned long long* id_key;
+    int* id_last;
+    uint8_t* id_res;
+    uint32_t* reload_mark;
+};
+
+struct KeyParams {
+    float voxel;
+    unsigned long long p1, p2, p3;
+};
+
+__device__ __forceinline__ unsigned long long map_key(const float* p, const KeyParams& kp) {
+    const long long cx = (long long)floorf(p[0] / kp.voxel);
+    const long long cy = (long long)floorf(p[1] / kp.voxel);
+    const long long cz = (long long)floorf(p[2] / kp.voxel);
+    const unsigned long long k =
+        (unsigned long long)cx * kp.p1 + (unsigned long long)cy * kp.p2 + (unsigned long long)cz * kp.p3;
+    return k == kEmptyKey ? kEmptyKey - 1 : k;
+}
+
+// MurmurHash3's 64-bit finaliser (Appleby): spreads the key's bits over the slot index.
+__device__ __forceinline__ unsigned long long fmix64(unsigned long long k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_probe_kernel(MapDev m, const float* __restrict__ pts,
+                                                               long long n, KeyParams kp, uint32_t* slot) {
+    const long long i = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = map_key(pts + 3 * i, kp);
+    unsigned long long h = fmix64(k) & m.mask;
+    // keys only ever change from empty to a key, so a stale empty read is settled by the CAS;
+    // the table always has free slots (at most half full), so the walk ends
+    for (unsigned long long probe = 0; probe <= m.mask; ++probe) {
+        const unsigned long long cur = m.tab_keys[h];
+        if (cur == k) break;
+        if (cur == kEmptyKey) {
+            const unsigned long long old = atomicCAS(&m.tab_keys[h], kEmptyKey, k);
+            if (old == kEmptyKey || old == k) break;
+        }
+        h = (h + 1) & m.mask;
+    }
+    slot[i] = (uint32_t)h;
+    if (m.tab_vals[h] < 0) atomicMin(&m.tab_claim[h], (int)i);
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_flag_kernel(MapDev m, const uint32_t* __restrict__ slot,
+                                                              long long n, uint32_t* newf) {
+    const long long i = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t h = slot[i];
+    newf[i] = (m.tab_vals[h] < 0 && m.tab_claim[h] == (int)i) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_assign_kernel(MapDev m, long long n,
+                                                                const uint32_t* __restrict__ slot,
+                                                                const uint32_t* __restrict__ newf,
+                                                                const uint32_t* __restrict__ rank, int id_base,
+                                                                uint32_t* new_point) {
+    const long long i = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (i >= n || !newf[i]) return;
+    const uint32_t h = slot[i];
+    const uint32_t r = rank[i];
+    const int id = id_base + (int)r;
+    m.tab_vals[h] = id;
+    m.tab_claim[h] = INT_MAX;
+    m.id_key[id] = m.tab_keys[h];
+    m.id_res[id] = 1;
+    new_point[r] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_touch_kernel(MapDev m, long long n,
+                                                               const uint32_t* __restrict__ slot, int frame,
+                                                               int32_t* point_id) {
+    const long long i = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (i >= n) return;
+    const int id = m.tab_vals[slot[i]];
+    if (point_id) point_id[i] = id;
+    m.id_last[id] = frame;
+    if (!m.id_res[id]) m.reload_mark[id] = 1u;
+}
+
+// Offloaded ids met by the call, in id order; they become resident.
+__global__ __launch_bounds__(kMapThreads) void map_reload_list_kernel(MapDev m, long long n_ids,
+                                                                     const uint32_t* __restrict__ pos,
+                                                                     uint32_t* list) {
+    const long long id = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (id >= n_ids || !m.reload_mark[id]) return;
+    list[pos[id]] = (uint32_t)id;
+    m.reload_mark[id] = 0u;
+    m.id_res[id] = 1;
+}
+
+struct ListArgs {
+    long long n_in, n_new, n_list;
+    int id_base;
+    const int32_t* in_ids;
+    const uint32_t* reload_list;
+};
+
+__device__ __forceinline__ int list_id(const ListArgs& l, long long q) {
+    if (q < l.n_in) return l.in_ids[q];
+    if (q < l.n_in + l.n_new) return l.id_base + (int)(q - l.n_in);
+    return (int)l.reload_list[q - l.n_in - l.n_new];
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_lru_keys_kernel(MapDev m, ListArgs l, uint32_t* keys,
+                                                                  uint32_t* vals) {
+    const long long q = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (q >= l.n_list) return;
+    keys[q] = (uint32_t)m.id_last[list_id(l, q)];
+    vals[q] = (uint32_t)q;
+}
+
+__global__ __launch_bounds__(kMapThreads) void map_mark_evict_kernel(const uint32_t* __restrict__ sorted_rows,
+                                                                    long long n_evict, uint32_t* flag) {
+    const long long e = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (e < n_evict) flag[sorted_rows[e]] = 1u;
+}
+
+struct RebuildArgs {
+    ListArgs l;
+    int F, k3, chunks;
+    long long n_keep;
+    const float* in[3][5];
+    float* out[3][5];
+    const float* pts;
+    const float* cols;
+    const uint32_t* new_point;
+    const float* stage_in;          // reloaded rows [r][3 F]
+    float* stage_out;               // offloaded rows [e][3 F]
+    const uint32_t* evict_flag;     // null: nothing offloaded
+    const uint32_t* evict_pos;
+    int32_t* out_ids;
+    int32_t* evict_ids;             // map-owned [max_points]
+    int32_t* evict_ids_user;        // or null
+    float ln_s_init, logit_init;
+};
+
+// Row offsets of the five fields inside one splat's F floats.
+__device__ __forceinline__ int field_base(int f) { return f == 0 ? 0 : f == 1 ? 3 : f == 2 ? 6 : f == 3 ? 10 : 11; }
+
+// Value of row r (of F) of a new splat's parameters made from point i.
+__device__ __forceinline__ float new_value(const RebuildArgs& a, long long i, int r) {
+    if (r < 3) return a.pts[3 * i + r];
+    if (r < 6) return a.ln_s_init;
+    if (r < 10) return r == 6 ? 1.f : 0.f;
+    if (r == 10) return a.logit_init;
+    const int s = r - 11;                       // SH row: coefficient s / 3, channel s % 3
+    return s < 3 ? (a.cols[3 * i + s] - 0.5f) / kShC0 : 0.f;
+}
+
+// grid (ceil(n_list / 256), 3 * chunks): a thread moves rows [r0, r0 + rows) of one array
+// (parameters, m, v) of listed row q to its new place.  Chunk 0 = the 11 rows of means,
+// log-scales, quaternion and logit (and the row's id bookkeeping); chunks 1.. = SH rows in
+// groups of kMapRows.
+__global__ __launch_bounds__(kMapThreads) void map_rebuild_kernel(RebuildArgs a, MapDev m) {
+    const long long q = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (q >= a.l.n_list) return;
+    const int t = blockIdx.y / a.chunks, c = blockIdx.y % a.chunks;
+    const bool evict = a.evict_flag && a.evict_flag[q];
+    const long long ep = a.evict_flag ? (long long)a.evict_pos[q] : 0;
+    const long long dst = q - ep;               // row in the new resident set
+    const int r0 = c == 0 ? 0 : 11 + (c - 1) * kMapRows;
+    const int rows = c == 0 ? 11 : (a.k3 - (c - 1) * kMapRows < kMapRows ? a.k3 - (c - 1) * kMapRows : kMapRows);
+    const int kind = q < a.l.n_in ? 0 : (q < a.l.n_in + a.l.n_new ? 1 : 2);
+    float v[kMapRows];
+#pragma unroll
+    for (int k = 0; k < kMapRows; ++k) {
+        const int r = r0 + (k < rows ? k : rows - 1);
+        float x;
+        if (kind == 0) {
+            int f = r < 3 ? 0 : r < 6 ? 1 : r < 10 ? 2 : r < 11 ? 3 : 4;
+            x = a.in[t][f][(long long)(r - field_base(f)) * a.l.n_in + q];
+        } else if (kind == 1) {
+            x = t == 0 ? new_value(a, a.new_point[q - a.l.n_in], r) : 0.f;
+        } else {
+            x = a.stage_in[(q - a.l.n_in - a.l.n_new) * 3 * a.F + (long long)t * a.F + r];
+        }
+        v[k] = x;
+    }
+    if (evict) {
+        float* row = a.stage_out + ep * 3 * a.F + (long long)t * a.F;
+#pragma unroll
+        for (int k = 0; k < kMapRows; ++k)
+            if (k < rows) row[r0 + k] = v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kMapRows; ++k) {
+            if (k < rows) {
+                const int r = r0 + k;
+                const int f = r < 3 ? 0 : r < 6 ? 1 : r < 10 ? 2 : r < 11 ? 3 : 4;
+                a.out[t][f][(long long)(r - field_base(f)) * a.n_keep + dst] = v[k];
+            }
+        }
+    }
+    if (t == 0 && c == 0) {
+        const int id = list_id(a.l, q);
+        if (evict) {
+            m.id_res[id] = 0;
+            a.evict_ids[ep] = id;
+            if (a.evict_ids_user) a.evict_ids_user[ep] = id;
+        } else {
+            a.out_ids[dst] = id;
+        }
+    }
+}
+
+}  // namespace ags
+
+using namespace ags;
+
+namespace {
+
+constexpr size_t kMapAlign = 256;
+size_t map_align(size_t x) { return (x + kMapAlign - 1) / kMapAlign * kMapAlign; }
+
+bool map_gaussians_ok(const ags_gaussians* g, int deg) {
+    if (!g || g->n < 0 || g->sh_degree != deg) return false;
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)) return false;
+    return true;
+}
+
+unsigned grid_of(long long n) { return (unsigned)((n + kMapThreads - 1) / kMapThreads); }
+
+MapDev dev_of(const ags_map* mp) {
+    MapDev m;
+    m.tab_keys = mp->tab_keys;
+    m.tab_vals = mp->tab_vals;
+    m.tab_claim = mp->tab_claim;
+    m.mask = (unsigned long long)(mp->slots - 1);
+    m.id_key = mp->id_key;
+    m.id_last = mp->id_last;
+    m.id_res = mp->id_res;
+    m.reload_mark = mp->reload_mark;
+    return m;
+}
+
+void map_free(ags_map* m) {
+    void* dev[] = {m->tab_keys, m->tab_vals, m->tab_claim, m->id_key, m->id_last, m->id_res, m->reload_mark,
+                   m->slot, m->newf, m->rank, m->new_point, m->reload_pos, m->reload_list, m->keys[0],
+                   m->keys[1], m->vals[0], m->vals[1], m->evict_flag, m->evict_pos, m->evict_ids,
+                   m->counters, m->block_sums, m->hist, m->rowtot, m->stage_in, m->stage_out};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (m->pinned) (void)hipHostFree(m->pinned);
+    free(m->store);
+    delete m;
+}
+
+__global__ void map_fill_u64_kernel(unsigned long long* p, unsigned long long v, long long n) {
+    const long long i = (long long)blockIdx.x * kMapThreads + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ags_map_config_default(ags_map_config* c) {
+    if (!c) return AGS_ERR_INVALID_ARG;
+    c->voxel = 0.05f;
+    c->s_init = 0.005f;
+    c->o_init = 0.1f;
+    c->sh_degree = 3;
+    c->prime[0] = 73856093ULL;
+    c->prime[1] = 19349663ULL;
+    c->prime[2] = 83492791ULL;
+    c->max_ids = 1LL << 22;
+    c->max_points = 1LL << 20;
+    c->tau = 1LL << 20;
+    return AGS_OK;
+}
+
+int ags_map_create(ags_ctx* ctx, const ags_map_config* cfg, ags_map** out) {
+    if (!ctx || !cfg || !out) return AGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!(cfg->voxel > 0.f) || !(cfg->s_init > 0.f) || !(cfg->o_init > 0.f && cfg->o_init < 1.f))
+        return AGS_ERR_INVALID_ARG;
+    if (cfg->sh_degree < 0 || cfg->sh_degree > 3) return AGS_ERR_INVALID_ARG;
+    if (cfg->max_ids < 1 || cfg->max_ids > (1LL << 30) || cfg->max_points < 1 || cfg->max_points > (1LL << 28) ||
+        cfg->tau < 1 || cfg->tau > (1LL << 30))
+        return AGS_ERR_INVALID_ARG;
+    ags_map* m = new (std::nothrow) ags_map();
+    if (!m) return AGS_ERR_INVALID_ARG;
+    memset(m->keys, 0, sizeof(m->keys));
+    memset(m->vals, 0, sizeof(m->vals));
+    m->ctx = ctx;
+    m->cfg = *cfg;
+    m->device = ctx_device(ctx);
+    const int K = (cfg->sh_degree + 1) * (cfg->sh_degree + 1);
+    m->F = 11 + 3 * K;
+    long long slots = 1;
+    while (slots < 2 * cfg->max_ids) slots <<= 1;
+    m->slots = slots;
+    m->list_max = cfg->tau + cfg->max_points;
+    m->n_ids = 0;
+    m->last_frame = -1;
+    m->ln_s_init = (float)log((double)cfg->s_init);
+    m->logit_init = (float)log((double)cfg->o_init / (1.0 - (double)cfg->o_init));
+    if (hipSetDevice(m->device) != hipSuccess) {
+        int rc = ctx_record_hip(ctx, hipGetLastError());
+        delete m;
+        return rc;
+    }
+    const long long P = cfg->max_points, I = cfg->max_ids, Lm = m->list_max;
+    const size_t row_bytes = (size_t)3 * m->F * sizeof(float);
+    const int grid = sort_grid(Lm);
+    long long nb = scan_blocks(Lm > I ? Lm : I);
+    if (nb < 1) nb = 1;
+    struct A {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&m->tab_keys, 8 * (size_t)slots}, {(void**)&m->tab_vals, 4 * (size_t)slots},
+        {(void**)&m->tab_claim, 4 * (size_t)slots}, {(void**)&m->id_key, 8 * (size_t)I},
+        {(void**)&m->id_last, 4 * (size_t)I}, {(void**)&m->id_res, (size_t)I},
+        {(void**)&m->reload_mark, 4 * (size_t)I}, {(void**)&m->slot, 4 * (size_t)P},
+        {(void**)&m->newf, 4 * (size_t)P}, {(void**)&m->rank, 4 * (size_t)P},
+        {(void**)&m->new_point, 4 * (size_t)P}, {(void**)&m->reload_pos, 4 * (size_t)I},
+        {(void**)&m->reload_list, 4 * (size_t)P}, {(void**)&m->keys[0], 4 * (size_t)Lm},
+        {(void**)&m->keys[1], 4 * (size_t)Lm}, {(void**)&m->vals[0], 4 * (size_t)Lm},
+        {(void**)&m->vals[1], 4 * (size_t)Lm}, {(void**)&m->evict_flag, 4 * (size_t)Lm},
+        {(void**)&m->evict_pos, 4 * (size_t)Lm}, {(void**)&m->evict_ids, 4 * (size_t)P},
+        {(void**)&m->counters, 16}, {(void**)&m->block_sums, 4 * (size_t)nb},
+        {(void**)&m->hist, 4 * (size_t)sort_hist_entries(grid)}, {(void**)&m->rowtot, 4 * (size_t)sort_rowtot_entries()},
+        {(void**)&m->stage_in, row_bytes * (size_t)P}, {(void**)&m->stage_out, row_bytes * (size_t)P},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, map_align(a.bytes)) != hipSuccess) {
+            int rc = ctx_record_hip(ctx, hipGetLastError());
+            map_free(m);
+            return rc;
+        }
+    }
+    if (hipHostMalloc((void**)&m->pinned, row_bytes * (size_t)P, hipHostMallocDefault) != hipSuccess) {
+        int rc = ctx_record_hip(ctx, hipGetLastError());
+        map_free(m);
+        return rc;
+    }
+    m->store = (float*)malloc(row_bytes * (size_t)I);  // pages committed as rows are offloaded
+    if (!m->store) {
+        map_free(m);
+        return AGS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = nullptr;
+    hipLaunchKernelGGL(map_fill_u64_kernel, dim3(grid_of(slots)), dim3(kMapThreads), 0, s, m->tab_keys, kEmptyKey,
+                       slots);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->tab_vals), 0xffffffffu, slots, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->tab_claim), (uint32_t)INT_MAX, slots, s);
+    launch_fill_u32(m->reload_mark, 0u, I, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->id_last), 0u, I, s);
+    if (hipMemsetAsync(m->id_res, 0, (size_t)I, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        int rc = ctx_record_hip(ctx, hipGetLastError());
+        map_free(m);
+        return rc;
+    }
+    m->h_list.resize((size_t)P);
+    m->h_evicted.resize((size_t)P);
+    *out = m;
+    return AGS_OK;
+}
+
+int ags_map_destroy(ags_map* map) {
+    if (!map) return AGS_ERR_INVALID_ARG;
+    (void)hipSetDevice(map->device);
+    (void)hipDeviceSynchronize();
+    map_free(map);
+    return AGS_OK;
+}
+
+int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_t n_points, int32_t frame,
+                   const ags_gaussians* in, const ags_gaussians* in_m, const ags_gaussians* in_v,
+                   const int32_t* in_ids, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
+                   int32_t* out_ids, int32_t* point_id, int32_t* evicted_ids, ags_map_counts* counts,
+                   void* stream) {
+    if (!mp || !counts) return AGS_ERR_INVALID_ARG;
+    const ags_map_config& cfg = mp->cfg;
+    const int deg = cfg.sh_degree;
+    if (n_points < 0 || n_points > cfg.max_points || (n_points > 0 && (!points || !colors))) return AGS_ERR_INVALID_ARG;
+    if (frame < 0 || frame < mp->last_frame) return AGS_ERR_INVALID_ARG;
+    if (!map_gaussians_ok(in, deg) || !map_gaussians_ok(in_m, deg) || !map_gaussians_ok(in_v, deg) ||
+        !map_gaussians_ok(out, deg) || !map_gaussians_ok(out_m, deg) || !map_gaussians_ok(out_v, deg))
+        return AGS_ERR_INVALID_ARG;
+    const long long n_in = in->n;
+    if (in_m->n != n_in || in_v->n != n_in || n_in > cfg.tau || (n_in > 0 && !in_ids)) return AGS_ERR_INVALID_ARG;
+    if (out_m->n != out->n || out_v->n != out->n || !out_ids) return AGS_ERR_INVALID_ARG;
+    const long long need = n_in + n_points < cfg.tau ? n_in + n_points : cfg.tau;
+    if (out->n < need) return AGS_ERR_INVALID_ARG;
+    if (mp->n_ids + n_points > cfg.max_ids) return AGS_ERR_CAPACITY;
+    ags_ctx* ctx = mp->ctx;
+    if (hipSetDevice(mp->device) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
+    hipStream_t s = (hipStream_t)stream;
+    const MapDev m = dev_of(mp);
+    KeyParams kp;
+    kp.voxel = cfg.voxel;
+    kp.p1 = cfg.prime[0];
+    kp.p2 = cfg.prime[1];
+    kp.p3 = cfg.prime[2];
+    const int id_base = (int)mp->n_ids;
+    ScanTemp st;
+    st.block_sums = mp->block_sums;
+    // 1-3: probe, first points of new keys, ids, touch, reload marks
+    launch_fill_u32(mp->counters, 0u, 4, s);
+    if (n_points > 0) {
+        const unsigned g = grid_of(n_points);
+        hipLaunchKernelGGL(map_probe_kernel, dim3(g), dim3(kMapThreads), 0, s, m, points, (long long)n_points, kp,
+                           mp->slot);
+        hipLaunchKernelGGL(map_flag_kernel, dim3(g), dim3(kMapThreads), 0, s, m, mp->slot, (long long)n_points,
+                           mp->newf);
+        launch_scan(mp->newf, nullptr, false, mp->rank, n_points, nullptr, mp->counters, st, s);
+        hipLaunchKernelGGL(map_assign_kernel, dim3(g), dim3(kMapThreads), 0, s, m, (long long)n_points, mp->slot,
+                           mp->newf, mp->rank, id_base, mp->new_point);
+        hipLaunchKernelGGL(map_touch_kernel, dim3(g), dim3(kMapThreads), 0, s, m, (long long)n_points, mp->slot,
+                           frame, point_id);
+        if (id_base > 0) {
+            launch_scan(mp->reload_mark, nullptr, true, mp->reload_pos, id_base, nullptr, mp->counters + 1, st, s);
+            hipLaunchKernelGGL(map_reload_list_kernel, dim3(grid_of(id_base)), dim3(kMapThreads), 0, s, m,
+                               (long long)id_base, mp->reload_pos, mp->reload_list);
+        }
+    }
+    uint32_t hc[4];
+    if (hipMemcpyAsync(hc, mp->counters, sizeof(hc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ctx_record_hip(ctx, hipGetLastError());
+    const long long n_new = hc[0], n_reload = hc[1];
+    const size_t row_f = (size_t)3 * mp->F;
+    // 4: reloaded rows from the host store
+    if (n_reload > 0) {
+        if (hipMemcpyAsync(mp->h_list.data(), mp->reload_list, 4 * (size_t)n_reload, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return ctx_record_hip(ctx, hipGetLastError());
+        for (long long r = 0; r < n_reload; ++r)
+            memcpy(mp->pinned + r * row_f, mp->store + (size_t)mp->h_list[r] * row_f, row_f * sizeof(float));
+        if (hipMemcpyAsync(mp->stage_in, mp->pinned, row_f * sizeof(float) * (size_t)n_reload,
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return ctx_record_hip(ctx, hipGetLastError());
+    }
+    // 5: least recently used rows beyond tau
+    ListArgs l;
+    l.n_in = n_in;
+    l.n_new = n_new;
+    l.n_list = n_in + n_new + n_reload;
+    l.id_base = id_base;
+    l.in_ids = in_ids;
+    l.reload_list = mp->reload_list;
+    const long long n_keep = l.n_list < cfg.tau ? l.n_list : cfg.tau;
+    const long long n_evict = l.n_list - n_keep;
+    if (n_evict > 0) {
+        const unsigned g = grid_of(l.n_list);
+        hipLaunchKernelGGL(map_lru_keys_kernel, dim3(g), dim3(kMapThreads), 0, s, m, l, mp->keys[0], mp->vals[0]);
+        int bits = 0;
+        while (bits < 31 && (frame >> bits) != 0) ++bits;
+        SortTemp sort_tmp;
+        sort_tmp.hist = mp->hist;
+        sort_tmp.rowtot = mp->rowtot;
+        const int r = launch_radix_sort(mp->keys, mp->vals, l.n_list, nullptr, bits, sort_grid(l.n_list), sort_tmp, s);
+        launch_fill_u32(mp->evict_flag, 0u, l.n_list, s);
+        hipLaunchKernelGGL(map_mark_evict_kernel, dim3(grid_of(n_evict)), dim3(kMapThreads), 0, s, mp->vals[r],
+                           n_evict, mp->evict_flag);
+        launch_scan(mp->evict_flag, nullptr, false, mp->evict_pos, l.n_list, nullptr, nullptr, st, s);
+    }
+    // 6: the new resident set and the offloaded rows
+    if (l.n_list > 0) {
+        RebuildArgs a;
+        memset(&a, 0, sizeof(a));
+        a.l = l;
+        a.F = mp->F;
+        a.k3 = 3 * (deg + 1) * (deg + 1);
+        a.chunks = 1 + (a.k3 + kMapRows - 1) / kMapRows;
+        a.n_keep = n_keep;
+        const ags_gaussians* ins[3] = {in, in_m, in_v};
+        ags_gaussians* outs[3] = {out, out_m, out_v};
+        for (int t = 0; t < 3; ++t) {
+            const float* src[5] = {ins[t]->means, ins[t]->log_scales, ins[t]->quats, ins[t]->opacity_logits,
+                                   ins[t]->sh};
+            float* dst[5] = {outs[t]->means, outs[t]->log_scales, outs[t]->quats, outs[t]->opacity_logits,
+                             outs[t]->sh};
+            for (int f = 0; f < 5; ++f) {
+                a.in[t][f] = src[f];
+                a.out[t][f] = dst[f];
+            }
+        }
+        a.pts = points;
+        a.cols = colors;
+        a.new_point = mp->new_point;
+        a.stage_in = mp->stage_in;
+        a.stage_out = mp->stage_out;
+        a.evict_flag = n_evict > 0 ? mp->evict_flag : nullptr;
+        a.evict_pos = mp->evict_pos;
+        a.out_ids = out_ids;
+        a.evict_ids = mp->evict_ids;
+        a.evict_ids_user = evicted_ids;
+        a.ln_s_init = mp->ln_s_init;
+        a.logit_init = mp->logit_init;
+        hipLaunchKernelGGL(map_rebuild_kernel, dim3(grid_of(l.n_list), 3 * a.chunks), dim3(kMapThreads), 0, s, a,
+                           m);
+    }
+    if (n_evict > 0) {
+        if (hipMemcpyAsync(mp->pinned, mp->stage_out, row_f * sizeof(float) * (size_t)n_evict,
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(mp->h_evicted.data(), mp->evict_ids, 4 * (size_t)n_evict, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return ctx_record_hip(ctx, hipGetLastError());
+        for (long long e = 0; e < n_evict; ++e)
+            memcpy(mp->store + (size_t)mp->h_evicted[e] * row_f, mp->pinned + e * row_f, row_f * sizeof(float));
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
+        return ctx_record_hip(ctx, hipGetLastError());
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx_record_hip(ctx, e);
+    mp->n_ids += n_new;
+    mp->last_frame = frame;
+    counts->n_ids = mp->n_ids;
+    counts->n_resident = n_keep;
+    counts->n_new = n_new;
+    counts->n_reloaded = n_reload;
+    counts->n_evicted = n_evict;
+    return AGS_OK;
+}
+
+int ags_map_export(ags_map* mp, uint64_t* keys, int32_t* last_used, uint8_t* resident, uint64_t* table_keys,
+                   int32_t* table_ids, int64_t table_slots, int64_t* n_ids, int64_t* n_slots) {
+    if (!mp) return AGS_ERR_INVALID_ARG;
+    if ((table_keys || table_ids) && table_slots < mp->slots) return AGS_ERR_INVALID_ARG;
+    if (hipSetDevice(mp->device) != hipSuccess) return ctx_record_hip(mp->ctx, hipGetLastError());
+    const size_t I = (size_t)mp->n_ids;
+    if (hipDeviceSynchronize() != hipSuccess) return ctx_record_hip(mp->ctx, hipGetLastError());
+    if ((keys && I && hipMemcpy(keys, mp->id_key, 8 * I, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (last_used && I && hipMemcpy(last_used, mp->id_last, 4 * I, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (resident && I && hipMemcpy(resident, mp->id_res, I, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (table_keys && hipMemcpy(table_keys, mp->tab_keys, 8 * (size_t)mp->slots, hipMemcpyDeviceToHost) !=
+                           hipSuccess) ||
+        (table_ids &&
+         hipMemcpy(table_ids, mp->tab_vals, 4 * (size_t)mp->slots, hipMemcpyDeviceToHost) != hipSuccess))
+        return ctx_record_hip(mp->ctx, hipGetLastError());
+    if (n_ids) *n_ids = mp->n_ids;
+    if (n_slots) *n_slots = mp->slots;
+    return AGS_OK;
+}
+
+int ags_map_read_store(ags_map* mp, const int32_t* ids, int64_t n, float* rows) {
+    if (!mp || n < 0 || (n > 0 && (!ids || !rows))) return AGS_ERR_INVALID_ARG;
+    if (n == 0) return AGS_OK;
+    std::vector<uint8_t> res((size_t)mp->n_ids);
+    if (hipSetDevice(mp->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        (mp->n_ids > 0 && hipMemcpy(res.data(), mp->id_res, (size_t)mp->n_ids, hipMemcpyDeviceToHost) != hipSuccess))
+        return ctx_record_hip(mp->ctx, hipGetLastError());
+    const size_t row_f = (size_t)3 * mp->F;
+    for (int64_t k = 0; k < n; ++k)
+        if (ids[k] < 0 || ids[k] >= mp->n_ids || res[(size_t)ids[k]]) return AGS_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < n; ++k) memcpy(rows + k * row_f, mp->store + (size_t)ids[k] * row_f, row_f * sizeof(float));
+    return AGS_OK;
+}
+
+}  // extern "C"

@@ -7,7 +7,8 @@ import math
 
 import numpy as np
 
-from oracle.voxel_map import EMPTY_KEY, MASK64, SH_C0, VoxelMap, VoxelMapParams, voxel_cells, voxel_key
+from oracle.voxel_map import (EMPTY_KEY, MASK64, SH_C0, VoxelMap, VoxelMapParams, voxel_cells, voxel_key,
+                              voxel_keys)
 
 P = (73856093, 19349663, 83492791)
 
@@ -131,3 +132,12 @@ def test_invariants_of_random_sequences():
             assert max(m.last_used[j] for j in m.store) <= min(m.last_used[j] for j in m.resident)
         # every id met in this call is used now
         assert all(m.last_used[j] == t for j in set(r["point_id"].tolist()))
+
+
+def test_vectorised_keys_equal_the_per_point_keys():
+    rng = np.random.default_rng(5)
+    vp = VoxelMapParams(voxel=0.05)
+    pts = np.concatenate([rng.normal(0, 30, (500, 3)), rng.normal(0, 1e5, (100, 3))]).astype(np.float32)
+    ks = voxel_keys(pts, vp)
+    assert ks.dtype == np.uint64
+    assert [int(k) for k in ks] == [voxel_key(c, vp.primes) for c in voxel_cells(pts, vp.voxel)]
