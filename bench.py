@@ -172,6 +172,76 @@ def measure_lifecycle(ras, p, cams, views, buf, out, grads, pose, tg, loss, args
     return res
 
 
+def measure_voxel_map(ras, args, n_points=1 << 20, tau=1 << 20, warm_calls=8, timed_calls=6):
+    """Voxel-map insertion calls along a synthetic row: each call brings 2^20 points uniform in
+    a 6 x 3 x 3 m window (a camera rig's view of a canopy row, voxel 0.05 m) that advances
+    1.5 m per call, so about a quarter of the voxels are new; the resident set is bounded by
+    2^20 splats (SH degree 3).  The first calls fill the resident set; the timed ones run in
+    the steady state (new splats in, as many least recently used out to the host store).
+    Reported: wall time per call (host-synchronous: includes the reload / offload copies over
+    PCIe; the offloaded rows' copy into the host store runs on a host thread after the call
+    returns and is timed apart, by waiting for it before the next call), per-stage GPU times
+    (HIP events), and the roofline of the dominant kernel, the resident-set rebuild (HBM:
+    every listed row written, 3 x 4 x 59 B, and read from the previous set or the reload
+    staging, 24 B of point and colour for a new one)."""
+    import torch
+    from paper_2510_26358_amd.voxel_map import VoxelMap
+    gm = VoxelMap(ras, voxel=0.05, sh_degree=3, tau=tau, max_ids=1 << 23, max_points=n_points)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9090)
+    scale = torch.tensor([6.0, 3.0, 3.0], device="cuda")
+    row_bytes = 3 * 4 * gm.F
+
+    def call(t):
+        pts = torch.rand(n_points, 3, device="cuda", generator=gen) * scale
+        pts[:, 0] += 1.5 * t
+        pts[:, 1] -= 1.5
+        cols = torch.rand(n_points, 3, device="cuda", generator=gen)
+        torch.cuda.synchronize()
+        n_in = gm.n
+        w0 = time.perf_counter()
+        _, c = gm.insert(pts, cols, t)
+        wall = time.perf_counter() - w0
+        f0 = time.perf_counter()
+        gm.sync()
+        flush = time.perf_counter() - f0
+        listed = n_in + c["n_new"] + c["n_reloaded"]
+        rebuild = row_bytes * (n_in + c["n_reloaded"] + listed) + 24 * c["n_new"]
+        pcie = row_bytes * (c["n_reloaded"] + c["n_evicted"])
+        return wall * 1e3, flush * 1e3, rebuild, pcie, c
+
+    for t in range(warm_calls):
+        call(t)
+    ras.profile(True)
+    ras.profile_reset()
+    recs = [call(warm_calls + k) for k in range(timed_calls)]
+    torch.cuda.synchronize()
+    prof = ras.profile_read()
+    ras.profile(False)
+    stage = {k: round(v[0] / timed_calls, 4) for k, v in prof.items() if k.startswith("map_") and v[1] > 0}
+    mean = lambda k: sum(r[k] for r in recs) / len(recs)
+    wall, flush, rebuild, pcie = mean(0), mean(1), mean(2), mean(3)
+    reb_ms = stage.get("map_rebuild", float("nan"))
+    gbs = rebuild / (reb_ms * 1e-3) / 1e9
+    res = {"points_per_call": n_points, "tau": tau, "calls_timed": timed_calls,
+           "ms_per_call_wall": round(wall, 4), "host_store_ms_after_return": round(flush, 4),
+           "mpoints_per_s_wall": round(n_points / (wall * 1e-3) / 1e6, 2), "stage_ms_per_call": stage,
+           "new_per_call": round(sum(r[4]["n_new"] for r in recs) / len(recs)),
+           "evicted_per_call": round(sum(r[4]["n_evicted"] for r in recs) / len(recs)),
+           "reloaded_per_call": round(sum(r[4]["n_reloaded"] for r in recs) / len(recs)),
+           "n_ids": recs[-1][4]["n_ids"], "n_resident": recs[-1][4]["n_resident"],
+           "pcie_bytes_per_call": round(pcie),
+           "pcie_gbs": round(pcie / (stage.get("map_copy", float("nan")) * 1e-3) / 1e9, 2),
+           "roofline": {"kernel": "map_rebuild_kernel", "bound": "hbm", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "bytes_per_launch": round(rebuild)}}
+    log(f"[bench] voxel map: {wall:.3f} ms/call wall, {res}")
+    gm.close()
+    del gm
+    torch.cuda.empty_cache()
+    return res
+
+
 def _source_digest(stage):
     import hashlib
     src = {"raster_bwd": "raster.hip", "raster_fwd": "raster.hip", "project_bwd": "project_bwd.hip",
@@ -323,6 +393,8 @@ def main():
     ap.add_argument("--lifecycle", type=int, default=1,
                     help="also time the step accumulating the densification statistic and one lifecycle "
                          "pass (prune / split / duplicate / reset) over the Gaussians (0: skip)")
+    ap.add_argument("--voxel-map", type=int, default=1,
+                    help="also time voxel-map insertion calls (2^20 points each, resident bound 2^20; 0: skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -485,6 +557,10 @@ def main():
     if args.lifecycle and refiner is None:
         lifecycle = measure_lifecycle(ras, p, cams, views, buf, out, grads, pose, tg, loss, args, t_b)
 
+    vmap = None
+    if args.voxel_map and refiner is None:
+        vmap = measure_voxel_map(ras, args)
+
     loop = None
     if not args.no_loop and views.n_views > 1 and refiner is None:
         from paper_2510_26358_amd.rasterizer import LossTargets
@@ -537,6 +613,7 @@ def main():
                    "visible_pairs": V, "intersections": K},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
         "with_ssim": with_ssim, "with_rendered_variance": with_rv, "lifecycle": lifecycle,
+        "voxel_map": vmap,
     }
     print(json.dumps(rec), flush=True)
 

@@ -15,24 +15,11 @@ struct ProfEvent {
     hipEvent_t a, b;
 };
 
-enum Stage {
-    ST_PROJECT = 0,
-    ST_BINNING,
-    ST_RASTER_FWD,
-    ST_LIDAR,
-    ST_RASTER_BWD,
-    ST_PROJECT_BWD,
-    ST_CLEAR,
-    ST_ADAM,
-    ST_POSE,
-    ST_SSIM,
-    ST_LIFECYCLE,
-    ST_COUNT
-};
 static const char* kStageNames[ST_COUNT] = {"project_fwd", "binning",     "raster_fwd",
                                              "lidar_adjoint", "raster_bwd", "project_bwd",
                                              "clear",       "adam",        "pose_step", "ssim",
-                                             "lifecycle"};
+                                             "lifecycle",   "map_probe",   "map_lru",   "map_rebuild",
+                                             "map_copy"};
 
 struct ags_ctx {
     int device;
@@ -196,34 +183,7 @@ const T* at(const void* base, size_t off) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
 }
 
-// Profiling helpers: bracket a group of launches with events when enabled.
-struct Scope {
-    ags_ctx* ctx;
-    int stage;
-    hipStream_t s;
-    hipEvent_t a = nullptr, b = nullptr;
-    Scope(ags_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
-        if (!ctx->prof) return;
-        a = take();
-        b = take();
-        if (a) (void)hipEventRecord(a, s);
-    }
-    hipEvent_t take() {
-        if (!ctx->pool.empty()) {
-            hipEvent_t e = ctx->pool.back();
-            ctx->pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    ~Scope() {
-        if (!ctx->prof || !a || !b) return;
-        (void)hipEventRecord(b, s);
-        ctx->pending.push_back({stage, a, b});
-    }
-};
+using Scope = StageTimer;
 
 int hip_status(ags_ctx* ctx) {
     hipError_t e = hipGetLastError();
@@ -276,6 +236,28 @@ int run_binning(BinArgs a, hipStream_t s) { return launch_binning(a, s); }
 }  // namespace
 
 namespace ags {
+StageTimer::StageTimer(ags_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+    if (!ctx->prof) return;
+    a = take();
+    b = take();
+    if (a) (void)hipEventRecord(a, s);
+}
+hipEvent_t StageTimer::take() {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+StageTimer::~StageTimer() {
+    if (!ctx->prof || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    ctx->pending.push_back({stage, a, b});
+}
+
 int ctx_device(const ags_ctx* ctx) { return ctx->device; }
 int ctx_record_hip(ags_ctx* ctx, hipError_t e) {
     if (ctx) ctx->last_hip = (int)(e != hipSuccess ? e : hipErrorUnknown);

@@ -516,6 +516,37 @@ struct LifecycleArgs {
 };
 void launch_lifecycle(const LifecycleArgs& a, hipStream_t s);
 
+// Profiled stages (ags_profile_read reports their times under these indices).
+enum Stage {
+    ST_PROJECT = 0,
+    ST_BINNING,
+    ST_RASTER_FWD,
+    ST_LIDAR,
+    ST_RASTER_BWD,
+    ST_PROJECT_BWD,
+    ST_CLEAR,
+    ST_ADAM,
+    ST_POSE,
+    ST_SSIM,
+    ST_LIFECYCLE,
+    ST_MAP_PROBE,
+    ST_MAP_LRU,
+    ST_MAP_REBUILD,
+    ST_MAP_COPY,
+    ST_COUNT
+};
+
+// Brackets a group of launches on stream s with events while the context profiles.
+struct StageTimer {
+    ags_ctx* ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(ags_ctx* c, int st, hipStream_t str);
+    ~StageTimer();
+    hipEvent_t take();
+};
+
 // Context access for sources other than the context's own: its device, and recording a
 // failed HIP call (returns AGS_ERR_HIP).
 int ctx_device(const ags_ctx* ctx);

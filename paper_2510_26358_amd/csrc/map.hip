@@ -16,13 +16,18 @@
 //   5. if more than tau rows are listed: stable radix sort of the listed rows by last_used,
 //      the first (listed - tau) rows are offloaded;
 //   6. rebuild: one launch writes the new resident set (packed, row stride = its size) and the
-//      offloaded rows (device staging, then pinned host memory and the host store).
+//      offloaded rows (device staging, then pinned host memory; a host thread moves them
+//      into the host store while the caller goes on).
 #include <limits.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <sys/mman.h>
+
+#include <algorithm>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -64,9 +69,11 @@ struct ags_map {
     float* stage_out;              // [max_points][3 F] offloaded rows
     // host
     float* pinned;                 // [max_points][3 F]
-    float* store;                  // [max_ids][3 F]
+    float* store;                  // [max_ids][3 F], anonymous mapping, pages committed on use
+    size_t store_bytes;
     std::vector<uint32_t> h_list;
     std::vector<int32_t> h_evicted;
+    std::thread flush;             // host-store writes of the last call's offloaded rows
 };
 
 namespace ags {
@@ -238,6 +245,18 @@ __device__ __forceinline__ float new_value(const RebuildArgs& a, long long i, in
     return s < 3 ? (a.cols[3 * i + s] - 0.5f) / kShC0 : 0.f;
 }
 
+// Moves `rows` rows (row strides sn in, dn out) of one field from column q to column d.
+template <int R>
+__device__ __forceinline__ void map_move(const float* __restrict__ src, long long sn, float* __restrict__ dst,
+                                         long long dn, int rows, long long q, long long d) {
+    float v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[(long long)(r < rows ? r : rows - 1) * sn + q];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < rows) dst[(long long)r * dn + d] = v[r];
+}
+
 // grid (ceil(n_list / 256), 3 * chunks): a thread moves rows [r0, r0 + rows) of one array
 // (parameters, m, v) of listed row q to its new place.  Chunk 0 = the 11 rows of means,
 // log-scales, quaternion and logit (and the row's id bookkeeping); chunks 1.. = SH rows in
@@ -252,6 +271,30 @@ __global__ __launch_bounds__(kMapThreads) void map_rebuild_kernel(RebuildArgs a,
     const int r0 = c == 0 ? 0 : 11 + (c - 1) * kMapRows;
     const int rows = c == 0 ? 11 : (a.k3 - (c - 1) * kMapRows < kMapRows ? a.k3 - (c - 1) * kMapRows : kMapRows);
     const int kind = q < a.l.n_in ? 0 : (q < a.l.n_in + a.l.n_new ? 1 : 2);
+    if (t == 0 && c == 0) {
+        const int id = list_id(a.l, q);
+        if (evict) {
+            m.id_res[id] = 0;
+            a.evict_ids[ep] = id;
+            if (a.evict_ids_user) a.evict_ids_user[ep] = id;
+        } else {
+            a.out_ids[dst] = id;
+        }
+    }
+    if (kind == 0 && !evict) {
+        // a kept row of the previous set: SoA to SoA, all loads before the stores
+        if (c == 0) {
+            const int fr[4] = {3, 3, 4, 1};
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                map_move<4>(a.in[t][f], a.l.n_in, a.out[t][f], a.n_keep, fr[f], q, dst);
+        } else {
+            const long long s0 = (long long)(c - 1) * kMapRows;
+            map_move<kMapRows>(a.in[t][4] + s0 * a.l.n_in, a.l.n_in, a.out[t][4] + s0 * a.n_keep, a.n_keep, rows, q,
+                               dst);
+        }
+        return;
+    }
     float v[kMapRows];
 #pragma unroll
     for (int k = 0; k < kMapRows; ++k) {
@@ -280,16 +323,6 @@ __global__ __launch_bounds__(kMapThreads) void map_rebuild_kernel(RebuildArgs a,
                 const int f = r < 3 ? 0 : r < 6 ? 1 : r < 10 ? 2 : r < 11 ? 3 : 4;
                 a.out[t][f][(long long)(r - field_base(f)) * a.n_keep + dst] = v[k];
             }
-        }
-    }
-    if (t == 0 && c == 0) {
-        const int id = list_id(a.l, q);
-        if (evict) {
-            m.id_res[id] = 0;
-            a.evict_ids[ep] = id;
-            if (a.evict_ids_user) a.evict_ids_user[ep] = id;
-        } else {
-            a.out_ids[dst] = id;
         }
     }
 }
@@ -324,7 +357,33 @@ MapDev dev_of(const ags_map* mp) {
     return m;
 }
 
+// Runs fn(begin, end) over [0, n) split across up to 16 host threads (one when n is small).
+template <class Fn>
+void parallel_rows(long long n, long long min_per_thread, Fn fn) {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const long long t = std::max(1LL, std::min<long long>(hw, n / std::max(1LL, min_per_thread)));
+    std::vector<std::thread> pool;
+    long long done = 0;  // rows [0, done) handed to threads; the rest run on this thread
+    try {
+        pool.reserve((size_t)t);
+        for (long long k = 1; k < t; ++k) {
+            pool.emplace_back(fn, n * k / t, n * (k + 1) / t);
+            done = n * (k + 1) / t;
+        }
+    } catch (...) {
+    }
+    fn(0LL, t > 1 ? n / t : n);
+    if (t > 1 && done < n) fn(pool.empty() ? n / t : done, n);
+    for (auto& th : pool) th.join();
+}
+
+// Waits for the host-store writes of the previous call (they read the pinned staging).
+void flush_join(ags_map* m) {
+    if (m->flush.joinable()) m->flush.join();
+}
+
 void map_free(ags_map* m) {
+    flush_join(m);
     void* dev[] = {m->tab_keys, m->tab_vals, m->tab_claim, m->id_key, m->id_last, m->id_res, m->reload_mark,
                    m->slot, m->newf, m->rank, m->new_point, m->reload_pos, m->reload_list, m->keys[0],
                    m->keys[1], m->vals[0], m->vals[1], m->evict_flag, m->evict_pos, m->evict_ids,
@@ -332,7 +391,7 @@ void map_free(ags_map* m) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (m->pinned) (void)hipHostFree(m->pinned);
-    free(m->store);
+    if (m->store) munmap(m->store, m->store_bytes);
     delete m;
 }
 
@@ -426,11 +485,17 @@ int ags_map_create(ags_ctx* ctx, const ags_map_config* cfg, ags_map** out) {
         map_free(m);
         return rc;
     }
-    m->store = (float*)malloc(row_bytes * (size_t)I);  // pages committed as rows are offloaded
-    if (!m->store) {
+    // host store: reserved, committed page by page as rows are offloaded (transparent huge
+    // pages where the system allows them, so that committing costs few faults)
+    m->store_bytes = row_bytes * (size_t)I;
+    void* st = mmap(nullptr, m->store_bytes, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE,
+                    -1, 0);
+    if (st == MAP_FAILED) {
         map_free(m);
         return AGS_ERR_INVALID_ARG;
     }
+    (void)madvise(st, m->store_bytes, MADV_HUGEPAGE);
+    m->store = (float*)st;
     hipStream_t s = nullptr;
     hipLaunchKernelGGL(map_fill_u64_kernel, dim3(grid_of(slots)), dim3(kMapThreads), 0, s, m->tab_keys, kEmptyKey,
                        slots);
@@ -478,6 +543,7 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
     if (mp->n_ids + n_points > cfg.max_ids) return AGS_ERR_CAPACITY;
     ags_ctx* ctx = mp->ctx;
     if (hipSetDevice(mp->device) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
+    flush_join(mp);
     hipStream_t s = (hipStream_t)stream;
     const MapDev m = dev_of(mp);
     KeyParams kp;
@@ -489,6 +555,8 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
     ScanTemp st;
     st.block_sums = mp->block_sums;
     // 1-3: probe, first points of new keys, ids, touch, reload marks
+    {
+    StageTimer tm(ctx, ST_MAP_PROBE, s);
     launch_fill_u32(mp->counters, 0u, 4, s);
     if (n_points > 0) {
         const unsigned g = grid_of(n_points);
@@ -507,6 +575,7 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
                                (long long)id_base, mp->reload_pos, mp->reload_list);
         }
     }
+    }
     uint32_t hc[4];
     if (hipMemcpyAsync(hc, mp->counters, sizeof(hc), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -519,8 +588,11 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return ctx_record_hip(ctx, hipGetLastError());
-        for (long long r = 0; r < n_reload; ++r)
-            memcpy(mp->pinned + r * row_f, mp->store + (size_t)mp->h_list[r] * row_f, row_f * sizeof(float));
+        parallel_rows(n_reload, 2048, [&](long long b, long long e) {
+            for (long long r = b; r < e; ++r)
+                memcpy(mp->pinned + r * row_f, mp->store + (size_t)mp->h_list[r] * row_f, row_f * sizeof(float));
+        });
+        StageTimer tm(ctx, ST_MAP_COPY, s);
         if (hipMemcpyAsync(mp->stage_in, mp->pinned, row_f * sizeof(float) * (size_t)n_reload,
                            hipMemcpyHostToDevice, s) != hipSuccess)
             return ctx_record_hip(ctx, hipGetLastError());
@@ -536,6 +608,7 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
     const long long n_keep = l.n_list < cfg.tau ? l.n_list : cfg.tau;
     const long long n_evict = l.n_list - n_keep;
     if (n_evict > 0) {
+        StageTimer tm(ctx, ST_MAP_LRU, s);
         const unsigned g = grid_of(l.n_list);
         hipLaunchKernelGGL(map_lru_keys_kernel, dim3(g), dim3(kMapThreads), 0, s, m, l, mp->keys[0], mp->vals[0]);
         int bits = 0;
@@ -551,6 +624,7 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
     }
     // 6: the new resident set and the offloaded rows
     if (l.n_list > 0) {
+        StageTimer tm(ctx, ST_MAP_REBUILD, s);
         RebuildArgs a;
         memset(&a, 0, sizeof(a));
         a.l = l;
@@ -586,14 +660,29 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
                            m);
     }
     if (n_evict > 0) {
-        if (hipMemcpyAsync(mp->pinned, mp->stage_out, row_f * sizeof(float) * (size_t)n_evict,
-                           hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(mp->h_evicted.data(), mp->evict_ids, 4 * (size_t)n_evict, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return ctx_record_hip(ctx, hipGetLastError());
-        for (long long e = 0; e < n_evict; ++e)
-            memcpy(mp->store + (size_t)mp->h_evicted[e] * row_f, mp->pinned + e * row_f, row_f * sizeof(float));
+        {
+            StageTimer tm(ctx, ST_MAP_COPY, s);
+            if (hipMemcpyAsync(mp->pinned, mp->stage_out, row_f * sizeof(float) * (size_t)n_evict,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(mp->h_evicted.data(), mp->evict_ids, 4 * (size_t)n_evict, hipMemcpyDeviceToHost,
+                               s) != hipSuccess)
+                return ctx_record_hip(ctx, hipGetLastError());
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
+        // the rows go into the host store on a host thread while the caller goes on; the
+        // next call (or ags_map_sync / read_store / destroy) waits for it first
+        auto write_rows = [mp, n_evict, row_f]() {
+            parallel_rows(n_evict, 2048, [&](long long b, long long e) {
+                for (long long r = b; r < e; ++r)
+                    memcpy(mp->store + (size_t)mp->h_evicted[r] * row_f, mp->pinned + r * row_f,
+                           row_f * sizeof(float));
+            });
+        };
+        try {
+            mp->flush = std::thread(write_rows);
+        } catch (...) {
+            write_rows();  // no thread available: write them now
+        }
     } else if (hipStreamSynchronize(s) != hipSuccess) {
         return ctx_record_hip(ctx, hipGetLastError());
     }
@@ -629,9 +718,16 @@ int ags_map_export(ags_map* mp, uint64_t* keys, int32_t* last_used, uint8_t* res
     return AGS_OK;
 }
 
+int ags_map_sync(ags_map* mp) {
+    if (!mp) return AGS_ERR_INVALID_ARG;
+    flush_join(mp);
+    return AGS_OK;
+}
+
 int ags_map_read_store(ags_map* mp, const int32_t* ids, int64_t n, float* rows) {
     if (!mp || n < 0 || (n > 0 && (!ids || !rows))) return AGS_ERR_INVALID_ARG;
     if (n == 0) return AGS_OK;
+    flush_join(mp);
     std::vector<uint8_t> res((size_t)mp->n_ids);
     if (hipSetDevice(mp->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         (mp->n_ids > 0 && hipMemcpy(res.data(), mp->id_res, (size_t)mp->n_ids, hipMemcpyDeviceToHost) != hipSuccess))

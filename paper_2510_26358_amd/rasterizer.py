@@ -382,7 +382,7 @@ class Rasterizer:
         L.check(self.lib.ags_profile_enable(self.ctx, int(enable)), "ags_profile_enable")
 
     def profile_read(self):
-        n = 16
+        n = 32
         names = (C.c_char_p * n)()
         tot = (C.c_double * n)()
         cnt = (C.c_int64 * n)()

@@ -97,6 +97,10 @@ class VoxelMap:
         res = (point_id[:M], counts)
         return res + (ev[:counts["n_evicted"]],) if evicted else res
 
+    def sync(self):
+        """Wait until the host store holds the rows the last insertion offloaded."""
+        L.check(self.lib.ags_map_sync(self.h), "ags_map_sync", self.ctx)
+
     def export(self):
         """Per-id keys (uint64), last_used (int32), resident (bool), and the table's keys / ids."""
         n_ids, n_slots = C.c_int64(), C.c_int64()
