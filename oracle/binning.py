@@ -10,8 +10,17 @@ that order as a plain definition so the kernel's lists can be compared bit for b
       x_lo = floor((u - ex) - 0.5), x_hi = ceil((u + ex) - 0.5), clamped to [0, W-1]
       y_lo = floor((v - ey) - 0.5), y_hi = ceil((v + ey) - 0.5), clamped to [0, H-1]
       empty when x_lo > x_hi or y_lo > y_hi (or when the pair is culled)
-  tile rectangle: x_lo // T .. x_hi // T, y_lo // T .. y_hi // T
-  one intersection per (view b, Gaussian i, tile) with global tile id
+  tile rectangle: x_lo // T .. x_hi // T, y_lo // T .. y_hi // T (the candidate tiles)
+  a candidate tile is kept when the alpha >= alpha_min ellipse reaches the rectangle of its
+      pixel centres [x0 + 1/2, x1 - 1/2] x [y0 + 1/2, y1 - 1/2] (clipped to the image):
+      with d = pixel centre - (u, v) and Q(d) = a dx^2 + 2 b dx dy + c dy^2 (the conic), the
+      minimum of Q over that rectangle is at most tau2 = 1.001 ex^2 (a c - b^2) / c + 0.001
+      (ex^2 (a c - b^2) / c is the level 2 ln(o / alpha_min) whose bounding box has the
+      half-width ex; the margin keeps the test conservative under rounding).  The minimum is
+      0 when the centre lies inside, else the least of the four edge minima (on an edge the
+      quadratic's minimiser clamped to the edge); every step is one rounded float32 operation
+      in the order written in `tile_reached`, so the decision is reproducible bit for bit.
+  one intersection per (view b, Gaussian i, kept tile) with global tile id
       tile_base[b] + ty * ntx_b + tx and key (tile_id << 32) | bits(float32 depth)
   emitted in (b, i, ty, tx) order and stably sorted by key; ranges[tile] = [first, last+1).
 
@@ -46,12 +55,54 @@ def pixel_rect_f32(u, v, ex, ey, width, height):
     return x0, y0, x1, y1, nonempty
 
 
-def bin_reference(records, views, T: int):
-    """records: list per view of dict(u, v, ex, ey, z (float32 arrays over the view's
-    Gaussian range), valid (bool)); views: list of (width, height, g_begin).
+_F = np.float32
 
-    Returns keys (uint64, sorted), vals (uint32 Gaussian index), ranges (n_tiles, 2) uint32,
-    counts per (view, local Gaussian) (list of int64 arrays), tile_base (n_views+1)."""
+
+def tile_tau2(a, b, c, ex):
+    """1.001 ex^2 (a c - b^2) / c + 0.001, each step rounded to float32."""
+    a, b, c, ex = (np.asarray(x, np.float32) for x in (a, b, c, ex))
+    det = a * c - b * b
+    t = (ex * ex) * det / c
+    return t * _F(1.001) + _F(1e-3)
+
+
+def _edge_q(a, b, c, X, lo, hi):
+    """min over y in [lo, hi] of a X^2 + 2 b X y + c y^2 (float32 steps)."""
+    y = (-(b * X)) / c
+    y = np.fmin(np.fmax(y, lo), hi)
+    t1 = (a * X) * X
+    t2 = ((_F(2) * b) * X) * y
+    t3 = (c * y) * y
+    return (t1 + t2) + t3
+
+
+def tile_reached(u, v, a, b, c, tau2, tx, ty, T, W, H):
+    """Whether the ellipse Q(d) <= tau2 reaches the pixel centres of tile (tx, ty)
+    (arrays broadcast; float32 steps; a NaN minimum keeps the tile)."""
+    u, v, a, b, c, tau2 = (np.asarray(x, np.float32) for x in (u, v, a, b, c, tau2))
+    tx = np.asarray(tx, np.int64)
+    ty = np.asarray(ty, np.int64)
+    X0 = (tx * T).astype(np.float32) + _F(0.5)
+    X1 = np.minimum((tx + 1) * T, W).astype(np.float32) - _F(0.5)
+    Y0 = (ty * T).astype(np.float32) + _F(0.5)
+    Y1 = np.minimum((ty + 1) * T, H).astype(np.float32) - _F(0.5)
+    lx, hx, ly, hy = X0 - u, X1 - u, Y0 - v, Y1 - v
+    inside = (lx <= 0) & (hx >= 0) & (ly <= 0) & (hy >= 0)
+    with np.errstate(all="ignore"):
+        q = _edge_q(a, b, c, lx, ly, hy)
+        q = np.fmin(q, _edge_q(a, b, c, hx, ly, hy))
+        q = np.fmin(q, _edge_q(c, b, a, ly, lx, hx))
+        q = np.fmin(q, _edge_q(c, b, a, hy, lx, hx))
+        return inside | ~(q > tau2)
+
+
+def bin_reference(records, views, T: int):
+    """records: list per view of dict(u, v, a, b, c, ex, ey, z (float32 arrays over the
+    view's Gaussian range), valid (bool)); views: list of (width, height, g_begin).
+
+    Returns keys (uint64, sorted, kept intersections), vals (uint32 Gaussian index), ranges
+    (n_tiles, 2) uint32, counts per (view, local Gaussian) of candidate tiles (list of int64
+    arrays), tile_base (n_views+1)."""
     tile_base = [0]
     for (W, H, _g0) in views:
         ntx, nty = tile_grid(W, H, T)
@@ -65,10 +116,14 @@ def bin_reference(records, views, T: int):
         cnt = np.where(ok, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0)
         counts.append(cnt)
         zbits = np.asarray(rec["z"], np.float32).view(np.uint32).astype(np.uint64)
+        tau2 = tile_tau2(rec["a"], rec["b"], rec["c"], rec["ex"])
         for i in np.nonzero(ok)[0]:
             ty = np.arange(ty0[i], ty1[i] + 1)
             tx = np.arange(tx0[i], tx1[i] + 1)
-            tiles = (tile_base[b] + ty[:, None] * ntx + tx[None, :]).ravel().astype(np.uint64)
+            TY, TX = np.meshgrid(ty, tx, indexing="ij")
+            keep = tile_reached(rec["u"][i], rec["v"][i], rec["a"][i], rec["b"][i], rec["c"][i], tau2[i],
+                                TX, TY, T, W, H).ravel()
+            tiles = (tile_base[b] + TY * ntx + TX).ravel().astype(np.uint64)[keep]
             keys_l.append((tiles << np.uint64(32)) | zbits[i])
             vals_l.append(np.full(len(tiles), g0 + i, np.uint32))
     keys = np.concatenate(keys_l) if keys_l else np.zeros(0, np.uint64)

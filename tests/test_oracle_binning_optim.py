@@ -7,7 +7,9 @@ import numpy as np
 import scipy.linalg
 import torch
 
-from oracle.binning import bin_reference, pixel_rect_f32, tile_grid
+import scipy.optimize
+
+from oracle.binning import bin_reference, pixel_rect_f32, tile_grid, tile_reached, tile_tau2
 from oracle.geometry import se3_exp, skew
 from oracle.optim import adam_update, pose_update
 from oracle.render import leaves, project, render
@@ -16,14 +18,36 @@ from paper_2510_26358_amd.scenes import tiny_scene
 
 
 def _random_records(rng, n, W, H):
+    """Seeded projected Gaussians: centre, a random positive-definite screen covariance
+    (conic = its inverse), opacity, and the footprint half-widths of the alpha = 1/255 level
+    (so that the tile test prunes the rectangle's corners)."""
     u = rng.uniform(-40, W + 40, n).astype(np.float32)
     v = rng.uniform(-40, H + 40, n).astype(np.float32)
-    ex = rng.exponential(8.0, n).astype(np.float32)
-    ey = rng.exponential(8.0, n).astype(np.float32)
+    sx = rng.exponential(4.0, n) + 0.3
+    sy = rng.exponential(4.0, n) + 0.3
+    rho = rng.uniform(-0.95, 0.95, n)
+    cxx, cyy, cxy = sx * sx, sy * sy, rho * sx * sy
+    det = cxx * cyy - cxy * cxy
+    o = rng.uniform(0.01, 0.99, n)
+    tau = 2 * np.log(255 * o)
+    a, b, c = (cyy / det).astype(np.float32), (-cxy / det).astype(np.float32), (cxx / det).astype(np.float32)
+    ex = np.sqrt(tau * cxx).astype(np.float32)
+    ey = np.sqrt(tau * cyy).astype(np.float32)
     # quantised depths so that exact key ties occur and stability matters
     z = (np.round(rng.uniform(0.5, 3.0, n) * 8) / 8).astype(np.float32)
     valid = rng.uniform(size=n) > 0.2
-    return {"u": u, "v": v, "ex": ex, "ey": ey, "z": z, "valid": valid}
+    return {"u": u, "v": v, "a": a, "b": b, "c": c, "ex": ex, "ey": ey, "z": z, "valid": valid,
+            "o": o.astype(np.float32)}
+
+
+def _box_min(a, b, c, lo, hi):
+    """min of d^T K d over the box lo <= d <= hi (K = [[a, b], [b, c]]) in float64, as the
+    bounded least-squares problem min |L^T d|^2 (K = L L^T) solved by scipy."""
+    K = np.array([[a, b], [b, c]], np.float64)
+    L = np.linalg.cholesky(K)
+    r = scipy.optimize.lsq_linear(L.T, np.zeros(2), bounds=(lo, hi), method="bvls")
+    d = r.x
+    return float(d @ K @ d)
 
 
 def test_binning_reference_equals_brute_force_enumeration():
@@ -32,10 +56,14 @@ def test_binning_reference_equals_brute_force_enumeration():
     views = [(64, 40, 0), (50, 30, 300)]
     recs = [_random_records(rng, 300, 64, 40), _random_records(rng, 200, 50, 30)]
     keys, vals, ranges, counts, base = bin_reference(recs, views, T)
-    # brute force: for every tile of every view test whether any pixel of the tile lies in
-    # the footprint rectangle (pixel-level test, then Python's stable sort on the key)
-    items = []
+    # brute force: every tile of every view that holds a pixel of the footprint rectangle is
+    # a candidate; it is kept when the float64 minimum of the conic's quadratic form over its
+    # pixel centres (scipy's bounded least squares) is at most 1.001 ex^2 det / c + 0.001.
+    # Candidates whose minimum lies within 1e-4 (relative) of that level are ambiguous in
+    # float32 and left out of the comparison on both sides.
+    items, ambiguous = [], set()
     tile0 = 0
+    n_cand = 0
     for b, ((W, H, g0), r) in enumerate(zip(views, recs)):
         ntx, nty = tile_grid(W, H, T)
         for i in range(len(r["u"])):
@@ -46,19 +74,31 @@ def test_binning_reference_equals_brute_force_enumeration():
             xhi = math.ceil(float(np.float32(np.float32(u + ex) - np.float32(0.5))))
             ylo = math.floor(float(np.float32(np.float32(v - ey) - np.float32(0.5))))
             yhi = math.ceil(float(np.float32(np.float32(v + ey) - np.float32(0.5))))
+            A, B, C = (float(r[k][i]) for k in ("a", "b", "c"))
+            lev = 1.001 * float(ex) ** 2 * (A * C - B * B) / C + 0.001
             for ty in range(nty):
                 for tx in range(ntx):
-                    hit = any(xlo <= px <= xhi and ylo <= py <= yhi
-                              for py in range(ty * T, min(H, ty * T + T))
-                              for px in range(tx * T, min(W, tx * T + T)))
-                    if hit:
+                    cand = any(xlo <= px <= xhi and ylo <= py <= yhi
+                               for py in range(ty * T, min(H, ty * T + T))
+                               for px in range(tx * T, min(W, tx * T + T)))
+                    if not cand:
+                        continue
+                    n_cand += 1
+                    lo = np.array([tx * T + 0.5 - float(u), ty * T + 0.5 - float(v)])
+                    hi = np.array([min(W, tx * T + T) - 0.5 - float(u), min(H, ty * T + T) - 0.5 - float(v)])
+                    q = _box_min(A, B, C, lo, hi)
+                    tid = tile0 + ty * ntx + tx
+                    if abs(q - lev) <= 1e-4 * max(1.0, lev):
+                        ambiguous.add((tid, g0 + i))
+                    elif q <= lev:
                         zb = int(np.float32(r["z"][i]).view(np.uint32))
-                        items.append((((tile0 + ty * ntx + tx) << 32) | zb, g0 + i))
+                        items.append((((tid) << 32) | zb, g0 + i))
         tile0 += ntx * nty
     items.sort(key=lambda e: e[0])  # Python's sort is stable: ties keep emission order
-    assert len(items) == len(keys)
-    assert [k for k, _ in items] == keys.tolist()
-    assert [g for _, g in items] == vals.tolist()
+    assert sum(int(cn.sum()) for cn in counts) == n_cand
+    got = [(int(k), int(g)) for k, g in zip(keys, vals) if (int(k) >> 32, int(g)) not in ambiguous]
+    assert got == items
+    assert len(items) < n_cand  # the test prunes some candidates
     # ranges: every tile's slice holds exactly its keys
     tiles = (keys >> np.uint64(32)).astype(np.int64)
     for t in range(base[-1]):
@@ -68,8 +108,9 @@ def test_binning_reference_equals_brute_force_enumeration():
 
 
 def test_every_contributing_pixel_lies_in_its_gaussians_tiles():
-    """The opacity-aware bounding box must cover every pixel where the brute-force
-    compositing keeps the Gaussian (alpha >= 1/255), for each tile size."""
+    """The opacity-aware bounding box, and the ellipse test on its tiles, must cover every
+    pixel where the brute-force compositing keeps the Gaussian (alpha >= 1/255), for each
+    tile size."""
     sc = tiny_scene()
     s = RenderSettings()
     out = render(sc, s)[0]
@@ -78,13 +119,19 @@ def test_every_contributing_pixel_lies_in_its_gaussians_tiles():
     W, H = 128, 96
     ext = pr["ext"].numpy()
     x0, y0, x1, y1, ne = pixel_rect_f32(pr["u"].numpy(), pr["v"].numpy(), ext[:, 0], ext[:, 1], W, H)
+    con = pr["conic"].detach().numpy().astype(np.float32)
+    u32, v32 = pr["u"].detach().numpy().astype(np.float32), pr["v"].detach().numpy().astype(np.float32)
+    tau2 = tile_tau2(con[:, 0], con[:, 1], con[:, 2], ext[:, 0].astype(np.float32))
+    gi = np.array([i for p in range(W * H) for i in dec.touched[p]], np.int64)
+    pp = np.array([p for p in range(W * H) for _ in dec.touched[p]], np.int64)
+    px, py = pp % W, pp // W
+    assert ne[gi].all()
     for T in (8, 16, 32):
-        ntx, _ = tile_grid(W, H, T)
-        for p in range(W * H):
-            px, py = p % W, p // W
-            for i in dec.touched[p]:
-                assert ne[i]
-                assert x0[i] // T <= px // T <= x1[i] // T and y0[i] // T <= py // T <= y1[i] // T
+        assert ((x0[gi] // T <= px // T) & (px // T <= x1[gi] // T)).all()
+        assert ((y0[gi] // T <= py // T) & (py // T <= y1[gi] // T)).all()
+        # the ellipse test keeps the tile of every pixel that uses the Gaussian
+        assert tile_reached(u32[gi], v32[gi], con[gi, 0], con[gi, 1], con[gi, 2], tau2[gi], px // T, py // T,
+                            T, W, H).all()
 
 
 def test_adam_matches_torch_adam_in_float64():
