@@ -17,9 +17,10 @@ that order as a plain definition so the kernel's lists can be compared bit for b
       minimum of Q over that rectangle is at most tau2 = 1.001 ex^2 (a c - b^2) / c + 0.001
       (ex^2 (a c - b^2) / c is the level 2 ln(o / alpha_min) whose bounding box has the
       half-width ex; the margin keeps the test conservative under rounding).  The minimum is
-      0 when the centre lies inside, else the least of the four edge minima (on an edge the
-      quadratic's minimiser clamped to the edge); every step is one rounded float32 operation
-      in the order written in `tile_reached`, so the decision is reproducible bit for bit.
+      0 when the centre lies inside, else it lies at a corner or at an edge's interior
+      minimiser (tested without division, see `tile_reached`); every step is one rounded
+      float32 operation in the order written there, so the decision is reproducible bit for
+      bit.
   one intersection per (view b, Gaussian i, kept tile) with global tile id
       tile_base[b] + ty * ntx_b + tx and key (tile_id << 32) | bits(float32 depth)
   emitted in (b, i, ty, tx) order and stably sorted by key; ranges[tile] = [first, last+1).
@@ -66,19 +67,17 @@ def tile_tau2(a, b, c, ex):
     return t * _F(1.001) + _F(1e-3)
 
 
-def _edge_q(a, b, c, X, lo, hi):
-    """min over y in [lo, hi] of a X^2 + 2 b X y + c y^2 (float32 steps)."""
-    y = (-(b * X)) / c
-    y = np.fmin(np.fmax(y, lo), hi)
-    t1 = (a * X) * X
-    t2 = ((_F(2) * b) * X) * y
-    t3 = (c * y) * y
-    return (t1 + t2) + t3
+def _q(a, b, c, x, y):
+    """a x^2 + 2 b x y + c y^2 in float32 steps."""
+    return ((a * x) * x + ((_F(2) * b) * x) * y) + (c * y) * y
 
 
 def tile_reached(u, v, a, b, c, tau2, tx, ty, T, W, H):
-    """Whether the ellipse Q(d) <= tau2 reaches the pixel centres of tile (tx, ty)
-    (arrays broadcast; float32 steps; a NaN minimum keeps the tile)."""
+    """Whether the ellipse Q(d) <= tau2 reaches the pixel centres of tile (tx, ty): the centre
+    inside the rectangle, a corner with Q <= tau2, or an edge whose interior holds the
+    quadratic's minimiser along it with that minimum, X^2 (a c - b^2) / c (for x = X),
+    at most tau2 -- compared as X^2 det <= tau2 c, so that no step divides.  Arrays
+    broadcast; float32 steps; a NaN keeps the tile."""
     u, v, a, b, c, tau2 = (np.asarray(x, np.float32) for x in (u, v, a, b, c, tau2))
     tx = np.asarray(tx, np.int64)
     ty = np.asarray(ty, np.int64)
@@ -87,13 +86,19 @@ def tile_reached(u, v, a, b, c, tau2, tx, ty, T, W, H):
     Y0 = (ty * T).astype(np.float32) + _F(0.5)
     Y1 = np.minimum((ty + 1) * T, H).astype(np.float32) - _F(0.5)
     lx, hx, ly, hy = X0 - u, X1 - u, Y0 - v, Y1 - v
-    inside = (lx <= 0) & (hx >= 0) & (ly <= 0) & (hy >= 0)
+    det = a * c - b * b
     with np.errstate(all="ignore"):
-        q = _edge_q(a, b, c, lx, ly, hy)
-        q = np.fmin(q, _edge_q(a, b, c, hx, ly, hy))
-        q = np.fmin(q, _edge_q(c, b, a, ly, lx, hx))
-        q = np.fmin(q, _edge_q(c, b, a, hy, lx, hx))
-        return inside | ~(q > tau2)
+        hit = (lx <= 0) & (hx >= 0) & (ly <= 0) & (hy >= 0)
+        for x in (lx, hx):
+            for y in (ly, hy):
+                hit = hit | ~(_q(a, b, c, x, y) > tau2)
+        for X in (lx, hx):       # edges x = X: minimiser y = -b X / c inside [ly, hy]
+            m = -(b * X)
+            hit = hit | ((c * ly <= m) & (m <= c * hy) & ~((X * X) * det > tau2 * c))
+        for Y in (ly, hy):       # edges y = Y: minimiser x = -b Y / a inside [lx, hx]
+            m = -(b * Y)
+            hit = hit | ((a * lx <= m) & (m <= a * hx) & ~((Y * Y) * det > tau2 * a))
+    return hit
 
 
 def bin_reference(records, views, T: int):

@@ -112,8 +112,8 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.P = pix;
     L.n_tiles = tiles;
     L.cap = cap;
-    int bits = 0;
-    while ((1LL << bits) < tiles) ++bits;
+    int bits = 0;  // tile ids 0 .. tiles - 1 and the key `tiles` of dropped intersections
+    while ((1LL << bits) <= tiles) ++bits;
     L.tile_bits = bits;
     L.depth_grid = sort_grid(L.Q);
     L.tile_grid = sort_grid(L.cap);

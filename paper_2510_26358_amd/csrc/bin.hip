@@ -17,9 +17,12 @@ namespace ags {
 // is slot k - emit_off[j] of that pair's tile rectangle (row-major).  A workgroup fills
 // kEmitSlots consecutive slots; since every visible pair owns >= 1 slot, they belong to at
 // most kEmitSlots consecutive pairs starting at block_first[workgroup].  Their offsets, and
-// for each pair the tile id of its rectangle's first tile, its width and the row pitch, are
-// staged in LDS (one thread per pair), and each slot binary-searches there.  Balanced
-// however unequal the footprints are, and the writes are coalesced.
+// for each pair the rectangle's first tile, its width, the view and the ellipse (centre,
+// conic, level), are staged in LDS (one thread per pair); each pair marks its first slot
+// and a prefix maximum over the slots gives every slot its pair.  A slot whose tile the
+// alpha >= alpha_min ellipse does not reach (tile_reached) gets the key n_tiles, which the
+// tile sort moves behind every list.  Balanced however unequal the footprints are, and the
+// writes are coalesced.
 constexpr int kEmitThreads = 256;
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const float* records,
@@ -29,64 +32,108 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
                                                             uint32_t* tile_vals) {
     constexpr int S = kEmitSlots, PT = S / kEmitThreads;
     __shared__ uint32_t s_off[S];
-    __shared__ uint32_t s_q[S], s_first[S], s_w[S], s_pitch[S];
+    __shared__ uint32_t s_own[S];                     // slot -> local pair index
+    __shared__ uint32_t s_q[S], s_first[S];           // pair, global id of the rectangle's first tile
+    __shared__ uint32_t s_wp[S], s_org[S], s_wh[S];   // width | pitch << 16, tx0 | ty0 << 16, W | H << 16
+    __shared__ float4 s_ell[S];                       // u, v, a, b
+    __shared__ float2 s_ell2[S];                      // c, level
+    __shared__ uint32_t s_wmax[kEmitThreads / 64];
     const long long k0 = (long long)blockIdx.x * S;
     long long keff = counters[CNT_KEFF];
     if (keff > capacity) keff = capacity;
     const long long nv = counters[CNT_V];
     if (k0 >= keff || nv == 0) return;  // uniform per workgroup
     const long long j0 = block_first[blockIdx.x];
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < PT; ++c) {
-        const long long j = j0 + c * kEmitThreads + t;
-        s_off[c * kEmitThreads + t] = j < nv ? emit_off[j] : 0xFFFFFFFFu;
-    }
-    __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t n_tiles = (uint32_t)vt.tile_base[vt.n_views];
     // pairs starting at or beyond the workgroup's last slot are not needed
     const long long kend = k0 + S < keff ? k0 + S : keff;
 #pragma unroll
     for (int c = 0; c < PT; ++c) {
         const int l = c * kEmitThreads + t;
-        if ((long long)s_off[l] < kend) {
-            const uint32_t q = depth_vals[j0 + l];
+        const long long j = j0 + l;
+        const uint32_t off = j < nv ? emit_off[j] : 0xFFFFFFFFu;
+        s_off[l] = off;
+        s_own[l] = 0u;
+        if ((long long)off < kend) {
+            const uint32_t q = depth_vals[j];
             const int b = view_of_pair(vt, q);
             const float4* rec = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
             const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+            const int W = vt.width[b], H = vt.height[b];
             int tx0 = 0, ty0 = 0, tx1 = 0, ty1 = 0;
-            tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1);
+            tile_rect(r0.x, r0.y, r1.w, r2.x, W, H, vt.tile, tx0, ty0, tx1, ty1);
             s_q[l] = q;
             s_first[l] = (uint32_t)(vt.tile_base[b] + ty0 * vt.ntx[b] + tx0);
-            s_w[l] = (uint32_t)(tx1 - tx0 + 1);
-            s_pitch[l] = (uint32_t)vt.ntx[b];
+            s_wp[l] = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)vt.ntx[b] << 16);
+            s_org[l] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+            s_wh[l] = (uint32_t)W | ((uint32_t)H << 16);
+            s_ell[l] = make_float4(r0.x, r0.y, r0.z, r0.w);
+            s_ell2[l] = make_float2(r1.x, tile_tau2(r0.z, r0.w, r1.x, r1.w));
         }
+    }
+    __syncthreads();
+    // slot -> pair: each pair after the first marks its first slot, a prefix maximum fills the
+    // rest (every visible pair owns at least one slot, so the marks are distinct)
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        const int l = c * kEmitThreads + t;
+        const long long off = (long long)s_off[l];
+        if (l > 0 && off < kend) s_own[off - k0] = (uint32_t)l;
+    }
+    __syncthreads();
+    {
+        uint32_t v[PT], m = 0;
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            v[i] = max(m, s_own[PT * t + i]);
+            m = v[i];
+        }
+        uint32_t incl = m;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+            if (lane >= o) incl = max(incl, y);
+        }
+        if (lane == 63) s_wmax[wv] = incl;
+        uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, 64);
+        if (lane == 0) excl = 0;
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < kEmitThreads / 64; ++x)
+            if (x < wv) excl = max(excl, s_wmax[x]);
+#pragma unroll
+        for (int i = 0; i < PT; ++i) s_own[PT * t + i] = max(excl, v[i]);
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < PT; ++c) {
         const long long k = k0 + c * kEmitThreads + t;
         if (k >= keff) break;
-        int lo = 0, hi = S - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((long long)s_off[mid] <= k) lo = mid;
-            else hi = mid - 1;
-        }
+        const uint32_t lo = s_own[k - k0];
         const uint32_t r = (uint32_t)(k - (long long)s_off[lo]);
-        const uint32_t w = s_w[lo];
-        const uint32_t row = r / w;
-        tile_keys[k] = s_first[lo] + row * s_pitch[lo] + (r - row * w);
+        const uint32_t wp = s_wp[lo], org = s_org[lo], wh = s_wh[lo];
+        const uint32_t w = wp & 0xFFFFu;
+        const uint32_t row = r / w, col = r - row * w;
+        const int tx = (int)(org & 0xFFFFu) + (int)col;
+        const int ty = (int)(org >> 16) + (int)row;
+        const float4 e = s_ell[lo];
+        const float2 e2 = s_ell2[lo];
+        const bool hit = tile_reached(e.x, e.y, e.z, e.w, e2.x, e2.y, tx, ty, vt.tile, (int)(wh & 0xFFFFu),
+                                      (int)(wh >> 16));
+        tile_keys[k] = hit ? s_first[lo] + row * (wp >> 16) + col : n_tiles;
         tile_vals[k] = s_q[lo];
     }
 }
 
 __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* counters, long long n_max,
-                              uint32_t* ranges) {
+                              uint32_t n_tiles, uint32_t* ranges) {
     long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long n = counters[CNT_KEFF];
     if (n > n_max) n = n_max;
     if (k >= n) return;
     uint32_t t = keys[k];
+    if (t >= n_tiles) return;  // intersections the ellipse test dropped sort last
     if (k == 0 || keys[k - 1] != t) ranges[2 * (long long)t] = (uint32_t)k;
     if (k == n - 1 || keys[k + 1] != t) ranges[2 * (long long)t + 1] = (uint32_t)(k + 1);
 }
@@ -150,7 +197,7 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     const long long n_tiles = a.vt.tile_base[a.vt.n_views];
     launch_fill_u32(a.ranges, 0u, 2 * n_tiles, s);
     hipLaunchKernelGGL(ranges_kernel, dim3(kgrid), dim3(256), 0, s, tk[rt], a.counters, a.capacity,
-                       a.ranges);
+                       (uint32_t)n_tiles, a.ranges);
     (void)tv;
     return (int)hipGetLastError();
 }

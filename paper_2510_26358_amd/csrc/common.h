@@ -74,6 +74,53 @@ __device__ __forceinline__ bool tile_rect(float u, float v, float ex, float ey, 
     return true;
 }
 
+// Level of the alpha >= alpha_min ellipse for the tile test: ex^2 (a c - b^2) / c is
+// 2 ln(o / alpha_min), the level whose bounding box has the footprint half-width ex; a
+// relative margin of 1e-3 plus 1e-3 keeps the test conservative under rounding.
+__device__ __forceinline__ float tile_tau2(float a, float b, float c, float ex) {
+    const float det = __fsub_rn(__fmul_rn(a, c), __fmul_rn(b, b));
+    const float t = __fdiv_rn(__fmul_rn(__fmul_rn(ex, ex), det), c);
+    return __fadd_rn(__fmul_rn(t, 1.001f), 1e-3f);
+}
+
+// a x^2 + 2 b x y + c y^2, explicitly rounded steps.
+__device__ __forceinline__ float tile_q(float a, float b, float c, float x, float y) {
+    const float t1 = __fmul_rn(__fmul_rn(a, x), x);
+    const float t2 = __fmul_rn(__fmul_rn(__fmul_rn(2.f, b), x), y);
+    const float t3 = __fmul_rn(__fmul_rn(c, y), y);
+    return __fadd_rn(__fadd_rn(t1, t2), t3);
+}
+
+// Whether the ellipse Q(d) = a dx^2 + 2 b dx dy + c dy^2 <= tau2 (d = pixel centre - (u, v))
+// reaches the pixel centres of tile (tx, ty) of a W x H view: (u, v) inside the rectangle of
+// those centres, a corner with Q <= tau2, or an edge whose interior holds the quadratic's
+// minimiser along it with that minimum, X^2 (a c - b^2) / c for x = X, at most tau2
+// (compared as X^2 det <= tau2 c: no division).  Every step is one explicitly rounded
+// single-precision operation, so that the decision can be reproduced bit for bit; NaN keeps
+// the tile.
+__device__ __forceinline__ bool tile_reached(float u, float v, float a, float b, float c, float tau2, int tx,
+                                             int ty, int T, int W, int H) {
+    const float X0 = (float)(tx * T) + 0.5f;
+    const float X1 = (float)((tx + 1) * T < W ? (tx + 1) * T : W) - 0.5f;
+    const float Y0 = (float)(ty * T) + 0.5f;
+    const float Y1 = (float)((ty + 1) * T < H ? (ty + 1) * T : H) - 0.5f;
+    const float lx = __fsub_rn(X0, u), hx = __fsub_rn(X1, u), ly = __fsub_rn(Y0, v), hy = __fsub_rn(Y1, v);
+    const float det = __fsub_rn(__fmul_rn(a, c), __fmul_rn(b, b));
+    bool hit = lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f;
+    hit |= !(tile_q(a, b, c, lx, ly) > tau2);
+    hit |= !(tile_q(a, b, c, lx, hy) > tau2);
+    hit |= !(tile_q(a, b, c, hx, ly) > tau2);
+    hit |= !(tile_q(a, b, c, hx, hy) > tau2);
+    const float tc = __fmul_rn(tau2, c), ta = __fmul_rn(tau2, a);
+    const float cly = __fmul_rn(c, ly), chy = __fmul_rn(c, hy), alx = __fmul_rn(a, lx), ahx = __fmul_rn(a, hx);
+    const float m0 = -__fmul_rn(b, lx), m1 = -__fmul_rn(b, hx), m2 = -__fmul_rn(b, ly), m3 = -__fmul_rn(b, hy);
+    hit |= cly <= m0 && m0 <= chy && !(__fmul_rn(__fmul_rn(lx, lx), det) > tc);
+    hit |= cly <= m1 && m1 <= chy && !(__fmul_rn(__fmul_rn(hx, hx), det) > tc);
+    hit |= alx <= m2 && m2 <= ahx && !(__fmul_rn(__fmul_rn(ly, ly), det) > ta);
+    hit |= alx <= m3 && m3 <= ahx && !(__fmul_rn(__fmul_rn(hy, hy), det) > ta);
+    return hit;
+}
+
 // Real spherical harmonics (Condon-Shortley phase, l-major, m = -l..l) as polynomials in
 // the unit direction; the constants are the normalisations sqrt((2l+1)/(4pi)(l-m)!/(l+m)!)
 // times the sqrt(2) of the real combination, folded into each monomial.

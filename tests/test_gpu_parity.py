@@ -88,21 +88,31 @@ def test_projection_records_match_oracle(ras):
 
 
 def _synthetic_records(rng, n_views, n, sizes, T):
+    """Seeded records: centre, conic of a random positive-definite screen covariance,
+    opacity, quantised depth (exact ties) and the half-widths of the alpha = 1/255 level."""
     recs, valid, ref_in = [], [], []
     for b in range(n_views):
         W, H = sizes[b]
         u = rng.uniform(-30, W + 30, n).astype(np.float32)
         v = rng.uniform(-30, H + 30, n).astype(np.float32)
-        ex = rng.exponential(6.0, n).astype(np.float32)
-        ey = rng.exponential(6.0, n).astype(np.float32)
+        sx = rng.exponential(3.0, n) + 0.3
+        sy = rng.exponential(3.0, n) + 0.3
+        rho = rng.uniform(-0.95, 0.95, n)
+        cxx, cyy, cxy = sx * sx, sy * sy, rho * sx * sy
+        det = cxx * cyy - cxy * cxy
+        o = rng.uniform(0.01, 0.99, n)
+        tau = 2 * np.log(255 * o)
+        ca, cb, cc = (cyy / det).astype(np.float32), (-cxy / det).astype(np.float32), (cxx / det).astype(np.float32)
+        ex = np.sqrt(tau * cxx).astype(np.float32)
+        ey = np.sqrt(tau * cyy).astype(np.float32)
         z = (np.round(rng.uniform(0.5, 4.0, n) * 16) / 16).astype(np.float32)  # exact ties
         ok = rng.uniform(size=n) > 0.25
         r = np.zeros((n, 12), np.float32)
-        r[:, 0], r[:, 1], r[:, 6], r[:, 7], r[:, 8] = u, v, z, ex, ey
-        r[:, 5] = 0.5
+        r[:, 0], r[:, 1], r[:, 2], r[:, 3], r[:, 4] = u, v, ca, cb, cc
+        r[:, 5], r[:, 6], r[:, 7], r[:, 8] = o.astype(np.float32), z, ex, ey
         recs.append(r)
         valid.append(ok)
-        ref_in.append({"u": u, "v": v, "ex": ex, "ey": ey, "z": z, "valid": ok})
+        ref_in.append({"u": u, "v": v, "a": ca, "b": cb, "c": cc, "ex": ex, "ey": ey, "z": z, "valid": ok})
     return np.concatenate(recs), np.concatenate(valid), ref_in
 
 
@@ -120,18 +130,24 @@ def test_binning_bit_exact_on_seeded_records(tile, sizes):
                      [(b + 1) * n for b in range(len(sizes))])
     keys, vals, ranges, counts, base = bin_reference(
         ref_in, [(w, h, b * n) for b, (w, h) in enumerate(sizes)], tile)
-    cap = max(len(keys), 1)
+    n_cand = int(sum(int(c.sum()) for c in counts))
+    cap = max(n_cand, 1)
     buf = r.buffers(views, N, 0, cap)
     r.bin_records(views, N, torch.from_numpy(recs).cuda(), torch.from_numpy(valid.astype(np.uint8)).cuda(), buf)
     torch.cuda.synchronize()
     sv = saved_arrays(buf, views)
-    assert sv["K"] == len(keys) and not sv["overflow"]
+    # K counts the candidate tiles; the ones the ellipse test drops carry the key n_tiles and
+    # sort behind every list
+    assert sv["K"] == n_cand and not sv["overflow"]
     assert np.array_equal(sv["pair_count"], np.concatenate(counts))
+    kept = len(keys)
+    assert kept <= n_cand
+    assert (sv["tile_keys"][kept:] == base[-1]).all()
     # pair ids -> Gaussian ids (view b's pairs start at pair_base[b] = b n and map to b n + local)
-    gauss = sv["tile_pairs"]  # here pair id == Gaussian id because ranges are [b n, (b+1) n)
+    gauss = sv["tile_pairs"][:kept]  # here pair id == Gaussian id because ranges are [b n, (b+1) n)
     assert np.array_equal(gauss, vals.astype(np.int64))
     zb = recs[:, 6].view(np.uint32).astype(np.uint64)[gauss]
-    gkeys = (sv["tile_keys"].astype(np.uint64) << np.uint64(32)) | zb
+    gkeys = (sv["tile_keys"][:kept].astype(np.uint64) << np.uint64(32)) | zb
     assert np.array_equal(gkeys, keys)
     assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
 
