@@ -255,9 +255,11 @@ def _source_digest(stage):
     return h.hexdigest()
 
 
-def measured_traffic(stage, workload):
+def measured_traffic(stage, workload, launch=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
-    this kernel and workload, or None when absent or when the kernel source changed since."""
+    this kernel and workload (for the launch configuration `launch` = (tile, pixels per
+    thread, LDS batch) when the summary lists several), or None when absent or when the
+    kernel source changed since."""
     path = os.path.join(PROFILES, f"{stage}_{workload}_counters.md")
     try:
         text = open(path).read()
@@ -270,13 +272,18 @@ def measured_traffic(stage, workload):
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != _source_digest(stage):
         return None
+    key = "hbm_bytes_per_launch"
+    if launch is not None and f"{key}[{','.join(str(x) for x in launch)}]" in vals:
+        key = f"{key}[{','.join(str(x) for x in launch)}]"
+    elif launch is not None and any(k.startswith(key + "[") for k in vals):
+        return None
     try:
-        return int(float(vals["hbm_bytes_per_launch"]))
+        return int(float(vals[key]))
     except (KeyError, ValueError):
         return None
 
 
-def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload):
+def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload, launch=None):
     """Roofline of the slowest stage, from the library's per-stage HIP events over a timed
     pass (events on the launch stream).  Algorithmic work per launch is stated in the design doc."""
     import torch
@@ -288,7 +295,7 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload)
     evals = int(last.sum())
     k, v, over, keff = buf.counters()
     info = {"stage": name, "avg_ms": ms_avg, "pairs_evaluated": evals, "K": int(k), "V": int(v)}
-    traffic = measured_traffic(name, workload)
+    traffic = measured_traffic(name, workload, launch)
     if name in FLOP_PER_PAIR:
         achieved = evals * FLOP_PER_PAIR[name] / (ms_avg * 1e-3) / 1e12
         rf = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_PEAK_TFLOPS, 2),
@@ -483,8 +490,10 @@ def main():
         ras.profile(False)
         stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1] > 0}
         log(f"[bench] per-stage avg ms: {stage_ms}")
+        launch = {"raster_bwd": (tile, ppt_b, batch_b), "raster_fwd": (tile, ppt, batch)}
+        top = max((k for k, v in prof.items() if v[1] > 0), key=lambda k: prof[k][0])
         roof, info = dominant_roofline(prof, views, over_buf, over_buf.sizes, args.steps, p.n,
-                                       (p.sh_degree + 1) ** 2, args.workload)
+                                       (p.sh_degree + 1) ** 2, args.workload, launch.get(top))
         info["stage_ms"] = stage_ms
         info["stages"] = stage_rooflines(stage_ms, info["pairs_evaluated"], P, p.n, (p.sh_degree + 1) ** 2,
                                          over_buf.sizes.n_pairs, info["V"], info["K"],
