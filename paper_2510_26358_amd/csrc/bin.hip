@@ -46,13 +46,16 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
     const long long j0 = block_first[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t n_tiles = (uint32_t)vt.tile_base[vt.n_views];
-    // pairs starting at or beyond the workgroup's last slot are not needed
+    // the workgroup's pairs: from the owner of its first slot to the owner of the next
+    // workgroup's first slot (or the last pair); pairs starting at or beyond the workgroup's
+    // last slot are not needed
     const long long kend = k0 + S < keff ? k0 + S : keff;
+    const long long jlast = k0 + S < keff ? (long long)block_first[blockIdx.x + 1] : nv - 1;
 #pragma unroll
     for (int c = 0; c < PT; ++c) {
         const int l = c * kEmitThreads + t;
         const long long j = j0 + l;
-        const uint32_t off = j < nv ? emit_off[j] : 0xFFFFFFFFu;
+        const uint32_t off = j <= jlast ? emit_off[j] : 0xFFFFFFFFu;
         s_off[l] = off;
         s_own[l] = 0u;
         if ((long long)off < kend) {
