@@ -619,7 +619,7 @@ def main():
                    "tile": tile, "lds_batch": batch, "px_per_thread": ppt, "lds_batch_bwd": batch_b,
                    "px_per_thread_bwd": ppt_b,
                    "autotuned": None if tuned is None else tuned["ms"],
-                   "visible_pairs": V, "intersections": K},
+                   "visible_pairs": V, "intersections": K, "tile_list_entries": over_buf.n_listed()},
         "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
         "with_ssim": with_ssim, "with_rendered_variance": with_rv, "lifecycle": lifecycle,
         "voxel_map": vmap,

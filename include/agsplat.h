@@ -189,13 +189,16 @@ typedef struct ags_sizes {
     int64_t n_pairs, n_pixels, n_tiles;
     int32_t tile_bits;       /* bits of the global tile id */
     /* offsets into `saved` */
-    size_t off_counters;     /* uint32[4]: K (all intersections), V (visible pairs),
-                                overflow flag (K > capacity), K kept (min(K, capacity)) */
+    size_t off_counters;     /* uint32[5]: K (all candidate intersections), V (visible
+                                pairs), overflow flag (K > capacity), K kept (min(K,
+                                capacity)), L (intersections in the tile lists: the kept
+                                candidates whose tile the alpha >= alpha_min ellipse reaches) */
     size_t off_records;      /* float[n_pairs][12]: u, v, conic a, b, c, opacity, z,
                                 ex, ey, r, g, b (written only for visible pairs) */
     size_t off_pair_count;   /* uint32[n_pairs]: tiles touched (0 = culled / off-screen) */
-    size_t off_tile_pairs;   /* uint32[capacity]: pair ids, grouped by global tile and
-                                ordered by (float32 depth bits, pair id) inside a tile */
+    size_t off_tile_pairs;   /* uint32[capacity]: the first L entries are pair ids, grouped
+                                by global tile and ordered by (float32 depth bits, pair id)
+                                inside a tile */
     size_t off_ranges;       /* uint32[n_tiles][2]: [start, end) into tile_pairs */
     size_t off_t_final;      /* float[P]: final transmittance */
     size_t off_last;         /* uint32[P]: tile-list entries up to the last contributor */
@@ -262,6 +265,11 @@ int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* params,
 int ags_pose_step(ags_ctx* ctx, const ags_adam* hp, ags_camera* cams, int32_t n_views,
                   const float* pose_grad, float* pose_m, float* pose_v, int32_t* step,
                   int32_t advance_step, void* stream);
+
+/* Debug aid, off the hot path: the number of non-finite values (NaN, +-inf) among all of
+ * g's parameters, written to *n_bad_dev (device int32).  Enqueued on the stream, no host
+ * synchronisation. */
+int ags_check_finite(ags_ctx* ctx, const ags_gaussians* g, int32_t* n_bad_dev, void* stream);
 
 /* Per-stage GPU time of the calls since the last reset (HIP events on the calls' streams;
  * enabling adds an event pair per kernel launch).  names: host array of n_max C strings. */

@@ -25,7 +25,7 @@ EXPORTED = [
     "ags_render_fwd", "ags_render_bwd", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
     "ags_lifecycle_step", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
-    "ags_map_export", "ags_map_read_store", "ags_map_sync",
+    "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
 ]
 
 
@@ -155,6 +155,7 @@ def load(path: str = LIB_PATH):
     lib.ags_map_export.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, P(C.c_int64), P(C.c_int64)]
     lib.ags_map_read_store.argtypes = [vp, vp, C.c_int64, vp]
     lib.ags_map_sync.argtypes = [vp]
+    lib.ags_check_finite.argtypes = [vp, P(Gaussians), vp, vp]
     lib.ags_lifecycle_workspace.argtypes = [C.c_int64, P(C.c_size_t)]
     lib.ags_lifecycle_step.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp,
                                        P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, C.c_size_t, vp]

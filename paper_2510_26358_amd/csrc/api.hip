@@ -715,6 +715,20 @@ int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussian
     return hip_status(ctx);
 }
 
+int ags_check_finite(ags_ctx* ctx, const ags_gaussians* g, int32_t* n_bad_dev, void* stream) {
+    if (!ctx || !n_bad_dev || check_gaussians(g)) return AGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(n_bad_dev), 0u, 1, s);
+    const long long n = g->n, k3 = 3LL * (g->sh_degree + 1) * (g->sh_degree + 1);
+    launch_count_nonfinite(g->means, 3 * n, n_bad_dev, s);
+    launch_count_nonfinite(g->log_scales, 3 * n, n_bad_dev, s);
+    launch_count_nonfinite(g->quats, 4 * n, n_bad_dev, s);
+    launch_count_nonfinite(g->opacity_logits, n, n_bad_dev, s);
+    launch_count_nonfinite(g->sh, k3 * n, n_bad_dev, s);
+    return hip_status(ctx);
+}
+
 int ags_pose_step(ags_ctx* ctx, const ags_adam* hp, ags_camera* cams, int32_t n_views,
                   const float* pose_grad, float* pose_m, float* pose_v, int32_t* step,
                   int32_t advance_step, void* stream) {

@@ -21,7 +21,7 @@ namespace ags {
 // conic, level), are staged in LDS (one thread per pair); each pair marks its first slot
 // and a prefix maximum over the slots gives every slot its pair.  A slot whose tile the
 // alpha >= alpha_min ellipse does not reach (tile_reached) gets the key n_tiles, which the
-// tile sort moves behind every list.  Balanced however unequal the footprints are, and the
+// tile sort's first pass drops.  Balanced however unequal the footprints are, and the
 // writes are coalesced.
 constexpr int kEmitThreads = 256;
 
@@ -132,11 +132,11 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
 __global__ void ranges_kernel(const uint32_t* keys, const uint32_t* counters, long long n_max,
                               uint32_t n_tiles, uint32_t* ranges) {
     long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = counters[CNT_KEFF];
+    long long n = counters[CNT_LIVE];
     if (n > n_max) n = n_max;
     if (k >= n) return;
     uint32_t t = keys[k];
-    if (t >= n_tiles) return;  // intersections the ellipse test dropped sort last
+    if (t >= n_tiles) return;
     if (k == 0 || keys[k - 1] != t) ranges[2 * (long long)t] = (uint32_t)k;
     if (k == n - 1 || keys[k + 1] != t) ranges[2 * (long long)t + 1] = (uint32_t)(k + 1);
 }
@@ -194,8 +194,10 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};
     uint32_t* tv[2] = {a.tile_vals[first], a.tile_vals[1 - first]};
+    //    (its first pass drops the intersections the ellipse test rejected, key n_tiles)
+    const long long n_tiles_all = a.vt.tile_base[a.vt.n_views];
     int rt = launch_radix_sort(tk, tv, a.capacity, a.counters + CNT_KEFF, a.tile_bits, a.tile_grid, a.sort_tmp,
-                               s);
+                               s, nullptr, nullptr, a.counters + CNT_LIVE, (uint32_t)n_tiles_all);
     // 6. per-tile ranges
     const long long n_tiles = a.vt.tile_base[a.vt.n_views];
     launch_fill_u32(a.ranges, 0u, 2 * n_tiles, s);

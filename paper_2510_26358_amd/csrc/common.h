@@ -36,7 +36,7 @@ struct Settings {
 };
 
 // Counters at the head of the saved buffer.
-enum { CNT_K = 0, CNT_V = 1, CNT_OVERFLOW = 2, CNT_KEFF = 3 };
+enum { CNT_K = 0, CNT_V = 1, CNT_OVERFLOW = 2, CNT_KEFF = 3, CNT_LIVE = 4 };
 
 __device__ __forceinline__ int view_of_pair(const ViewTable& vt, long long q) {
     int b = 0;
@@ -416,10 +416,11 @@ long long sort_hist_entries(int grid);
 long long sort_rowtot_entries();
 // keys/vals: [0] = input, [1] = other buffer; returns index of the buffer holding the
 // result (0 or 1).  With gather_out, the last pass also writes gather_out[i] =
-// gather_src[sorted value i].
+// gather_src[sorted value i].  With n_live, the first pass drops the items whose key is
+// drop_key, writes how many are kept to *n_live, and the later passes sort only those.
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
                       int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src = nullptr,
-                      uint32_t* gather_out = nullptr);
+                      uint32_t* gather_out = nullptr, uint32_t* n_live = nullptr, uint32_t drop_key = 0u);
 
 struct BinArgs {
     ViewTable vt;
@@ -610,6 +611,7 @@ struct AdamArgs {
     const int32_t* step;
 };
 void launch_adam(const AdamArgs& a, hipStream_t s);
+void launch_count_nonfinite(const float* x, long long n, int32_t* bad, hipStream_t s);
 void launch_pose_step(ags_camera* cams, int n_views, const float* g, float* m, float* v,
                       int32_t* step, int advance, float lr, float b1, float b2, float eps,
                       hipStream_t s);

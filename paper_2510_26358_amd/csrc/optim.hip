@@ -33,6 +33,19 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
     }
 }
 
+// Counts the non-finite values (NaN, +-inf) of n floats into *bad: one atomic per wave.
+__global__ __launch_bounds__(256) void count_nonfinite_kernel(const float* x, long long n, int32_t* bad) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool nf = i < n && !isfinite(x[i]);
+    const unsigned long long m = __ballot(nf);
+    if (m != 0ull && __lane_id() == (int)(__ffsll((long long)m) - 1)) atomicAdd(bad, (int32_t)__popcll(m));
+}
+
+void launch_count_nonfinite(const float* x, long long n, int32_t* bad, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, bad);
+}
+
 void launch_adam(const AdamArgs& a, hipStream_t s) {
     if (a.n <= 0) return;
     long long total = (long long)a.n * (11 + 3 * a.sh_k);

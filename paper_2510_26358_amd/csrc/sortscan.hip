@@ -357,7 +357,7 @@ __device__ __forceinline__ uint32_t sort_block_scan(uint32_t v, uint32_t* wtot, 
 
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
     const uint32_t* keys, long long n_max, const uint32_t* n_dev, int shift, int dbits, uint32_t* hist,
-    int grid) {
+    int grid, bool drop, uint32_t drop_key) {
     __shared__ uint32_t h[256];
     const long long n = live_count(n_max, n_dev);
     long long start, end;
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
         }
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool act = base + k * kSortThreads + threadIdx.x < end;
+            const bool act = base + k * kSortThreads + threadIdx.x < end && !(drop && kv[k] == drop_key);
             const uint32_t dig = (kv[k] >> shift) & mask;
             const unsigned long long m = match_digit(dig, dbits, __ballot(act));
             if (act && lanes_below(m) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
@@ -411,7 +411,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_rowscan_kernel(uint32_t* h
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
     long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
-    const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out) {
+    const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out, bool drop,
+    uint32_t drop_key, uint32_t* n_live) {
     __shared__ uint32_t run[256];                             // global cursor per digit
     __shared__ uint32_t cnt[kSortItems][kSortWaves][256];     // counts, then rank bases
     __shared__ uint32_t tstart[256];                          // digit start inside the tile
@@ -426,11 +427,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         uint32_t total;
         const uint32_t base = sort_block_scan(rowtot[t], wtot, total);
         run[t] = base + hist[(long long)t * grid + blockIdx.x];
+        if (drop && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
     }
     const uint32_t mask = (1u << dbits) - 1u;
     for (long long base = start; base < end; base += kSortTile) {
         const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
         uint32_t kv[kSortItems], vv[kSortItems], dig[kSortItems], below[kSortItems];
+        bool on[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const int l = k * kSortThreads + t;
@@ -444,11 +447,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool act = k * kSortThreads + t < nt;
+            on[k] = k * kSortThreads + t < nt && !(drop && kv[k] == drop_key);
             dig[k] = (kv[k] >> shift) & mask;
-            const unsigned long long m = match_digit(dig[k], dbits, __ballot(act));
+            const unsigned long long m = match_digit(dig[k], dbits, __ballot(on[k]));
             below[k] = lanes_below(m);
-            if (act && below[k] == 0) cnt[k][w][dig[k]] = (uint32_t)__popcll(m);
+            if (on[k] && below[k] == 0) cnt[k][w][dig[k]] = (uint32_t)__popcll(m);
         }
         __syncthreads();
         // thread t = digit: rank bases in (sub-tile, wave) order, then the digit starts
@@ -461,14 +464,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
                 cnt[k][x][t] = r;
                 r += c;
             }
-        uint32_t total;
+        uint32_t total;  // items of the tile taking part (all, or those not dropped)
         const uint32_t ds = sort_block_scan(r, wtot, total);
         tstart[t] = ds;
         ttot[t] = r;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            if (k * kSortThreads + t < nt) {
+            if (on[k]) {
                 const uint32_t pos = tstart[dig[k]] + cnt[k][w][dig[k]] + below[k];
                 skey[pos] = kv[k];
                 sval[pos] = vv[k];
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const int p = k * kSortThreads + t;
-            if (p < nt) {
+            if (p < (int)total) {
                 const uint32_t key = skey[p];
                 const uint32_t d = (key >> shift) & mask;
                 const uint32_t dst = run[d] + (uint32_t)p - tstart[d];
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
                       int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src,
-                      uint32_t* gather_out) {
+                      uint32_t* gather_out, uint32_t* n_live, uint32_t drop_key) {
     const int passes = sort_passes(bits);
     if (passes == 0) return 0;
     const int dbits = (bits + passes - 1) / passes;
@@ -503,12 +506,16 @@ int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, con
     for (int p = 0; p < passes; ++p) {
         const int shift = p * dbits;
         const int db = (shift + dbits > bits) ? bits - shift : dbits;
-        hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], n_max, n_dev,
-                           shift, db, tmp.hist, grid);
+        const bool drop = n_live && p == 0;
+        // after a dropping first pass the later ones sort only the items kept
+        const uint32_t* nd = (n_live && p > 0) ? n_live : n_dev;
+        hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], n_max, nd,
+                           shift, db, tmp.hist, grid, drop, drop_key);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3(256), dim3(kSortThreads), 0, s, tmp.hist, tmp.rowtot, grid);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
-                           keys[1 - cur], vals[1 - cur], n_max, n_dev, shift, db, tmp.hist, tmp.rowtot, grid,
-                           p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr);
+                           keys[1 - cur], vals[1 - cur], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
+                           p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr, drop,
+                           drop_key, n_live);
         cur = 1 - cur;
     }
     return cur;

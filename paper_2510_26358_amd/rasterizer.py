@@ -229,6 +229,10 @@ class Buffers:
         """(K, V, overflow, K kept) -- synchronises."""
         return self.view(self.sizes.off_counters, 4, torch.int32).cpu().numpy().astype(np.int64)
 
+    def n_listed(self) -> int:
+        """Intersections in the per-tile lists (candidates the ellipse test keeps) -- synchronises."""
+        return int(self.view(self.sizes.off_counters, 5, torch.int32)[4].item())
+
 
 class Rasterizer:
     """A library context plus settings.  One instance per stream at a time."""
@@ -317,6 +321,13 @@ class Rasterizer:
                                      C.byref(lc) if lc is not None else None, C.byref(gr),
                                      _ptr(loss_out), _ptr(buf.bwd_ws), buf.sizes.bwd_ws_bytes, _stream())
         L.check(rc, "ags_render_bwd", self.ctx)
+
+    def check_finite(self, params: SplatParams) -> int:
+        """Number of non-finite parameter values (debug aid; synchronises)."""
+        bad = torch.zeros(1, dtype=torch.int32, device=self.device)
+        g = params.c()
+        L.check(self.lib.ags_check_finite(self.ctx, C.byref(g), _ptr(bad), _stream()), "ags_check_finite", self.ctx)
+        return int(bad.item())
 
     def lifecycle_workspace(self, n: int) -> int:
         nbytes = C.c_size_t()

@@ -42,10 +42,12 @@ def saved_arrays(buf, views: ViewSpec):
     last = buf.view(s.off_last, views.n_pixels, torch.int32).cpu().numpy()
     recs = buf.view(s.off_records, s.n_pairs * 12, torch.float32).view(-1, 12).cpu().numpy()
     cnt = buf.view(s.off_pair_count, s.n_pairs, torch.int32).cpu().numpy()
-    pairs = buf.view(s.off_tile_pairs, int(keff), torch.int32).cpu().numpy().astype(np.int64)
+    n_list = buf.n_listed()
+    pairs = buf.view(s.off_tile_pairs, n_list, torch.int32).cpu().numpy().astype(np.int64)
     ranges = buf.view(s.off_ranges, 2 * s.n_tiles, torch.int32).view(-1, 2).cpu().numpy().astype(np.int64)
-    keys = buf.fwd_ws[s.off_tile_keys:s.off_tile_keys + 4 * int(keff)].view(torch.int32).cpu().numpy()
-    return {"K": int(k), "V": int(v), "overflow": int(over), "K_kept": int(keff), "t_final": t_final,
+    keys = buf.fwd_ws[s.off_tile_keys:s.off_tile_keys + 4 * n_list].view(torch.int32).cpu().numpy()
+    return {"K": int(k), "V": int(v), "overflow": int(over), "K_kept": int(keff), "n_listed": n_list,
+            "t_final": t_final,
             "last": last, "records": recs, "pair_count": cnt, "tile_pairs": pairs, "ranges": ranges,
             "tile_keys": keys.astype(np.int64) & 0xFFFFFFFF}
 

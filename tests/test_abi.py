@@ -102,3 +102,24 @@ def test_null_context_is_rejected_without_touching_a_device(lib):
     from paper_2510_26358_amd import _lib as L
     assert lib.ags_render_fwd(None, None, None, None, 0, None, None, None, 0, None) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_profile_enable(None, 1) == L.AGS_ERR_INVALID_ARG
+
+
+def test_lifecycle_and_map_host_calls(lib):
+    """Host-only parts of the lifecycle and voxel-map entry points: workspace sizing, the
+    map's defaults, and refusals that need no device."""
+    from paper_2510_26358_amd import _lib as L
+    nb = C.c_size_t()
+    assert lib.ags_lifecycle_workspace(1000, C.byref(nb)) == 0 and nb.value >= 2 * 4 * 1000
+    assert lib.ags_lifecycle_workspace(-1, C.byref(nb)) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_lifecycle_step(None, None, None, None, None, None, None, None, None, None, None, None, None,
+                                  None, 0, None) == L.AGS_ERR_INVALID_ARG
+    cfg = L.MapConfig()
+    assert lib.ags_map_config_default(C.byref(cfg)) == 0
+    assert abs(cfg.voxel - 0.05) < 1e-7 and list(cfg.prime) == [73856093, 19349663, 83492791]
+    assert cfg.tau == 1 << 20 and cfg.max_points == 1 << 20 and cfg.sh_degree == 3
+    h = C.c_void_p()
+    assert lib.ags_map_create(None, C.byref(cfg), C.byref(h)) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_map_insert(None, None, None, 0, 0, None, None, None, None, None, None, None, None, None, None,
+                              None, None) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_map_sync(None) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_map_destroy(None) == L.AGS_ERR_INVALID_ARG
