@@ -378,7 +378,8 @@ int ags_map_destroy(ags_map* map);
  * thread then writes the offloaded rows into the host store while the caller goes on, and
  * the next call on the map waits for it first (so do ags_map_sync, ags_map_read_store and
  * ags_map_destroy).  INVALID_ARG for bad
- * pointers or sizes, CAPACITY when n_ids + n_points > max_ids (nothing changed). */
+ * pointers or sizes, CAPACITY when n_ids + n_points > max_ids (nothing changed); after
+ * AGS_ERR_HIP the map's state is undefined (destroy it). */
 int ags_map_insert(ags_map* map, const float* points, const float* colors, int64_t n_points, int32_t frame,
                    const ags_gaussians* in, const ags_gaussians* in_m, const ags_gaussians* in_v,
                    const int32_t* in_ids, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,

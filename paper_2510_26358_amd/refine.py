@@ -9,16 +9,20 @@ step is captured once and replayed.  The step counter lives in device memory.
 
 The intersection count is data dependent: the capacity is fixed when capturing (with
 headroom), and `check_capacity()` (one host read) reports an overflow so the caller can
-re-capture with a larger capacity.
+re-capture with a larger capacity.  `save` / `load` checkpoint the loop's whole state
+(parameters, Adam moments, poses, pose optimiser state, step counter) as an .npz file.
 """
 from __future__ import annotations
 
 import ctypes as C
 
+import numpy as np
 import torch
 
 from . import _lib as L
 from .rasterizer import LossTargets, Rasterizer, SplatParams, ViewSpec
+
+FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 DEFAULT_LR = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity": 5e-2, "sh0": 2.5e-3,
               "shrest": 1.25e-4, "pose": 1e-3}
@@ -82,6 +86,39 @@ class Refiner:
     def replay(self, n: int = 1):
         for _ in range(n):
             self.graph.replay()
+
+    # ---------------------------------------------------------------- checkpoint / resume
+    def state(self) -> dict:
+        """Everything the loop carries between steps, as host numpy arrays: the parameters,
+        both Adam moments, the camera array (poses), the pose optimiser state and the step."""
+        torch.cuda.synchronize()
+        out = {"sh_degree": np.int64(self.p.sh_degree), "cams": self.cams.cpu().numpy(),
+               "pose_m": self.pose_m.cpu().numpy(), "pose_v": self.pose_v.cpu().numpy(),
+               "step": self.step_no.cpu().numpy()}
+        for tag, sp in (("p", self.p), ("m", self.m), ("v", self.v)):
+            for name, t in zip(FIELDS, sp.tensors()):
+                out[f"{tag}_{name}"] = t.cpu().numpy()
+        return out
+
+    def save(self, path: str):
+        """Checkpoint to an .npz file (plain arrays, no pickled objects)."""
+        np.savez(path, **self.state())
+
+    def load(self, path: str):
+        """Resume from a checkpoint written by `save` for the same Gaussian count and views:
+        values are copied into the existing buffers, so a captured graph stays valid."""
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["sh_degree"]) != self.p.sh_degree or z["p_means"].shape != tuple(self.p.means.shape) \
+                    or z["cams"].shape != tuple(self.cams.shape):
+                raise ValueError(f"{path}: checkpoint shape does not match this refiner")
+            for tag, sp in (("p", self.p), ("m", self.m), ("v", self.v)):
+                for name, t in zip(FIELDS, sp.tensors()):
+                    t.copy_(torch.from_numpy(z[f"{tag}_{name}"]))
+            self.cams.copy_(torch.from_numpy(z["cams"]))
+            self.pose_m.copy_(torch.from_numpy(z["pose_m"]))
+            self.pose_v.copy_(torch.from_numpy(z["pose_v"]))
+            self.step_no.copy_(torch.from_numpy(z["step"]))
+        torch.cuda.synchronize()
 
     def check_capacity(self) -> bool:
         """True when the last forward fitted its intersection capacity (synchronises)."""

@@ -124,3 +124,32 @@ def test_refinement_pose_gradient_matches_fp64_finite_differences_every_10_steps
         if it < 20:
             ref.replay()
     assert ref.check_capacity()
+
+
+def test_checkpoint_resume_continues_the_loop(ras, tmp_path):
+    """Three steps, save, three more; a fresh loop loaded from the checkpoint and run for
+    three steps lands on the same state (float atomics leave last-bit differences in the
+    gradients, so parameters agree to rounding, the step counter exactly)."""
+    sc = random_scene(402, n=2000, sh_degree=2, n_views=2, width=80, height=60, f=70.0)
+    a = _refiner(ras, sc)
+    for _ in range(3):
+        a.step()
+    path = str(tmp_path / "ckpt.npz")
+    a.save(path)
+    for _ in range(3):
+        a.step()
+    b = _refiner(ras, sc, capacity=a.buf.capacity)
+    b.load(path)
+    for _ in range(3):
+        b.step()
+    sa, sb = a.state(), b.state()
+    assert int(sa["step"][0]) == int(sb["step"][0]) == 7
+    for k in sa:
+        if k in ("step", "sh_degree"):
+            continue
+        assert np.allclose(sa[k], sb[k], rtol=1e-4, atol=1e-6), k
+    # a checkpoint of another shape is refused
+    other = random_scene(403, n=100, sh_degree=2, n_views=2, width=80, height=60, f=70.0)
+    c = _refiner(ras, other)
+    with pytest.raises(ValueError):
+        c.load(path)
