@@ -376,8 +376,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
         for (int k = 0; k < kSortItems; ++k) {
             const bool act = base + k * kSortThreads + threadIdx.x < end && !(drop && kv[k] == drop_key);
             const uint32_t dig = (kv[k] >> shift) & mask;
-            const unsigned long long m = match_digit(dig, dbits, __ballot(act));
-            if (act && lanes_below(m) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
+            if (act) atomicAdd(&h[dig], 1u);  // LDS atomics (cheaper here than aggregating by ballots)
         }
     }
     __syncthreads();
