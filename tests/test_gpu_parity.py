@@ -209,3 +209,47 @@ def test_check_finite_counts_non_finite_parameters(ras):
     q.sh[0, 2, 11] = float("-inf")
     q.opacity_logits[p.n - 1] = float("nan")
     assert ras.check_finite(q) == 4
+
+
+def _many_view_scene(seed, n_views, n=300):
+    """The largest view count the ABI accepts, with ragged image sizes and per-view Gaussian
+    ranges (some views see every Gaussian, others a slice), each camera slightly rotated
+    and shifted; random targets and a few LiDAR pixels per view."""
+    import math
+    from tests.oracle_helpers import camera
+    sc = random_scene(seed, n=n, sh_degree=2, n_views=1, width=24, height=16, f=22.0)
+    rng = np.random.default_rng(seed + 1)
+    cams, gts, lidar = [], [], []
+    for b in range(n_views):
+        ay, ax = rng.uniform(-0.15, 0.15), rng.uniform(-0.1, 0.1)
+        Ry = np.array([[math.cos(ay), 0, math.sin(ay)], [0, 1, 0], [-math.sin(ay), 0, math.cos(ay)]])
+        Rx = np.array([[1, 0, 0], [0, math.cos(ax), -math.sin(ax)], [0, math.sin(ax), math.cos(ax)]])
+        w, h = 16 + 8 * (b % 3), 12 + 4 * (b % 2)
+        c = camera(R=Rx @ Ry, t=rng.uniform(-0.2, 0.2, 3), f=18.0 + b % 4, width=w, height=h)
+        if b % 4 == 3:
+            c.g_begin, c.g_end = n // 4, 3 * n // 4
+        else:
+            c.g_begin, c.g_end = 0, n
+        cams.append(c)
+        gts.append(rng.uniform(0, 1, (3, h, w)))
+        m = 6
+        pix = np.sort(rng.choice(w * h, m, replace=False)).astype(np.int32)
+        lidar.append({"pix": pix, "depth": rng.uniform(2.5, 3.5, m), "sigma": rng.uniform(0.5, 1.0, m)})
+    sc.cameras, sc.gt_rgb, sc.lidar = cams, gts, lidar
+    return sc
+
+
+def test_loss_and_gradients_at_the_maximum_view_count(ras):
+    from paper_2510_26358_amd._lib import AGS_MAX_VIEWS
+    sc = _many_view_scene(211, AGS_MAX_VIEWS)
+    g = run_loss_backward(sc, ras, w_l1=0.7, lam=0.5)
+    ref = loss_and_grads(sc, RenderSettings(), w_l1=0.7, lam=0.5)
+    print("views", len(sc.cameras), "loss", g["loss"], ref["loss"], "excluded", ref["amb_gauss"].sum())
+    assert abs(g["loss"] - ref["loss"]) <= 1e-5 * max(1, abs(ref["loss"]))
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ok, msg = grad_close(g["grads"][name], ref["grads"][name], ref["amb_gauss"])
+        print(name, msg)
+        assert ok, (name, msg)
+    ok, msg = grad_close(g["pose"], ref["pose"])
+    print("pose", msg)
+    assert ok, msg
