@@ -219,7 +219,10 @@ void ags_ctx_destroy(ags_ctx* ctx);
 int ags_ctx_set_config(ags_ctx* ctx, const ags_config* cfg);
 
 /* Host-only arithmetic: sizes of the buffers fwd/bwd need for this shape and capacity
- * (maximum number of (tile, Gaussian) intersections).  No device access. */
+ * (maximum number of (tile, Gaussian) intersections).  No device access.  The `saved` and
+ * `ws` buffers passed to ags_render_fwd / ags_render_bwd / ags_bin_records (and the records
+ * of ags_bin_records) must start on a 16-byte boundary, as hipMalloc'd and torch-allocated
+ * memory does; otherwise those calls return AGS_ERR_INVALID_ARG. */
 int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_gaussians,
                      int32_t sh_degree, int64_t isect_capacity, ags_sizes* out);
 

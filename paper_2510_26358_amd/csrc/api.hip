@@ -36,6 +36,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+// the kernels read records and sorted keys as 16-byte vectors at offsets that are multiples
+// of kAlign from the buffer's start
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
 
 struct Layout {
     ViewTable vt;
@@ -370,6 +373,7 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* out,
                    void* saved, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || !out || !saved || !ws || !cams) return AGS_ERR_INVALID_ARG;
+    if (misaligned(saved) || misaligned(ws)) return AGS_ERR_INVALID_ARG;
     int rc = check_gaussians(g);
     if (rc) return rc;
     Layout L;
@@ -427,6 +431,7 @@ int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, c
                     size_t ws_bytes, void* stream) {
     if (!ctx || !saved || !ws || (!records && n_gaussians > 0) || (!valid && n_gaussians > 0))
         return AGS_ERR_INVALID_ARG;
+    if (misaligned(saved) || misaligned(ws) || misaligned(records)) return AGS_ERR_INVALID_ARG;
     Layout L;
     int rc = build_layout(&ctx->cfg, views, n_gaussians, isect_capacity, L);
     if (rc) return rc;
@@ -448,6 +453,7 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const void* saved, const ags_upstream* up, const ags_loss* loss,
                    ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || !saved || !ws || !cams || !grads) return AGS_ERR_INVALID_ARG;
+    if (misaligned(saved) || misaligned(ws)) return AGS_ERR_INVALID_ARG;
     if ((up == nullptr) == (loss == nullptr)) return AGS_ERR_INVALID_ARG;
     int rc = check_gaussians(g);
     if (rc) return rc;

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
                                                             const uint32_t* depth_vals, const uint32_t* emit_off,
                                                             const uint32_t* block_first, const uint32_t* counters,
                                                             long long capacity, uint32_t* tile_keys,
-                                                            uint32_t* tile_vals) {
+                                                            uint32_t* tile_vals, uint32_t* ranges) {
     constexpr int S = kEmitSlots, PT = S / kEmitThreads;
     __shared__ uint32_t s_off[S];
     __shared__ uint32_t s_own[S];                     // slot -> local pair index
@@ -39,13 +39,17 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
     __shared__ float2 s_ell2[S];                      // c, level
     __shared__ uint32_t s_wmax[kEmitThreads / 64];
     const long long k0 = (long long)blockIdx.x * S;
+    const uint32_t n_tiles = (uint32_t)vt.tile_base[vt.n_views];
+    // every tile's range starts empty; ranges_kernel later sets the non-empty ones
+    for (long long e = (long long)blockIdx.x * kEmitThreads + threadIdx.x; e < 2LL * n_tiles;
+         e += (long long)gridDim.x * kEmitThreads)
+        ranges[e] = 0u;
     long long keff = counters[CNT_KEFF];
     if (keff > capacity) keff = capacity;
     const long long nv = counters[CNT_V];
     if (k0 >= keff || nv == 0) return;  // uniform per workgroup
     const long long j0 = block_first[blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t n_tiles = (uint32_t)vt.tile_base[vt.n_views];
     // the workgroup's pairs: from the owner of its first slot to the owner of the next
     // workgroup's first slot (or the last pair); pairs starting at or beyond the workgroup's
     // last slot are not needed
@@ -129,16 +133,33 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
     }
 }
 
-__global__ void ranges_kernel(const uint32_t* keys, const uint32_t* counters, long long n_max,
-                              uint32_t n_tiles, uint32_t* ranges) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Tile ranges of the sorted list: four consecutive entries per thread, each compared with
+// its neighbours; only entries that open or close a tile's run write.
+constexpr int kRangeItems = 4;
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* keys, const uint32_t* counters,
+                                                     long long n_max, uint32_t n_tiles, uint32_t* ranges) {
     long long n = counters[CNT_LIVE];
     if (n > n_max) n = n_max;
-    if (k >= n) return;
-    uint32_t t = keys[k];
-    if (t >= n_tiles) return;
-    if (k == 0 || keys[k - 1] != t) ranges[2 * (long long)t] = (uint32_t)k;
-    if (k == n - 1 || keys[k + 1] != t) ranges[2 * (long long)t + 1] = (uint32_t)(k + 1);
+    const long long k0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+    if (k0 >= n) return;
+    uint32_t v[kRangeItems + 2];
+    v[0] = k0 > 0 ? keys[k0 - 1] : 0xFFFFFFFFu;
+    if (k0 + kRangeItems <= n) {
+        const uint4 x = *reinterpret_cast<const uint4*>(keys + k0);  // k0 is a multiple of 4
+        v[1] = x.x; v[2] = x.y; v[3] = x.z; v[4] = x.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) v[1 + j] = k0 + j < n ? keys[k0 + j] : 0xFFFFFFFFu;
+    }
+    v[kRangeItems + 1] = k0 + kRangeItems < n ? keys[k0 + kRangeItems] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < kRangeItems; ++j) {
+        const long long k = k0 + j;
+        const uint32_t t = v[1 + j];
+        if (k >= n || t >= n_tiles) continue;
+        if (v[j] != t) ranges[2 * (long long)t] = (uint32_t)k;
+        if (v[2 + j] != t) ranges[2 * (long long)t + 1] = (uint32_t)(k + 1);
+    }
 }
 
 // Stage entry from externally supplied records: counts and depth bits per pair.
@@ -185,12 +206,11 @@ int launch_binning(BinArgs& a, hipStream_t s) {
     //    number of tile-sort passes ends in final_vals
     const int tp = sort_passes(a.tile_bits);
     const int first = (a.final_vals == a.tile_vals[0]) ? (tp % 2) : 1 - (tp % 2);
-    const unsigned kgrid = (unsigned)((a.capacity + 255) / 256 > 0 ? (a.capacity + 255) / 256 : 1);
     const unsigned egrid = (unsigned)((a.capacity + kEmitSlots - 1) / kEmitSlots > 0
                                           ? (a.capacity + kEmitSlots - 1) / kEmitSlots
                                           : 1);
     hipLaunchKernelGGL(emit_kernel, dim3(egrid), dim3(kEmitThreads), 0, s, a.vt, a.records, dvals, a.emit_off,
-                       a.block_first, a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first]);
+                       a.block_first, a.counters, a.capacity, a.tile_keys[first], a.tile_vals[first], a.ranges);
     // 5. stable sort by tile id
     uint32_t* tk[2] = {a.tile_keys[first], a.tile_keys[1 - first]};
     uint32_t* tv[2] = {a.tile_vals[first], a.tile_vals[1 - first]};
@@ -200,8 +220,10 @@ int launch_binning(BinArgs& a, hipStream_t s) {
                                s, nullptr, nullptr, a.counters + CNT_LIVE, (uint32_t)n_tiles_all);
     // 6. per-tile ranges
     const long long n_tiles = a.vt.tile_base[a.vt.n_views];
-    launch_fill_u32(a.ranges, 0u, 2 * n_tiles, s);
-    hipLaunchKernelGGL(ranges_kernel, dim3(kgrid), dim3(256), 0, s, tk[rt], a.counters, a.capacity,
+    const unsigned rgrid = (unsigned)((a.capacity + 256 * kRangeItems - 1) / (256 * kRangeItems) > 0
+                                          ? (a.capacity + 256 * kRangeItems - 1) / (256 * kRangeItems)
+                                          : 1);
+    hipLaunchKernelGGL(ranges_kernel, dim3(rgrid), dim3(256), 0, s, tk[rt], a.counters, a.capacity,
                        (uint32_t)n_tiles, a.ranges);
     (void)tv;
     return (int)hipGetLastError();

@@ -389,7 +389,7 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
                  hipStream_t s);
 
 // Output slots per emission workgroup.
-constexpr int kEmitSlots = 1024;
+constexpr int kEmitSlots = 512;
 
 // Exclusive scan of counts[order[i]] (counts[i] when order is null; out may then be
 // counts itself) over i < *n_dev into out, for the intersection

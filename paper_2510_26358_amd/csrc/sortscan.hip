@@ -292,9 +292,11 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
 //  2. row scan: one workgroup per digit turns its row into exclusive offsets and stores
 //     the row total.
 //  3. scatter: a workgroup starts digit d at (sum of the row totals below d) + its row
-//     offset, then per tile ranks the items by digit in LDS (stable: ballots inside a
-//     wave, per-(sub-tile, wave) counts across waves), regroups the tile by digit in LDS
-//     and writes each digit's run to consecutive addresses.
+//     offset, then per tile ranks the items by digit in LDS and regroups the tile by digit
+//     there before writing each digit's run to consecutive addresses.  Each wave ranks a
+//     contiguous 512-item slice of the tile, 64 items at a time, against running per-wave
+//     digit counts (ballots inside the 64; 4 KB of counts, so six workgroups fit a CU);
+//     a scan across waves and digits then places the slices.
 // Item order inside a digit is preserved, so the passes compose into a stable sort.
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
@@ -412,8 +414,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
     const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out, bool drop,
     uint32_t drop_key, uint32_t* n_live) {
+    constexpr int WS = kSortTile / kSortWaves;                // items per wave slice (512)
     __shared__ uint32_t run[256];                             // global cursor per digit
-    __shared__ uint32_t cnt[kSortItems][kSortWaves][256];     // counts, then rank bases
+    __shared__ uint32_t wcnt[kSortWaves][256];                // slice counts, then slice bases
     __shared__ uint32_t tstart[256];                          // digit start inside the tile
     __shared__ uint32_t ttot[256];                            // digit count of the tile
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const long long n = live_count(n_max, n_dev);
     long long start, end;
     chunk_of_block(n, grid, start, end);
-    const int t = threadIdx.x, w = t >> 6;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     {
         uint32_t total;
         const uint32_t base = sort_block_scan(rowtot[t], wtot, total);
@@ -429,40 +432,44 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         if (drop && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
     }
     const uint32_t mask = (1u << dbits) - 1u;
+    uint32_t* const cw = wcnt[w];
     for (long long base = start; base < end; base += kSortTile) {
         const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
-        uint32_t kv[kSortItems], vv[kSortItems], dig[kSortItems], below[kSortItems];
+        uint32_t kv[kSortItems], vv[kSortItems], dig[kSortItems], rank[kSortItems];
         bool on[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const int l = k * kSortThreads + t;
+            const int l = w * WS + k * 64 + lane;
             kv[k] = l < nt ? keys_in[base + l] : 0u;
             vv[k] = l < nt ? vals_in[base + l] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k)
-#pragma unroll
-            for (int x = 0; x < kSortWaves; ++x) cnt[k][x][t] = 0;
+        for (int x = 0; x < kSortWaves; ++x) wcnt[x][t] = 0;
         __syncthreads();
+        // item order inside the slice is (k, lane); the wave's running count of a digit is
+        // read by every lane holding it, then advanced by the lowest such lane (LDS
+        // operations of one wave complete in issue order)
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            on[k] = k * kSortThreads + t < nt && !(drop && kv[k] == drop_key);
+            on[k] = w * WS + k * 64 + lane < nt && !(drop && kv[k] == drop_key);
             dig[k] = (kv[k] >> shift) & mask;
             const unsigned long long m = match_digit(dig[k], dbits, __ballot(on[k]));
-            below[k] = lanes_below(m);
-            if (on[k] && below[k] == 0) cnt[k][w][dig[k]] = (uint32_t)__popcll(m);
+            const uint32_t below = lanes_below(m);
+            const uint32_t prev = on[k] ? cw[dig[k]] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (on[k] && below == 0) cw[dig[k]] = prev + (uint32_t)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            rank[k] = prev + below;
         }
         __syncthreads();
-        // thread t = digit: rank bases in (sub-tile, wave) order, then the digit starts
+        // thread t = digit: slice bases in wave order, then the digit starts
         uint32_t r = 0;
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k)
-#pragma unroll
-            for (int x = 0; x < kSortWaves; ++x) {
-                const uint32_t c = cnt[k][x][t];
-                cnt[k][x][t] = r;
-                r += c;
-            }
+        for (int x = 0; x < kSortWaves; ++x) {
+            const uint32_t c = wcnt[x][t];
+            wcnt[x][t] = r;
+            r += c;
+        }
         uint32_t total;  // items of the tile taking part (all, or those not dropped)
         const uint32_t ds = sort_block_scan(r, wtot, total);
         tstart[t] = ds;
@@ -471,7 +478,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             if (on[k]) {
-                const uint32_t pos = tstart[dig[k]] + cnt[k][w][dig[k]] + below[k];
+                const uint32_t pos = tstart[dig[k]] + cw[dig[k]] + rank[k];
                 skey[pos] = kv[k];
                 sval[pos] = vv[k];
             }

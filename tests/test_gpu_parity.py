@@ -151,6 +151,34 @@ def test_binning_bit_exact_on_seeded_records(tile, sizes):
     assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
 
 
+def test_misaligned_buffers_are_rejected_before_any_launch():
+    """The kernels read records and sorted keys as 16-byte vectors: buffers that do not start
+    on a 16-byte boundary are refused on the host, and an aligned call still works."""
+    import ctypes as C
+    from paper_2510_26358_amd import _lib as L
+    from paper_2510_26358_amd.rasterizer import Rasterizer, ViewSpec, _stream
+    r = Rasterizer(0, tile=16, batch=256, px_per_thread=1)
+    rng = np.random.default_rng(77)
+    recs, valid, _ = _synthetic_records(rng, 1, 64, [(64, 48)], 16)
+    views = ViewSpec([64], [48], [0], [64])
+    buf = r.buffers(views, 64, 0, 4096)
+    rec_t = torch.from_numpy(recs).cuda()
+    val_t = torch.from_numpy(valid.astype(np.uint8)).cuda()
+    raw = torch.zeros(recs.size + 4, dtype=torch.float32, device="cuda")
+    shifted = raw[1:1 + recs.size]            # 4 bytes past an aligned start
+    shifted.copy_(rec_t.reshape(-1))
+
+    def call(records, saved, ws):
+        return r.lib.ags_bin_records(r.ctx, C.byref(views.c), 64, records, val_t.data_ptr(), buf.capacity,
+                                     saved, ws, buf.sizes.fwd_ws_bytes, _stream())
+    saved, ws = buf.saved.data_ptr(), buf.fwd_ws.data_ptr()
+    assert call(shifted.data_ptr(), saved, ws) == L.AGS_ERR_INVALID_ARG
+    assert call(rec_t.data_ptr(), saved + 8, ws) == L.AGS_ERR_INVALID_ARG
+    assert call(rec_t.data_ptr(), saved, ws + 4) == L.AGS_ERR_INVALID_ARG
+    assert call(rec_t.data_ptr(), saved, ws) == L.AGS_OK
+    torch.cuda.synchronize()
+
+
 def test_overflow_is_flagged_and_recovered(ras):
     sc = scenes.tiny_scene()
     from paper_2510_26358_amd.rasterizer import SplatParams, ViewSpec, cameras_tensor
