@@ -64,8 +64,16 @@ void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s) {
 // Deterministic sum of the per-block loss partials (fixed order, one workgroup).
 __global__ __launch_bounds__(1024) void sum_partials_kernel(const float* p, long long n, float* out) {
     __shared__ float sred[16];
-    float s = 0.f;
-    for (long long i = threadIdx.x; i < n; i += 1024) s += p[i];
+    // eight independent sums per thread, so eight loads are in flight at a time (fixed order)
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    long long i = threadIdx.x;
+    for (; i + 7 * 1024 < n; i += 8 * 1024)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += p[i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (i + u * 1024 < n) acc[u] += p[i + u * 1024];
+    float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
     __syncthreads();
