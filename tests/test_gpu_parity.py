@@ -227,6 +227,44 @@ def test_loss_and_gradients_sh3_lidar(ras, seed, n_views):
     assert ok, msg
 
 
+# Every (tile, LDS batch, pixels per thread) launch shape the library accepts, each used for
+# both passes, and two forward/backward pairs of different shapes on one tile size: the
+# benchmark's autotuner may pick any of them.  Two 70x45 views (ragged tiles for 8, 16 and 32),
+# up to ~90 contributors per pixel, so the 64- and 128-record batches loop.
+_SHAPES = [(8, 64, 1), (8, 128, 1), (16, 128, 1), (16, 256, 1), (16, 128, 2), (16, 256, 2), (16, 64, 4),
+           (32, 256, 4), (32, 512, 2)]
+_SHAPE_CASES = [(s, s[1:]) for s in _SHAPES] + [((16, 256, 1), (128, 2)), ((16, 64, 4), (256, 1))]
+_shape_ref = {}
+
+
+def _shape_reference():
+    if not _shape_ref:
+        sc = random_scene(233, n=900, sh_degree=3, n_views=2, width=70, height=45, f=55.0)
+        _shape_ref.update(scene=sc, fwd=render(sc, RenderSettings()),
+                          loss=loss_and_grads(sc, RenderSettings(), w_l1=0.8, lam=0.5))
+    return _shape_ref
+
+
+@pytest.mark.parametrize("fwd,bwd", _SHAPE_CASES, ids=[f"fwd{f}-bwd{b}" for f, b in _SHAPE_CASES])
+def test_every_launch_shape_matches_the_oracle(fwd, bwd):
+    from paper_2510_26358_amd.rasterizer import Rasterizer
+    ref = _shape_reference()
+    sc, lr = ref["scene"], ref["loss"]
+    r = Rasterizer(0, tile=fwd[0], batch=fwd[1], px_per_thread=fwd[2], batch_bwd=bwd[0], px_per_thread_bwd=bwd[1])
+    print("forward", fwd, "backward", bwd, flush=True)
+    g = run_loss_backward(sc, r, w_l1=0.8, lam=0.5)
+    _compare_forward(g["fwd"], ref["fwd"], sc)
+    print("loss", g["loss"], lr["loss"], "excluded", lr["amb_gauss"].sum())
+    assert abs(g["loss"] - lr["loss"]) <= 1e-5 * max(1, abs(lr["loss"]))
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ok, msg = grad_close(g["grads"][name], lr["grads"][name], lr["amb_gauss"])
+        print(name, msg)
+        assert ok, (name, msg)
+    ok, msg = grad_close(g["pose"], lr["pose"])
+    print("pose", msg)
+    assert ok, msg
+
+
 def test_check_finite_counts_non_finite_parameters(ras):
     from paper_2510_26358_amd.rasterizer import SplatParams
     p = SplatParams.from_scene(scenes.tiny_scene())
