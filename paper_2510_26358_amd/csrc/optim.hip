@@ -7,29 +7,54 @@
 
 namespace ags {
 
+// One Adam update of parameter value j of a group (torch.optim.Adam without weight decay).
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
+                                         float bc1, float bc2, float eps) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
+// Grid row y = parameter group (means, log-scales, quaternions, logits, SH degree 0, SH
+// degree >= 1), each a contiguous run of the SoA buffers; a thread updates four consecutive
+// values per step with 16-byte accesses when the group's four buffers allow them.
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+    const int grp = blockIdx.y;
     const long long n = a.n;
-    const long long sizes[5] = {3 * n, 3 * n, 4 * n, n, (long long)a.sh_k * 3 * n};
-    const long long total = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4];
+    const int seg = grp < 5 ? grp : 4;  // both SH groups live in the SH buffers
+    const long long off = grp == 5 ? 3 * n : 0;
+    const long long len = grp == 0 ? 3 * n : grp == 1 ? 3 * n : grp == 2 ? 4 * n : grp == 3 ? n
+                        : grp == 4 ? (a.sh_k > 0 ? 3 * n : 0) : (long long)(a.sh_k - 1) * 3 * n;
+    if (len <= 0) return;
+    float* p = a.p[seg] + off;
+    const float* g = a.g[seg] + off;
+    float* m = a.m[seg] + off;
+    float* v = a.v[seg] + off;
+    const float lr = a.lr[grp];
+    const float b1 = a.beta1, b2 = a.beta2, eps = a.eps;
     const float t = (float)(*a.step);
-    const float bc1 = 1.f - powf(a.beta1, t);
-    const float bc2 = 1.f - powf(a.beta2, t);
-    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (; e < total; e += stride) {
-        long long j = e;
-        int seg = 0;
-        while (seg < 4 && j >= sizes[seg]) {
-            j -= sizes[seg];
-            ++seg;
+    const float bc1 = 1.f - powf(b1, t);
+    const float bc2 = 1.f - powf(b2, t);
+    const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) |
+                       reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15u) == 0;
+    const long long stride = 4LL * gridDim.x * blockDim.x;
+    for (long long e = 4LL * ((long long)blockIdx.x * blockDim.x + threadIdx.x); e < len; e += stride) {
+        if (vec && e + 4 <= len) {
+            float4 pp = *reinterpret_cast<float4*>(p + e);
+            const float4 gg = *reinterpret_cast<const float4*>(g + e);
+            float4 mm = *reinterpret_cast<float4*>(m + e);
+            float4 vv = *reinterpret_cast<float4*>(v + e);
+            adam_one(pp.x, gg.x, mm.x, vv.x, lr, b1, b2, bc1, bc2, eps);
+            adam_one(pp.y, gg.y, mm.y, vv.y, lr, b1, b2, bc1, bc2, eps);
+            adam_one(pp.z, gg.z, mm.z, vv.z, lr, b1, b2, bc1, bc2, eps);
+            adam_one(pp.w, gg.w, mm.w, vv.w, lr, b1, b2, bc1, bc2, eps);
+            *reinterpret_cast<float4*>(p + e) = pp;
+            *reinterpret_cast<float4*>(m + e) = mm;
+            *reinterpret_cast<float4*>(v + e) = vv;
+        } else {
+            const long long e1 = e + 4 < len ? e + 4 : len;
+            for (long long j = e; j < e1; ++j) adam_one(p[j], g[j], m[j], v[j], lr, b1, b2, bc1, bc2, eps);
         }
-        const float lr = seg < 4 ? a.lr[seg] : (j < 3 * n ? a.lr[4] : a.lr[5]);
-        const float g = a.g[seg][j];
-        const float m = a.beta1 * a.m[seg][j] + (1.f - a.beta1) * g;
-        const float v = a.beta2 * a.v[seg][j] + (1.f - a.beta2) * g * g;
-        a.m[seg][j] = m;
-        a.v[seg][j] = v;
-        a.p[seg][j] -= lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
     }
 }
 
@@ -48,10 +73,12 @@ void launch_count_nonfinite(const float* x, long long n, int32_t* bad, hipStream
 
 void launch_adam(const AdamArgs& a, hipStream_t s) {
     if (a.n <= 0) return;
-    long long total = (long long)a.n * (11 + 3 * a.sh_k);
-    long long g = (total + 255) / 256;
-    if (g > 16384) g = 16384;
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)g), dim3(256), 0, s, a);
+    // sized for the largest group (SH degree >= 1 at degree 3: 45 n values), 4 values a thread
+    const long long big = (long long)a.n * (a.sh_k > 1 ? 3 * (a.sh_k - 1) : 4);
+    long long g = (big + 1023) / 1024;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)g, 6), dim3(256), 0, s, a);
 }
 
 // One thread per view (<= AGS_MAX_VIEWS); the exponential map is evaluated in double.
