@@ -320,10 +320,12 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
     return rf, info
 
 
-def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms):
+def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fused_adam=False):
     """Every stage against its bound from the per-stage HIP-event times: algorithmic bytes
     (HBM-bound stages) or FLOP (raster) per launch, as listed in the design doc; plus the whole
-    step's algorithmic bytes over its time (the HBM fraction of the step)."""
+    step's algorithmic bytes over its time (the HBM fraction of the step).  With the fused
+    backward + Adam the projection backward also carries Adam's bytes, less the SH gradient's
+    write and re-read and the second read of the SH coefficients."""
     F = 11 + 3 * sh_k
     byts = {
         "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V,
@@ -334,6 +336,10 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms):
         "raster_fwd": 28 * P,
         "raster_bwd": 44 * P,
     }
+    if "adam" in stage_ms:
+        byts["adam"] = 7 * 4 * F * N
+    elif fused_adam:
+        byts["project_bwd"] += 7 * 4 * F * N - 3 * 4 * 3 * sh_k * N
     out = {}
     for name, ms in stage_ms.items():
         if ms <= 0:
@@ -497,7 +503,8 @@ def main():
         info["stage_ms"] = stage_ms
         info["stages"] = stage_rooflines(stage_ms, info["pairs_evaluated"], P, p.n, (p.sh_degree + 1) ** 2,
                                          over_buf.sizes.n_pairs, info["V"], info["K"],
-                                         int(tg.depth_pix.numel()), t_b * 1e3)
+                                         int(tg.depth_pix.numel()), t_b * 1e3,
+                                         fused_adam=refiner is not None and refiner.fused_adam)
 
     # the same step with the D-SSIM part of the photometric loss switched on
     with_ssim = None

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define AGS_ABI_VERSION 2
+#define AGS_ABI_VERSION 3
 #define AGS_MAX_VIEWS 32
 
 enum {
@@ -261,6 +261,22 @@ typedef struct ags_adam {
 int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* params,
                   const ags_grads* grads, ags_gaussians* m, ags_gaussians* v,
                   const int32_t* step, void* stream);
+
+/* The backward of ags_render_bwd followed by ags_adam_step on `params`, in one pass over
+ * the Gaussians: the kernel that completes each Gaussian's gradient (the colour adjoint
+ * through the SH evaluation, Sec. III-C, joined with the geometry part) applies Adam to all of
+ * its parameters in place, so the SH gradient, 48 of a degree-3 Gaussian's 59 values, is
+ * never written to or re-read from memory.  Arguments as for ags_render_bwd and
+ * ags_adam_step; `grads` still receives the pose gradient, the densification statistic if
+ * requested and the geometry gradients (means without the SH direction term, log_scales,
+ * quats, opacity_logits), while grads->sh is not written and may be NULL; grads->accumulate
+ * must be 0.  The result equals the two calls in sequence. */
+int ags_render_bwd_adam(ags_ctx* ctx, const ags_views* views, ags_gaussians* params,
+                        const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
+                        const void* saved, const ags_upstream* up, const ags_loss* loss,
+                        ags_grads* grads, float* loss_out, const ags_adam* hp, ags_gaussians* m,
+                        ags_gaussians* v, const int32_t* step, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Adam on each view's se(3) increment (pose_m, pose_v: device float[n_views][6]), then
  * the left retraction W_b <- Exp(delta_b) W_b written into cams; if advance_step != 0 the

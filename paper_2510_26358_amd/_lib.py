@@ -22,7 +22,7 @@ AGS_MAX_VIEWS = 32
 EXPORTED = [
     "ags_version", "ags_error_string", "ags_last_hip_error", "ags_config_default",
     "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
-    "ags_render_fwd", "ags_render_bwd", "ags_bin_records", "ags_adam_step", "ags_pose_step",
+    "ags_render_fwd", "ags_render_bwd", "ags_render_bwd_adam", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
     "ags_lifecycle_step", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
     "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
@@ -107,7 +107,7 @@ class Adam(C.Structure):
                 ("eps", C.c_float)]
 
 
-ABI_VERSION = 2  # include/agsplat.h AGS_ABI_VERSION
+ABI_VERSION = 3  # include/agsplat.h AGS_ABI_VERSION
 
 _lib = None
 
@@ -141,6 +141,9 @@ def load(path: str = LIB_PATH):
                                    C.c_size_t, vp]
     lib.ags_render_bwd.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp,
                                    P(Upstream), P(Loss), P(Grads), vp, vp, C.c_size_t, vp]
+    lib.ags_render_bwd_adam.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp,
+                                        P(Upstream), P(Loss), P(Grads), vp, P(Adam), P(Gaussians), P(Gaussians),
+                                        vp, vp, C.c_size_t, vp]
     lib.ags_bin_records.argtypes = [vp, P(Views), C.c_int32, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
     lib.ags_adam_step.argtypes = [vp, P(Adam), P(Gaussians), P(Grads), P(Gaussians), P(Gaussians), vp, vp]
     lib.ags_pose_step.argtypes = [vp, P(Adam), vp, C.c_int32, vp, vp, vp, vp, C.c_int32, vp]

@@ -448,10 +448,14 @@ int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, c
     return hip_status(ctx);
 }
 
-int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
-                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
-                   const void* saved, const ags_upstream* up, const ags_loss* loss,
-                   ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+// The backward; with `fused` non-null the colour kernel also applies Adam to every
+// Gaussian parameter (grads->sh is then not written and may be null).
+int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const ags_camera* cams,
+               int64_t isect_capacity, const ags_fwd_out* fwd, const void* saved, const ags_upstream* up,
+               const ags_loss* loss, ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream,
+               const AdamArgs* fused) {
     if (!ctx || !saved || !ws || !cams || !grads) return AGS_ERR_INVALID_ARG;
     if (misaligned(saved) || misaligned(ws)) return AGS_ERR_INVALID_ARG;
     if ((up == nullptr) == (loss == nullptr)) return AGS_ERR_INVALID_ARG;
@@ -462,8 +466,9 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     if (rc) return rc;
     if (ws_bytes < L.b_total) return AGS_ERR_WORKSPACE;
     if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
-                     !grads->sh))
+                     (!grads->sh && !fused)))
         return AGS_ERR_INVALID_ARG;
+    if (fused && grads->accumulate) return AGS_ERR_INVALID_ARG;
     if (!grads->pose) return AGS_ERR_INVALID_ARG;
     if ((grads->stat_grad == nullptr) != (grads->stat_count == nullptr)) return AGS_ERR_INVALID_ARG;
     long long n_targets = 0;
@@ -600,23 +605,20 @@ int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.vis_mask = at<uint32_t>(ws, L.b_vis);
         pa.stat_grad = grads->stat_grad;
         pa.stat_count = grads->stat_count;
+        pa.fused_adam = fused != nullptr;
+        if (fused) pa.adam = *fused;
+        else memset(&pa.adam, 0, sizeof(pa.adam));
         launch_project_bwd(pa, s);
     }
     if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);
     return hip_status(ctx);
 }
 
-int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* p, const ags_grads* gr,
-                  ags_gaussians* m, ags_gaussians* v, const int32_t* step, void* stream) {
-    if (!ctx || !hp || !p || !gr || !m || !v || !step) return AGS_ERR_INVALID_ARG;
-    if (check_gaussians(p) || check_gaussians(m) || check_gaussians(v)) return AGS_ERR_INVALID_ARG;
-    if (m->n != p->n || v->n != p->n || m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
-        return AGS_ERR_INVALID_ARG;
-    if (p->n > 0 && (!gr->means || !gr->log_scales || !gr->quats || !gr->opacity_logits || !gr->sh))
-        return AGS_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+// Adam arguments from the public structs (validated by the caller).
+AdamArgs adam_args(const ags_adam* hp, ags_gaussians* p, const ags_grads* gr, ags_gaussians* m, ags_gaussians* v,
+                   const int32_t* step) {
     AdamArgs a;
+    memset(&a, 0, sizeof(a));
     a.n = p->n;
     a.sh_k = (p->sh_degree + 1) * (p->sh_degree + 1);
     float* pp[5] = {p->means, p->log_scales, p->quats, p->opacity_logits, p->sh};
@@ -639,6 +641,45 @@ int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* p, const ags_
     a.beta2 = hp->beta2;
     a.eps = hp->eps;
     a.step = step;
+    return a;
+}
+
+bool adam_shapes_ok(const ags_gaussians* p, const ags_gaussians* m, const ags_gaussians* v) {
+    if (check_gaussians(p) || check_gaussians(m) || check_gaussians(v)) return false;
+    return m->n == p->n && v->n == p->n && m->sh_degree == p->sh_degree && v->sh_degree == p->sh_degree;
+}
+
+}  // namespace
+
+int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
+                   const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
+                   const void* saved, const ags_upstream* up, const ags_loss* loss,
+                   ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+    return render_bwd(ctx, views, g, cams, isect_capacity, fwd, saved, up, loss, grads, loss_out, ws, ws_bytes,
+                      stream, nullptr);
+}
+
+int ags_render_bwd_adam(ags_ctx* ctx, const ags_views* views, ags_gaussians* params, const ags_camera* cams,
+                        int64_t isect_capacity, const ags_fwd_out* fwd, const void* saved,
+                        const ags_upstream* up, const ags_loss* loss, ags_grads* grads, float* loss_out,
+                        const ags_adam* hp, ags_gaussians* m, ags_gaussians* v, const int32_t* step, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!ctx || !params || !grads || !hp || !m || !v || !step) return AGS_ERR_INVALID_ARG;
+    if (!adam_shapes_ok(params, m, v)) return AGS_ERR_INVALID_ARG;
+    const AdamArgs a = adam_args(hp, params, grads, m, v, step);
+    return render_bwd(ctx, views, params, cams, isect_capacity, fwd, saved, up, loss, grads, loss_out, ws, ws_bytes,
+                      stream, &a);
+}
+
+int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* p, const ags_grads* gr,
+                  ags_gaussians* m, ags_gaussians* v, const int32_t* step, void* stream) {
+    if (!ctx || !hp || !p || !gr || !m || !v || !step) return AGS_ERR_INVALID_ARG;
+    if (!adam_shapes_ok(p, m, v)) return AGS_ERR_INVALID_ARG;
+    if (p->n > 0 && (!gr->means || !gr->log_scales || !gr->quats || !gr->opacity_logits || !gr->sh))
+        return AGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    const AdamArgs a = adam_args(hp, p, gr, m, v, step);
     Scope sc(ctx, ST_ADAM, s);
     launch_adam(a, s);
     return hip_status(ctx);

@@ -525,6 +525,29 @@ int lidar_blocks(long long n_targets);
 void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s);
 void launch_sum_partials(const float* partials, long long n, float* out, hipStream_t s);
 
+// Adam on the Gaussian parameters: groups means, log-scales, quaternions, logits, SH
+// degree 0, SH degree >= 1 (lr[0..5]); the SH buffer holds both SH groups.
+struct AdamArgs {
+    int n, sh_k;
+    float* p[5];
+    const float* g[5];
+    float* m[5];
+    float* v[5];
+    float lr[6];
+    float beta1, beta2, eps;
+    const int32_t* step;
+};
+
+// One Adam update of one value (torch.optim.Adam without weight decay); bc1, bc2 are the
+// bias corrections 1 - beta^t.  The moment updates are written as explicit fused
+// multiply-adds so every kernel that inlines this rounds them the same way.
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
+                                         float bc1, float bc2, float eps) {
+    m = fmaf(b1, m, (1.f - b1) * g);
+    v = fmaf(b2, v, ((1.f - b2) * g) * g);
+    p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
 struct ProjectBwdArgs {
     ViewTable vt;
     Settings st;
@@ -540,6 +563,10 @@ struct ProjectBwdArgs {
     float* stat_grad;      // [n] or null: += |dL/d(u, v)| per view seeing the Gaussian
     float* stat_count;     // [n] or null: += number of those views
     int accumulate;
+    // fused optimiser step: the colour kernel, which finishes each Gaussian's gradient, applies
+    // Adam to all its parameters instead of writing the SH gradient (g_sh unused)
+    int fused_adam;
+    AdamArgs adam;
 };
 int project_bwd_blocks(int n);
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
@@ -600,16 +627,6 @@ struct StageTimer {
 int ctx_device(const ags_ctx* ctx);
 int ctx_record_hip(ags_ctx* ctx, hipError_t e);
 
-struct AdamArgs {
-    int n, sh_k;
-    float* p[5];
-    const float* g[5];
-    float* m[5];
-    float* v[5];
-    float lr[6];
-    float beta1, beta2, eps;
-    const int32_t* step;
-};
 void launch_adam(const AdamArgs& a, hipStream_t s);
 void launch_count_nonfinite(const float* x, long long n, int32_t* bad, hipStream_t s);
 void launch_pose_step(ags_camera* cams, int n_views, const float* g, float* m, float* v,

@@ -7,14 +7,6 @@
 
 namespace ags {
 
-// One Adam update of parameter value j of a group (torch.optim.Adam without weight decay).
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
-                                         float bc1, float bc2, float eps) {
-    m = b1 * m + (1.f - b1) * g;
-    v = b2 * v + (1.f - b2) * g * g;
-    p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
-}
-
 // Grid row y = parameter group (means, log-scales, quaternions, logits, SH degree 0, SH
 // degree >= 1), each a contiguous run of the SoA buffers; a thread updates four consecutive
 // values per step with 16-byte accesses when the group's four buffers allow them.

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
 // tangent plane of the unit sphere), added to dL/dmu and, as R_b g_dir, to the view's
 // dL/drho.  One thread per Gaussian; its K x 3 coefficients are read once, the K x 3 sums
 // stay in registers and are written once.
-template <int DEG>
+template <int DEG, bool FUSED>
 __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,6 +354,76 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
             (DEG > 0 && k < 3) ? spose[b][k][0] + spose[b][k][1] + spose[b][k][2] + spose[b][k][3] : 0.f;
     }
     if (!active) return;
+    if (FUSED) {
+        // the Gaussian's gradient is complete here: update all its parameters in place, in
+        // batches whose loads are all issued before any of the batch's stores
+        const AdamArgs& ad = a.adam;
+        const float t = (float)(*ad.step);
+        const float b1 = ad.beta1, b2 = ad.beta2, eps = ad.eps;
+        const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+        constexpr int R = 3 * K, CH = 8;  // SH rows (coefficient k, channel c) = 3 k + c
+#pragma unroll
+        for (int r0 = 0; r0 < R; r0 += CH) {
+            float pp[CH], mm[CH], vv[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (r0 + j < R) {
+                    const long long e = (long long)(r0 + j) * n + i;
+                    pp[j] = ad.p[4][e];
+                    mm[j] = ad.m[4][e];
+                    vv[j] = ad.v[4][e];
+                }
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (r0 + j < R)
+                    adam_one(pp[j], acc[(r0 + j) / 3][(r0 + j) % 3], mm[j], vv[j], r0 + j < 3 ? ad.lr[4] : ad.lr[5], b1,
+                             b2, bc1, bc2, eps);
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (r0 + j < R) {
+                    const long long e = (long long)(r0 + j) * n + i;
+                    ad.p[4][e] = pp[j];
+                    ad.m[4][e] = mm[j];
+                    ad.v[4][e] = vv[j];
+                }
+        }
+        // means (with the direction term), log-scales, quaternion, logit: 11 rows
+        float* const P[11] = {ad.p[0], ad.p[0] + n, ad.p[0] + 2 * (long long)n, ad.p[1], ad.p[1] + n,
+                              ad.p[1] + 2 * (long long)n, ad.p[2], ad.p[2] + n, ad.p[2] + 2 * (long long)n,
+                              ad.p[2] + 3 * (long long)n, ad.p[3]};
+        float* const Mo[11] = {ad.m[0], ad.m[0] + n, ad.m[0] + 2 * (long long)n, ad.m[1], ad.m[1] + n,
+                               ad.m[1] + 2 * (long long)n, ad.m[2], ad.m[2] + n, ad.m[2] + 2 * (long long)n,
+                               ad.m[2] + 3 * (long long)n, ad.m[3]};
+        float* const Vo[11] = {ad.v[0], ad.v[0] + n, ad.v[0] + 2 * (long long)n, ad.v[1], ad.v[1] + n,
+                               ad.v[1] + 2 * (long long)n, ad.v[2], ad.v[2] + n, ad.v[2] + 2 * (long long)n,
+                               ad.v[2] + 3 * (long long)n, ad.v[3]};
+        const float* const G[11] = {a.g_means, a.g_means + n, a.g_means + 2 * (long long)n, a.g_log_scales,
+                                    a.g_log_scales + n, a.g_log_scales + 2 * (long long)n, a.g_quats,
+                                    a.g_quats + n, a.g_quats + 2 * (long long)n, a.g_quats + 3 * (long long)n,
+                                    a.g_logits};
+        float pp[11], mm[11], vv[11], gg[11];
+#pragma unroll
+        for (int j = 0; j < 11; ++j) {
+            pp[j] = P[j][i];
+            mm[j] = Mo[j][i];
+            vv[j] = Vo[j][i];
+            gg[j] = G[j][i];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gg[j] = gg[j] + gm[j];
+#pragma unroll
+        for (int j = 0; j < 11; ++j) {
+            const float lr = j < 3 ? ad.lr[0] : j < 6 ? ad.lr[1] : j < 10 ? ad.lr[2] : ad.lr[3];
+            adam_one(pp[j], gg[j], mm[j], vv[j], lr, b1, b2, bc1, bc2, eps);
+        }
+#pragma unroll
+        for (int j = 0; j < 11; ++j) {
+            P[j][i] = pp[j];
+            Mo[j][i] = mm[j];
+            Vo[j][i] = vv[j];
+        }
+        return;
+    }
     if (a.accumulate) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -406,12 +476,20 @@ void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
     const int nb = project_bwd_blocks(a.n);
     if (nb > 0) launch_project_bwd_main(a, s);
     if (nb > 0) {
+#define SHB(d_)                                                                        \
+    do {                                                                               \
+        if (a.fused_adam)                                                              \
+            hipLaunchKernelGGL((sh_bwd_kernel<d_, true>), dim3(nb), dim3(256), 0, s, a);  \
+        else                                                                           \
+            hipLaunchKernelGGL((sh_bwd_kernel<d_, false>), dim3(nb), dim3(256), 0, s, a); \
+    } while (0)
         switch (a.sh_degree) {
-            case 0: hipLaunchKernelGGL(sh_bwd_kernel<0>, dim3(nb), dim3(256), 0, s, a); break;
-            case 1: hipLaunchKernelGGL(sh_bwd_kernel<1>, dim3(nb), dim3(256), 0, s, a); break;
-            case 2: hipLaunchKernelGGL(sh_bwd_kernel<2>, dim3(nb), dim3(256), 0, s, a); break;
-            default: hipLaunchKernelGGL(sh_bwd_kernel<3>, dim3(nb), dim3(256), 0, s, a); break;
+            case 0: SHB(0); break;
+            case 1: SHB(1); break;
+            case 2: SHB(2); break;
+            default: SHB(3); break;
         }
+#undef SHB
     }
     if (nb > 0)
         hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, 2 * nb,

@@ -300,9 +300,12 @@ class Rasterizer:
 
     def backward_into(self, params: SplatParams, cams, views: ViewSpec, buf: Buffers, out, grads,
                       pose_grad, upstream=None, loss: LossTargets | None = None, loss_out=None,
-                      accumulate=False, stats=None):
+                      accumulate=False, stats=None, adam=None):
         """stats: optional (grad, count) float tensors [N] accumulating the densification
-        statistic (|dL/d(u, v)| and the number of views seeing each Gaussian)."""
+        statistic (|dL/d(u, v)| and the number of views seeing each Gaussian).
+        adam: optional (hp: _lib.Adam, m: SplatParams, v: SplatParams, step: int32 tensor [1]):
+        apply Adam to `params` in the same pass (ags_render_bwd_adam; grads.sh is then left
+        unwritten)."""
         fo = _fwd_out(out)
         g = params.c()
         st = (None, None) if stats is None else (stats[0].data_ptr(), stats[1].data_ptr())
@@ -316,6 +319,16 @@ class Rasterizer:
                             d_alpha.data_ptr() if d_alpha is not None else None)
         if loss is not None:
             lc = loss.c()
+        if adam is not None:
+            hp, m, v, step = adam
+            mc, vc = m.c(), v.c()
+            rc = self.lib.ags_render_bwd_adam(self.ctx, C.byref(views.c), C.byref(g), _ptr(cams), buf.capacity,
+                                              C.byref(fo), _ptr(buf.saved), C.byref(up) if up is not None else None,
+                                              C.byref(lc) if lc is not None else None, C.byref(gr),
+                                              _ptr(loss_out), C.byref(hp), C.byref(mc), C.byref(vc), _ptr(step),
+                                              _ptr(buf.bwd_ws), buf.sizes.bwd_ws_bytes, _stream())
+            L.check(rc, "ags_render_bwd_adam", self.ctx)
+            return
         rc = self.lib.ags_render_bwd(self.ctx, C.byref(views.c), C.byref(g), _ptr(cams), buf.capacity,
                                      C.byref(fo), _ptr(buf.saved), C.byref(up) if up is not None else None,
                                      C.byref(lc) if lc is not None else None, C.byref(gr),

@@ -31,8 +31,9 @@ DEFAULT_LR = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity": 5e-2,
 class Refiner:
     def __init__(self, ras: Rasterizer, params: SplatParams, cams: torch.Tensor, views: ViewSpec,
                  targets: LossTargets, lr: dict | None = None, capacity: int | None = None,
-                 headroom: float = 1.3, betas=(0.9, 0.999), eps=1e-15):
+                 headroom: float = 1.3, betas=(0.9, 0.999), eps=1e-15, fused_adam: bool = True):
         self.ras, self.p, self.cams, self.views, self.targets = ras, params, cams, views, targets
+        self.fused_adam = fused_adam
         lr = {**DEFAULT_LR, **(lr or {})}
         self.hp = L.Adam(lr["means"], lr["log_scales"], lr["quats"], lr["opacity"], lr["sh0"], lr["shrest"],
                          lr["pose"], betas[0], betas[1], eps)
@@ -60,13 +61,19 @@ class Refiner:
         """Enqueue one optimisation step on the current stream (no host sync)."""
         ras, lib = self.ras, self.ras.lib
         ras.forward_into(self.p, self.cams, self.views, self.buf, self.out)
-        ras.backward_into(self.p, self.cams, self.views, self.buf, self.out, self.grads, self.pose_grad,
-                          loss=self.targets, loss_out=self.loss)
-        gr = L.Grads(*[t.data_ptr() for t in self.grads.tensors()], self.pose_grad.data_ptr(), 0)
-        pc, mc, vc = self.p.c(), self.m.c(), self.v.c()
         stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-        L.check(lib.ags_adam_step(ras.ctx, C.byref(self.hp), C.byref(pc), C.byref(gr), C.byref(mc), C.byref(vc),
-                                  C.c_void_p(self.step_no.data_ptr()), stream), "ags_adam_step", ras.ctx)
+        if self.fused_adam:
+            # backward and Adam in one pass over the Gaussians (the SH gradient stays in registers)
+            ras.backward_into(self.p, self.cams, self.views, self.buf, self.out, self.grads, self.pose_grad,
+                              loss=self.targets, loss_out=self.loss, adam=(self.hp, self.m, self.v, self.step_no))
+        else:
+            ras.backward_into(self.p, self.cams, self.views, self.buf, self.out, self.grads, self.pose_grad,
+                              loss=self.targets, loss_out=self.loss)
+            gr = L.Grads(*[t.data_ptr() for t in self.grads.tensors()], self.pose_grad.data_ptr(), 0)
+            pc, mc, vc = self.p.c(), self.m.c(), self.v.c()
+            L.check(lib.ags_adam_step(ras.ctx, C.byref(self.hp), C.byref(pc), C.byref(gr), C.byref(mc),
+                                      C.byref(vc), C.c_void_p(self.step_no.data_ptr()), stream), "ags_adam_step",
+                    ras.ctx)
         L.check(lib.ags_pose_step(ras.ctx, C.byref(self.hp), C.c_void_p(self.cams.data_ptr()), self.views.n_views,
                                   C.c_void_p(self.pose_grad.data_ptr()), C.c_void_p(self.pose_m.data_ptr()),
                                   C.c_void_p(self.pose_v.data_ptr()), C.c_void_p(self.step_no.data_ptr()), 1,

@@ -23,18 +23,19 @@ def ras():
     return Rasterizer(0)
 
 
-def _refiner(ras, sc, capacity=None):
+def _refiner(ras, sc, capacity=None, fused_adam=True):
     views = ViewSpec.from_scene(sc)
     p = SplatParams.from_scene(sc)
     cams = cameras_tensor(sc.cameras)
     tg = LossTargets.from_scene(sc, views, lambda_lidar=0.5)
-    return Refiner(ras, p, cams, views, tg, capacity=capacity)
+    return Refiner(ras, p, cams, views, tg, capacity=capacity, fused_adam=fused_adam)
 
 
-def test_graph_replay_matches_eager_steps(ras):
+@pytest.mark.parametrize("fused_adam", [True, False])
+def test_graph_replay_matches_eager_steps(ras, fused_adam):
     sc = random_scene(401, n=3000, sh_degree=3, n_views=2, width=96, height=72, f=80.0)
-    a = _refiner(ras, sc)
-    b = _refiner(ras, sc, capacity=a.buf.capacity)
+    a = _refiner(ras, sc, fused_adam=fused_adam)
+    b = _refiner(ras, sc, capacity=a.buf.capacity, fused_adam=fused_adam)
     b.capture()
     losses = []
     for it in range(4):
@@ -51,6 +52,31 @@ def test_graph_replay_matches_eager_steps(ras):
         losses.append(a.loss.item())
         assert abs(a.loss.item() - b.loss.item()) <= 1e-4 * abs(a.loss.item())
     assert losses[-1] < losses[0]
+
+
+@pytest.mark.parametrize("deg", [3, 1, 0])
+def test_fused_backward_adam_equals_backward_then_adam(ras, deg):
+    """ags_render_bwd_adam against ags_render_bwd followed by ags_adam_step over four steps
+    (moments non-zero after the first, bias corrections changing): parameters, both Adam
+    moments, the pose gradient, the poses and the loss agree to the tolerance of the graph
+    replay test.  Not bit for bit: the per-pair adjoint sums of the raster backward are float
+    atomics, whose order differs from run to run, so two backward passes differ in the last
+    bits of their gradients."""
+    sc = random_scene(411 + deg, n=1500, sh_degree=deg, n_views=2, width=80, height=60, f=70.0)
+    a = _refiner(ras, sc, fused_adam=True)
+    b = _refiner(ras, sc, capacity=a.buf.capacity, fused_adam=False)
+    for it in range(4):
+        a.step()
+        b.step()
+        torch.cuda.synchronize()
+        assert a.check_capacity() and b.check_capacity()
+        for name, x, y in zip(("p", "m", "v"), (a.p, a.m, a.v), (b.p, b.m, b.v)):
+            for fx, fy in zip(x.tensors(), y.tensors()):
+                tol = 1e-6 if name == "p" else 1e-6 * max(fy.abs().max().item(), 1e-30)
+                assert torch.allclose(fx, fy, rtol=1e-5, atol=tol), (it, name, (fx - fy).abs().max().item())
+        assert torch.allclose(a.pose_grad, b.pose_grad, rtol=1e-4, atol=1e-6 * b.pose_grad.abs().max().item()), it
+        assert torch.allclose(a.cams, b.cams, rtol=1e-5, atol=1e-6), it
+        assert abs(a.loss.item() - b.loss.item()) <= 1e-5 * abs(b.loss.item()), it
 
 
 def _crop(sc, cams_np, params_aos, rng, n_keep=4096, win=128):
