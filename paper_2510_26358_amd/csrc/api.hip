@@ -450,8 +450,8 @@ int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, c
 
 namespace {
 
-// The backward; with `fused` non-null the colour kernel also applies Adam to every
-// Gaussian parameter (grads->sh is then not written and may be null).
+// The backward; with `fused` non-null the colour phase of the projection backward also
+// applies Adam to every Gaussian parameter (grads->sh is then not written and may be null).
 int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const ags_camera* cams,
                int64_t isect_capacity, const ags_fwd_out* fwd, const void* saved, const ags_upstream* up,
                const ags_loss* loss, ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream,

@@ -559,11 +559,11 @@ struct ProjectBwdArgs {
     const float* grad2d;
     float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh, *g_pose;
     float* pose_partials;  // [n_views * 6][2 project_bwd_blocks(n)]: geometry, then colour
-    uint32_t* vis_mask;    // [n]: views keeping each Gaussian (geometry kernel -> colour kernel)
+    uint32_t* vis_mask;    // [n]: views keeping each Gaussian (geometry phase -> colour phase)
     float* stat_grad;      // [n] or null: += |dL/d(u, v)| per view seeing the Gaussian
     float* stat_count;     // [n] or null: += number of those views
     int accumulate;
-    // fused optimiser step: the colour kernel, which finishes each Gaussian's gradient, applies
+    // fused optimiser step: the colour phase, which finishes each Gaussian's gradient, applies
     // Adam to all its parameters instead of writing the SH gradient (g_sh unused)
     int fused_adam;
     AdamArgs adam;

@@ -11,13 +11,14 @@
 // Pose, left perturbation W_b <- Exp(delta) W_b with delta = (rho, phi):
 //   g_rho += g_xc,  g_phi += x_c x g_xc + (N_12 - N_21, N_20 - N_02, N_01 - N_10),
 //   N = R_b G_T^T J.
-// The colour part runs in a second kernel that reads the SH coefficients once per
+// The colour part follows in the same kernel (a second phase of the thread, so the pair's
+// 2D adjoint and the Gaussian's mean are still cached) and reads the SH coefficients once per
 // Gaussian: the clamp-masked colour adjoint (the mask is the forward's stored colour > 0),
 // Y(d) for the coefficients, and grad Y projected on the sphere for the direction
 // d = (mu - C_b) / |mu - C_b|, which adds to mu and, through the camera centre moving by
 // -R_b^T rho, g_rho += R_b g_dir.
 // The per-view pose sums are reduced over the wave, then over the workgroup in LDS, into
-// one partial per workgroup and view (both kernels); a third kernel adds the partials in a
+// one partial per workgroup and view (one per phase); a second kernel adds the partials in a
 // fixed order (deterministic, and no contention on the 6 B floats).  Shared-Gaussian terms
 // (Sigma -> scale, rotation; opacity -> logit) are chained once after the view loop.
 #include "common.h"
@@ -27,7 +28,7 @@ namespace ags {
 void launch_project_bwd_main(const ProjectBwdArgs& a, hipStream_t s);
 
 template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
+__device__ __forceinline__ void geometry_bwd(const ProjectBwdArgs& a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < a.n;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
     float GSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float gmu[3] = {0.f, 0.f, 0.f};
     float go = 0.f;
-    uint32_t vmask = 0;  // views keeping this Gaussian, for the colour kernel
+    uint32_t vmask = 0;  // views keeping this Gaussian, for the colour phase
     float stat_g = 0.f, stat_c = 0.f;  // densification statistic (|dL/d(u, v)| per view)
 
     for (int b = 0; b < vt.n_views; ++b) {
@@ -259,9 +260,9 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
 // g_dir = P_d (sum_c gcol_c sum_k f_kc grad Y_k(d)) / |mu - C_b| (P_d the projection on the
 // tangent plane of the unit sphere), added to dL/dmu and, as R_b g_dir, to the view's
 // dL/drho.  One thread per Gaussian; its K x 3 coefficients are read once, the K x 3 sums
-// stay in registers and are written once.
+// stay in registers and are written once (or, with FUSED, applied by Adam at once).
 template <int DEG, bool FUSED>
-__global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
+__device__ __forceinline__ void colour_bwd(const ProjectBwdArgs& a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < a.n;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const ViewTable& vt = a.vt;
     __shared__ float spose[kMaxViews][3][4];
-    // second half of each partials row: this kernel's grid equals the geometry kernel's
+    // second half of each partials row (the geometry phase fills the first)
     float* partials = a.pose_partials + gridDim.x;
 
     float mx = 0.f, my = 0.f, mz = 0.f;
@@ -443,6 +444,14 @@ __global__ __launch_bounds__(256) void sh_bwd_kernel(ProjectBwdArgs a) {
     }
 }
 
+// Both phases for one Gaussian per thread: the geometry adjoint, then the colour adjoint
+// (with FUSED, followed by the Adam step on all of the Gaussian's parameters).
+template <int DEG, bool FUSED>
+__global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
+    geometry_bwd<DEG>(a);
+    colour_bwd<DEG, FUSED>(a);
+}
+
 // Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component),
 // whose partials form one contiguous row of n_blocks values.
 __global__ __launch_bounds__(256) void pose_reduce_kernel(const float* partials, int n_blocks, int n_views,
@@ -475,22 +484,6 @@ int project_bwd_blocks(int n) { return n > 0 ? (n + 255) / 256 : 0; }
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
     const int nb = project_bwd_blocks(a.n);
     if (nb > 0) launch_project_bwd_main(a, s);
-    if (nb > 0) {
-#define SHB(d_)                                                                        \
-    do {                                                                               \
-        if (a.fused_adam)                                                              \
-            hipLaunchKernelGGL((sh_bwd_kernel<d_, true>), dim3(nb), dim3(256), 0, s, a);  \
-        else                                                                           \
-            hipLaunchKernelGGL((sh_bwd_kernel<d_, false>), dim3(nb), dim3(256), 0, s, a); \
-    } while (0)
-        switch (a.sh_degree) {
-            case 0: SHB(0); break;
-            case 1: SHB(1); break;
-            case 2: SHB(2); break;
-            default: SHB(3); break;
-        }
-#undef SHB
-    }
     if (nb > 0)
         hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, 2 * nb,
                            a.vt.n_views, a.g_pose, a.accumulate);
@@ -500,12 +493,20 @@ void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
 
 void launch_project_bwd_main(const ProjectBwdArgs& a, hipStream_t s) {
     dim3 grid((a.n + 255) / 256), block(256);
+#define PB(d_)                                                                                 \
+    do {                                                                                       \
+        if (a.fused_adam)                                                                      \
+            hipLaunchKernelGGL((project_bwd_kernel<d_, true>), grid, block, 0, s, a);           \
+        else                                                                                   \
+            hipLaunchKernelGGL((project_bwd_kernel<d_, false>), grid, block, 0, s, a);          \
+    } while (0)
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, a); break;
+        case 0: PB(0); break;
+        case 1: PB(1); break;
+        case 2: PB(2); break;
+        default: PB(3); break;
     }
+#undef PB
 }
 
 }  // namespace ags
