@@ -79,6 +79,33 @@ def test_fused_backward_adam_equals_backward_then_adam(ras, deg):
         assert abs(a.loss.item() - b.loss.item()) <= 1e-5 * abs(b.loss.item()), it
 
 
+def test_fused_backward_adam_arguments(ras):
+    """The fused call leaves grads.sh alone (it may be NULL) and refuses accumulation; both
+    checked on the host before any launch."""
+    import ctypes as C
+    from paper_2510_26358_amd import _lib as L
+    from paper_2510_26358_amd.rasterizer import _fwd_out, _ptr, _stream
+    sc = random_scene(431, n=300, sh_degree=3, n_views=1, width=48, height=32, f=50.0)
+    r = _refiner(ras, sc)
+    ras.forward_into(r.p, r.cams, r.views, r.buf, r.out)
+    fo, g, mc, vc, lc = _fwd_out(r.out), r.p.c(), r.m.c(), r.v.c(), r.targets.c()
+
+    def call(sh_ptr, acc):
+        ptrs = [t.data_ptr() for t in r.grads.tensors()]
+        gr = L.Grads(ptrs[0], ptrs[1], ptrs[2], ptrs[3], sh_ptr, r.pose_grad.data_ptr(), acc, None, None)
+        return ras.lib.ags_render_bwd_adam(ras.ctx, C.byref(r.views.c), C.byref(g), _ptr(r.cams), r.buf.capacity,
+                                           C.byref(fo), _ptr(r.buf.saved), None, C.byref(lc), C.byref(gr),
+                                           _ptr(r.loss), C.byref(r.hp), C.byref(mc), C.byref(vc), _ptr(r.step_no),
+                                           _ptr(r.buf.bwd_ws), r.buf.sizes.bwd_ws_bytes, _stream())
+    assert call(r.grads.sh.data_ptr(), 1) == L.AGS_ERR_INVALID_ARG
+    r.grads.sh.fill_(7.0)
+    assert call(r.grads.sh.data_ptr(), 0) == L.AGS_OK
+    assert call(None, 0) == L.AGS_OK
+    torch.cuda.synchronize()
+    assert torch.equal(r.grads.sh, torch.full_like(r.grads.sh, 7.0))
+    assert torch.isfinite(r.p.sh).all() and int(r.step_no.item()) == 1
+
+
 def _crop(sc, cams_np, params_aos, rng, n_keep=4096, win=128):
     """4096 Gaussians nearest (in 3D, in front of the camera) to the ray through the centre
     of a seeded 128x128 window of view 0, seen through a window camera whose principal
