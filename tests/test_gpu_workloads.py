@@ -42,7 +42,7 @@ def _restrict_lidar(lid, pix):
     return {k: np.asarray(v)[keep] for k, v in lid.items()}
 
 
-@pytest.mark.parametrize("maker", ["single_view", "multi_view"])
+@pytest.mark.parametrize("maker", ["single_view", "multi_view", "submaps", "refine"])
 def test_full_size_forward_and_gradients_on_pixel_samples(ras, maker):
     sc = scenes.CONFIGS[maker]()
     rng = np.random.default_rng(4242)
