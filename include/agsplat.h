@@ -98,7 +98,10 @@ typedef struct ags_views {
  *   means [3][n], log_scales [3][n] (scale = exp), quats [4][n] (w, x, y, z; any norm),
  *   opacity_logits [n] (opacity = sigmoid), sh [K][3][n] (coefficient k, channel c of
  *   Gaussian i at (k * 3 + c) * n + i; real SH, l-major, m = -l..l, Condon-Shortley phase;
- *   colour = max(0, sum_k Y_k(d) sh_k + 0.5), d the unit direction camera centre -> mean). */
+ *   colour = max(0, sum_k Y_k(d) sh_k + 0.5), d the unit direction camera centre -> mean).
+ * All arithmetic is float32: keep world coordinates near the origin of the frame they are
+ * rendered in (e.g. one frame per sub-map); hundreds of metres out, float32 spacing moves
+ * projected centres by hundredths of a pixel once the camera transform cancels them. */
 typedef struct ags_gaussians {
     int32_t n;
     int32_t sh_degree;        /* 0 .. 3 */
