@@ -313,7 +313,7 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
         elif name == "adam":
             by = 7 * 4 * F * n_gauss
         else:
-            by = 4 * 4 * Q + 8 * 4 * int(v) + 2 * 16 * int(keff)
+            by = 8 * Q + 84 * int(v) + 44 * int(keff)
         achieved = by / (ms_avg * 1e-3) / 1e9
         rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -329,7 +329,7 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
     F = 11 + 3 * sh_k
     byts = {
         "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V,
-        "binning": 4 * Q + 72 * V + 44 * K,
+        "binning": 8 * Q + 84 * V + 44 * K,
         "lidar_adjoint": 16 * n_targets,
         "project_bwd": 2 * 4 * F * N + 56 * V + 24 * N,
         "clear": 40 * Q + 4 * P,

@@ -175,9 +175,9 @@ __global__ void count_from_records_kernel(ViewTable vt, const float* records, co
         int tx0, ty0, tx1, ty1;
         if (tile_rect(r0.x, r0.y, r1.w, r2.x, vt.width[b], vt.height[b], vt.tile, tx0, ty0, tx1, ty1))
             cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        pair_z[q] = __float_as_uint(r1.z);
     }
     pair_count[q] = cnt;
+    pair_z[q] = cnt ? __float_as_uint(reinterpret_cast<const float4*>(records + q * kRecFloats)[1].z) : kNoDepth;
 }
 
 void launch_count_from_records(const ViewTable& vt, const float* records, const uint8_t* valid,
@@ -190,13 +190,12 @@ void launch_count_from_records(const ViewTable& vt, const float* records, const 
 
 int launch_binning(BinArgs& a, hipStream_t s) {
     const long long Q = a.n_pairs;
-    // 1. visible pairs, compacted in pair order with their depth keys
-    launch_scan_compact(a.pair_count, a.pair_z, Q, a.counters + CNT_V, a.depth_keys[0], a.depth_vals[0],
-                        a.scan_tmp, s);
-    // 2. stable depth sort of the visible pairs
-    //    (its last pass also lays out the pairs' tile counts in depth order, in emit_off)
-    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, a.counters + CNT_V, 32, a.depth_grid, a.sort_tmp, s,
-                              a.pair_count, a.emit_off);
+    // 1-2. stable depth sort of the visible pairs: the first pass reads every pair's depth
+    //    key (pair_z; kNoDepth for a pair no view keeps) with the pair id as value, drops the
+    //    invisible ones and counts the visible ones into CNT_V; its last pass also lays out
+    //    the pairs' tile counts in depth order, in emit_off
+    int r = launch_radix_sort(a.depth_keys, a.depth_vals, Q, nullptr, 32, a.depth_grid, a.sort_tmp, s,
+                              a.pair_count, a.emit_off, a.counters + CNT_V, kNoDepth, a.pair_z);
     const uint32_t* dvals = a.depth_vals[r];
     // 3. intersection offsets in depth order (in place), total K, overflow flag, first pair
     //    of each emission workgroup

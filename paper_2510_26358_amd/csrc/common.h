@@ -388,6 +388,10 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
                  long long n_max, const uint32_t* n_dev, uint32_t* total, ScanTemp tmp,
                  hipStream_t s);
 
+// Depth key of a (view, Gaussian) pair that no tile receives: a NaN bit pattern, never the
+// bits of a depth >= z_near.
+constexpr uint32_t kNoDepth = 0xFFFFFFFFu;
+
 // Output slots per emission workgroup.
 constexpr int kEmitSlots = 512;
 
@@ -398,11 +402,6 @@ constexpr int kEmitSlots = 512;
 void launch_emit_scan(const uint32_t* counts, const uint32_t* order, uint32_t* out, long long n_max,
                       const uint32_t* n_dev, uint32_t* counters, long long capacity, uint32_t* block_first,
                       ScanTemp tmp, hipStream_t s);
-
-// Order-preserving compaction: (payload[i], i) for every i < n with src[i] != 0, count to
-// *total.
-void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
-                         uint32_t* keys, uint32_t* vals, ScanTemp tmp, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) u32 pairs on bits [0, bits), n read from n_dev,
 // with `grid` workgroups per pass (sort_grid of the static maximum, at most 256).
@@ -418,9 +417,13 @@ long long sort_rowtot_entries();
 // result (0 or 1).  With gather_out, the last pass also writes gather_out[i] =
 // gather_src[sorted value i].  With n_live, the first pass drops the items whose key is
 // drop_key, writes how many are kept to *n_live, and the later passes sort only those.
+// With first_keys, the first pass reads its keys from there and takes each item's index as
+// its value (keys[0] / vals[0] are then only written); the result is in buffer
+// (passes - 1) % 2.
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
                       int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src = nullptr,
-                      uint32_t* gather_out = nullptr, uint32_t* n_live = nullptr, uint32_t drop_key = 0u);
+                      uint32_t* gather_out = nullptr, uint32_t* n_live = nullptr, uint32_t drop_key = 0u,
+                      const uint32_t* first_keys = nullptr);
 
 struct BinArgs {
     ViewTable vt;
@@ -446,8 +449,8 @@ struct BinArgs {
 void launch_count_from_records(const ViewTable& vt, const float* records, const uint8_t* valid,
                                long long n_pairs, uint32_t* pair_count, uint32_t* pair_z,
                                hipStream_t s);
-// Runs visibility scan + compaction, depth sort, tile-count scan, emission, tile sort and
-// ranges.  Returns 0 or a HIP error.
+// Runs the depth sort (its first pass drops the pairs no tile receives), tile-count scan,
+// emission, tile sort and ranges.  Returns 0 or a HIP error.
 int launch_binning(BinArgs& a, hipStream_t s);
 
 struct RasterArgs {

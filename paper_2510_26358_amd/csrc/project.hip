@@ -101,6 +101,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
             }
         }
         a.pair_count[q] = cnt;
+        if (!cnt) a.pair_z[q] = kNoDepth;  // dropped by the depth sort's first pass
     }
     if (vis == 0u) return;
 

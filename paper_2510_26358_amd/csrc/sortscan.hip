@@ -146,47 +146,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(
     }
 }
 
-// Apply phase that compacts instead of writing prefixes: element i with src[i] != 0 goes to
-// position prefix(i) of (keys, vals) as (payload[i], i).  Order-preserving.
-__global__ __launch_bounds__(kScanThreads) void scan_compact_kernel(
-    const uint32_t* src, const uint32_t* payload, long long n, const uint32_t* block_sums, uint32_t* keys,
-    uint32_t* vals) {
-    __shared__ uint32_t wave_tot[kScanThreads / 64];
-    const long long base = (long long)blockIdx.x * kScanTile;
-    if (base >= n) return;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        long long i = base + (long long)threadIdx.x * kScanItems + k;
-        v[k] = (i < n && src[i] != 0u) ? 1u : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
-    uint32_t run = block_sums[blockIdx.x] + incl - s;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        long long i = base + (long long)threadIdx.x * kScanItems + k;
-        if (v[k]) {
-            keys[run] = payload[i];
-            vals[run] = (uint32_t)i;
-        }
-        run += v[k];
-    }
-}
-
-void launch_scan_compact(const uint32_t* src, const uint32_t* payload, long long n, uint32_t* total,
-                         uint32_t* keys, uint32_t* vals, ScanTemp tmp, hipStream_t s) {
-    long long nb = scan_blocks(n);
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, nullptr, true, n,
-                       nullptr, tmp.block_sums);
-    hipLaunchKernelGGL(scan_blocksums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp.block_sums, nb, total);
-    hipLaunchKernelGGL(scan_compact_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, payload, n,
-                       tmp.block_sums, keys, vals);
-}
-
 // Scan of the tile counts in depth order (value i = counts[order[i]], i < *n_dev) that also
 // publishes the intersection total: counters[CNT_K] = K, counters[CNT_OVERFLOW] = K >
 // capacity, counters[CNT_KEFF] = min(K, capacity).
@@ -441,7 +400,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         for (int k = 0; k < kSortItems; ++k) {
             const int l = w * WS + k * 64 + lane;
             kv[k] = l < nt ? keys_in[base + l] : 0u;
-            vv[k] = l < nt ? vals_in[base + l] : 0u;
+            vv[k] = l < nt ? (vals_in ? vals_in[base + l] : (uint32_t)(base + l)) : 0u;  // index if no values
         }
 #pragma unroll
         for (int x = 0; x < kSortWaves; ++x) wcnt[x][t] = 0;
@@ -504,27 +463,33 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
                       int bits, int grid, SortTemp tmp, hipStream_t s, const uint32_t* gather_src,
-                      uint32_t* gather_out, uint32_t* n_live, uint32_t drop_key) {
+                      uint32_t* gather_out, uint32_t* n_live, uint32_t drop_key, const uint32_t* first_keys) {
     const int passes = sort_passes(bits);
     if (passes == 0) return 0;
     const int dbits = (bits + passes - 1) / passes;
-    int cur = 0;
+    // pass p reads buffer `in` and writes buffer `out`; with first_keys the first pass reads
+    // the external keys (values = indices) and writes buffer 0
+    int in = 0;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * dbits;
         const int db = (shift + dbits > bits) ? bits - shift : dbits;
         const bool drop = n_live && p == 0;
         // after a dropping first pass the later ones sort only the items kept
         const uint32_t* nd = (n_live && p > 0) ? n_live : n_dev;
-        hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], n_max, nd,
-                           shift, db, tmp.hist, grid, drop, drop_key);
+        const bool ext = first_keys && p == 0;
+        const uint32_t* kin = ext ? first_keys : keys[in];
+        const uint32_t* vin = ext ? nullptr : vals[in];
+        const int out = ext ? 0 : 1 - in;
+        hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, n_max, nd, shift, db,
+                           tmp.hist, grid, drop, drop_key);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3(256), dim3(kSortThreads), 0, s, tmp.hist, tmp.rowtot, grid);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
-                           keys[1 - cur], vals[1 - cur], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, vin, keys[out],
+                           vals[out], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
                            p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr, drop,
                            drop_key, n_live);
-        cur = 1 - cur;
+        in = out;
     }
-    return cur;
+    return in;
 }
 
 long long sort_hist_entries(int grid) { return 256LL * grid; }
