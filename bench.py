@@ -178,9 +178,10 @@ def measure_voxel_map(ras, args, n_points=1 << 20, tau=1 << 20, warm_calls=8, ti
     1.5 m per call, so about a quarter of the voxels are new; the resident set is bounded by
     2^20 splats (SH degree 3).  The first calls fill the resident set; the timed ones run in
     the steady state (new splats in, as many least recently used out to the host store).
-    Reported: wall time per call (host-synchronous: includes the reload / offload copies over
-    PCIe; the offloaded rows' copy into the host store runs on a host thread after the call
-    returns and is timed apart, by waiting for it before the next call), per-stage GPU times
+    Reported: wall time per call (host-synchronous: includes the reload copy over PCIe; the
+    offloaded rows leave on the map's copy stream and reach the host store on a host thread
+    after the call returns, which is timed apart by waiting for it before the next call),
+    per-stage GPU times
     (HIP events), and the roofline of the dominant kernel, the resident-set rebuild (HBM:
     every listed row written, 3 x 4 x 59 B, and read from the previous set or the reload
     staging, 24 B of point and colour for a new one)."""

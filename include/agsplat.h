@@ -396,10 +396,12 @@ int ags_map_destroy(ags_map* map);
  * rows, which must be >= min(in->n + n_points, tau).  point_id: device int32[n_points] (or
  * NULL): the splat id of each point.  evicted_ids: device int32[n_points] (or NULL): the ids
  * offloaded by this call, in row order.  Host-synchronous: returns after the stream's work
- * (two synchronisations: the reload list, then the offloaded rows in pinned memory); a host
- * thread then writes the offloaded rows into the host store while the caller goes on, and
- * the next call on the map waits for it first (so do ags_map_sync, ags_map_read_store and
- * ags_map_destroy).  INVALID_ARG for bad
+ * (two synchronisations: the reload list, then the new resident set).  The offloaded rows
+ * leave for pinned memory on a copy stream of the map's own, which waits for them to be
+ * staged and then overlaps whatever the caller enqueues next; a host thread waits for that
+ * copy and writes the rows into the host store, and the next call on the map waits for it
+ * first (so do ags_map_sync, ags_map_read_store and ags_map_destroy; a failed copy makes the
+ * next of them return AGS_ERR_HIP).  INVALID_ARG for bad
  * pointers or sizes, CAPACITY when n_ids + n_points > max_ids (nothing changed); after
  * AGS_ERR_HIP the map's state is undefined (destroy it). */
 int ags_map_insert(ags_map* map, const float* points, const float* colors, int64_t n_points, int32_t frame,
@@ -408,7 +410,8 @@ int ags_map_insert(ags_map* map, const float* points, const float* colors, int64
                    int32_t* out_ids, int32_t* point_id, int32_t* evicted_ids, ags_map_counts* counts,
                    void* stream);
 
-/* Waits until the host store holds the rows the last call offloaded. */
+/* Waits until the host store holds the rows the last call offloaded; AGS_ERR_HIP if their
+ * copy failed. */
 int ags_map_sync(ags_map* map);
 
 /* Copies per-id state to host memory (any pointer may be NULL): keys[n_ids], last_used[n_ids],

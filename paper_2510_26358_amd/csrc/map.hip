@@ -26,6 +26,7 @@
 #include <sys/mman.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <thread>
 #include <vector>
@@ -71,9 +72,15 @@ struct ags_map {
     float* pinned;                 // [max_points][3 F]
     float* store;                  // [max_ids][3 F], anonymous mapping, pages committed on use
     size_t store_bytes;
+    int32_t* h_evicted;            // [max_points] pinned: ids of the offloaded rows
     std::vector<uint32_t> h_list;
-    std::vector<int32_t> h_evicted;
+    // offload: the rows leave on a copy stream of the map's own (default priority), so the
+    // transfer overlaps the caller's next work; a host thread waits for it and writes the
+    // rows into the host store
+    hipStream_t cstream;
+    hipEvent_t ev_ready, ev_copied;
     std::thread flush;             // host-store writes of the last call's offloaded rows
+    std::atomic<int> flush_err;    // a HIP error seen by that thread
 };
 
 namespace ags {
@@ -377,13 +384,15 @@ void parallel_rows(long long n, long long min_per_thread, Fn fn) {
     for (auto& th : pool) th.join();
 }
 
-// Waits for the host-store writes of the previous call (they read the pinned staging).
-void flush_join(ags_map* m) {
+// Waits for the host-store writes of the previous call (they read the pinned staging);
+// AGS_ERR_HIP if its copy failed.
+int flush_join(ags_map* m) {
     if (m->flush.joinable()) m->flush.join();
+    return m->flush_err.exchange(0) ? AGS_ERR_HIP : AGS_OK;
 }
 
 void map_free(ags_map* m) {
-    flush_join(m);
+    (void)flush_join(m);
     void* dev[] = {m->tab_keys, m->tab_vals, m->tab_claim, m->id_key, m->id_last, m->id_res, m->reload_mark,
                    m->slot, m->newf, m->rank, m->new_point, m->reload_pos, m->reload_list, m->keys[0],
                    m->keys[1], m->vals[0], m->vals[1], m->evict_flag, m->evict_pos, m->evict_ids,
@@ -391,6 +400,10 @@ void map_free(ags_map* m) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (m->pinned) (void)hipHostFree(m->pinned);
+    if (m->h_evicted) (void)hipHostFree(m->h_evicted);
+    if (m->ev_ready) (void)hipEventDestroy(m->ev_ready);
+    if (m->ev_copied) (void)hipEventDestroy(m->ev_copied);
+    if (m->cstream) (void)hipStreamDestroy(m->cstream);
     if (m->store) munmap(m->store, m->store_bytes);
     delete m;
 }
@@ -480,7 +493,11 @@ int ags_map_create(ags_ctx* ctx, const ags_map_config* cfg, ags_map** out) {
             return rc;
         }
     }
-    if (hipHostMalloc((void**)&m->pinned, row_bytes * (size_t)P, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&m->pinned, row_bytes * (size_t)P, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&m->h_evicted, 4 * (size_t)P, hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&m->cstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&m->ev_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&m->ev_copied, hipEventDisableTiming) != hipSuccess) {
         int rc = ctx_record_hip(ctx, hipGetLastError());
         map_free(m);
         return rc;
@@ -509,7 +526,6 @@ int ags_map_create(ags_ctx* ctx, const ags_map_config* cfg, ags_map** out) {
         return rc;
     }
     m->h_list.resize((size_t)P);
-    m->h_evicted.resize((size_t)P);
     *out = m;
     return AGS_OK;
 }
@@ -543,7 +559,7 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
     if (mp->n_ids + n_points > cfg.max_ids) return AGS_ERR_CAPACITY;
     ags_ctx* ctx = mp->ctx;
     if (hipSetDevice(mp->device) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
-    flush_join(mp);
+    if (flush_join(mp) != AGS_OK) return AGS_ERR_HIP;  // the previous call's offload failed
     hipStream_t s = (hipStream_t)stream;
     const MapDev m = dev_of(mp);
     KeyParams kp;
@@ -660,18 +676,26 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
                            m);
     }
     if (n_evict > 0) {
+        // the offloaded rows (device staging, written by the rebuild) go to pinned memory on
+        // the copy stream, which waits for the rebuild; the caller's stream goes on at once
+        if (hipEventRecord(mp->ev_ready, s) != hipSuccess || hipStreamWaitEvent(mp->cstream, mp->ev_ready, 0) != hipSuccess)
+            return ctx_record_hip(ctx, hipGetLastError());
         {
-            StageTimer tm(ctx, ST_MAP_COPY, s);
+            StageTimer tm(ctx, ST_MAP_COPY, mp->cstream);  // the copies alone, after the wait
             if (hipMemcpyAsync(mp->pinned, mp->stage_out, row_f * sizeof(float) * (size_t)n_evict,
-                               hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(mp->h_evicted.data(), mp->evict_ids, 4 * (size_t)n_evict, hipMemcpyDeviceToHost,
-                               s) != hipSuccess)
+                               hipMemcpyDeviceToHost, mp->cstream) != hipSuccess ||
+                hipMemcpyAsync(mp->h_evicted, mp->evict_ids, 4 * (size_t)n_evict, hipMemcpyDeviceToHost,
+                               mp->cstream) != hipSuccess ||
+                hipEventRecord(mp->ev_copied, mp->cstream) != hipSuccess)
                 return ctx_record_hip(ctx, hipGetLastError());
         }
-        if (hipStreamSynchronize(s) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
-        // the rows go into the host store on a host thread while the caller goes on; the
-        // next call (or ags_map_sync / read_store / destroy) waits for it first
+        // a host thread waits for the copy and puts the rows into the host store while the
+        // caller goes on; the next call (or ags_map_sync / read_store / destroy) joins it first
         auto write_rows = [mp, n_evict, row_f]() {
+            if (hipEventSynchronize(mp->ev_copied) != hipSuccess) {
+                mp->flush_err.store(1);
+                return;
+            }
             parallel_rows(n_evict, 2048, [&](long long b, long long e) {
                 for (long long r = b; r < e; ++r)
                     memcpy(mp->store + (size_t)mp->h_evicted[r] * row_f, mp->pinned + r * row_f,
@@ -683,9 +707,9 @@ int ags_map_insert(ags_map* mp, const float* points, const float* colors, int64_
         } catch (...) {
             write_rows();  // no thread available: write them now
         }
-    } else if (hipStreamSynchronize(s) != hipSuccess) {
-        return ctx_record_hip(ctx, hipGetLastError());
     }
+    // the resident set is complete when the call returns
+    if (hipStreamSynchronize(s) != hipSuccess) return ctx_record_hip(ctx, hipGetLastError());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_record_hip(ctx, e);
     mp->n_ids += n_new;
@@ -720,14 +744,13 @@ int ags_map_export(ags_map* mp, uint64_t* keys, int32_t* last_used, uint8_t* res
 
 int ags_map_sync(ags_map* mp) {
     if (!mp) return AGS_ERR_INVALID_ARG;
-    flush_join(mp);
-    return AGS_OK;
+    return flush_join(mp);
 }
 
 int ags_map_read_store(ags_map* mp, const int32_t* ids, int64_t n, float* rows) {
     if (!mp || n < 0 || (n > 0 && (!ids || !rows))) return AGS_ERR_INVALID_ARG;
     if (n == 0) return AGS_OK;
-    flush_join(mp);
+    if (flush_join(mp) != AGS_OK) return AGS_ERR_HIP;
     std::vector<uint8_t> res((size_t)mp->n_ids);
     if (hipSetDevice(mp->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
         (mp->n_ids > 0 && hipMemcpy(res.data(), mp->id_res, (size_t)mp->n_ids, hipMemcpyDeviceToHost) != hipSuccess))
