@@ -46,7 +46,7 @@ struct Layout {
     int tile_bits;
     int depth_grid, tile_grid;
     // saved
-    size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_t_final, s_last, s_total;
+    size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_work, s_t_final, s_last, s_total;
     // fwd ws
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
@@ -128,6 +128,7 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.s_pair_count = o; o = align_up(o + (size_t)Qs * 4);
     L.s_tile_pairs = o; o = align_up(o + (size_t)caps * 4);
     L.s_ranges = o; o = align_up(o + (size_t)(tiles > 0 ? tiles : 1) * 8);
+    L.s_work = o; o = align_up(o + (size_t)(tiles > 0 ? tiles : 1) * 4);
     L.s_t_final = o; o = align_up(o + (size_t)pix * 4);
     L.s_last = o; o = align_up(o + (size_t)pix * 4);
     L.s_total = o;
@@ -224,6 +225,7 @@ BinArgs bin_args(const Layout& L, void* saved, void* ws) {
     a.tile_vals[0] = at<uint32_t>(saved, L.s_tile_pairs);
     a.tile_vals[1] = at<uint32_t>(ws, L.f_tvals1);
     a.ranges = at<uint32_t>(saved, L.s_ranges);
+    a.work = at<uint32_t>(saved, L.s_work);
     a.final_vals = a.tile_vals[0];
     a.tile_bits = L.tile_bits;
     a.scan_tmp.block_sums = at<uint32_t>(ws, L.f_block_sums);
@@ -414,6 +416,7 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         ra.records = at<float>(saved, L.s_records);
         ra.tile_pairs = at<uint32_t>(saved, L.s_tile_pairs);
         ra.ranges = at<uint32_t>(saved, L.s_ranges);
+        ra.work = at<uint32_t>(saved, L.s_work);
         ra.rgb = out->rgb;
         ra.depth = out->depth;
         ra.alpha = out->alpha;
@@ -512,6 +515,7 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
     ra.records = at<float>(saved, L.s_records);
     ra.tile_pairs = at<uint32_t>(saved, L.s_tile_pairs);
     ra.ranges = at<uint32_t>(saved, L.s_ranges);
+    ra.work = at<uint32_t>(saved, L.s_work);
     ra.t_final = at<float>(saved, L.s_t_final);
     ra.last = at<uint32_t>(saved, L.s_last);
     ra.grad2d = grad2d;

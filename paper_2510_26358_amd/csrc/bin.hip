@@ -162,6 +162,36 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* keys, const
     }
 }
 
+// Raster work order: every tile once, longest lists first (by 4 log2(length + 1) buckets),
+// so the few heavy tiles start early instead of trailing the launch.  One workgroup: bucket
+// counts in LDS, their scan in descending bucket order, then each tile claims a slot of its
+// bucket (the order inside a bucket is that of the claims; any order gives the same image).
+constexpr int kWorkThreads = 1024, kWorkBuckets = 64;
+__global__ __launch_bounds__(kWorkThreads) void work_list_kernel(const uint32_t* ranges, int n_tiles,
+                                                                 uint32_t* work) {
+    __shared__ uint32_t cnt[kWorkBuckets];
+    const int t = threadIdx.x;
+    if (t < kWorkBuckets) cnt[t] = 0;
+    __syncthreads();
+    auto bucket = [&](int tile) {
+        const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+        const int b = (int)(4.f * log2f((float)len + 1.f));
+        return b < kWorkBuckets - 1 ? b : kWorkBuckets - 1;
+    };
+    for (int tile = t; tile < n_tiles; tile += kWorkThreads) atomicAdd(&cnt[bucket(tile)], 1u);
+    __syncthreads();
+    if (t == 0) {  // exclusive starts, largest bucket first
+        uint32_t run = 0;
+        for (int b = kWorkBuckets - 1; b >= 0; --b) {
+            const uint32_t c = cnt[b];
+            cnt[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int tile = t; tile < n_tiles; tile += kWorkThreads) work[atomicAdd(&cnt[bucket(tile)], 1u)] = (uint32_t)tile;
+}
+
 // Stage entry from externally supplied records: counts and depth bits per pair.
 __global__ void count_from_records_kernel(ViewTable vt, const float* records, const uint8_t* valid,
                                           long long n_pairs, uint32_t* pair_count, uint32_t* pair_z) {
@@ -224,6 +254,9 @@ int launch_binning(BinArgs& a, hipStream_t s) {
                                           : 1);
     hipLaunchKernelGGL(ranges_kernel, dim3(rgrid), dim3(256), 0, s, tk[rt], a.counters, a.capacity,
                        (uint32_t)n_tiles, a.ranges);
+    // 7. raster work order
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(work_list_kernel, dim3(1), dim3(kWorkThreads), 0, s, a.ranges, (int)n_tiles, a.work);
     (void)tv;
     return (int)hipGetLastError();
 }

@@ -440,6 +440,7 @@ struct BinArgs {
     uint32_t* tile_keys[2];  // [capacity]
     uint32_t* tile_vals[2];
     uint32_t* ranges;        // [n_tiles][2]
+    uint32_t* work;          // [n_tiles] raster work order: tiles by descending list length
     uint32_t* final_vals;    // where the tile-sorted pair ids must end (== one of tile_vals)
     int tile_bits;
     ScanTemp scan_tmp;
@@ -459,6 +460,7 @@ struct RasterArgs {
     const float* records;
     const uint32_t* tile_pairs;
     const uint32_t* ranges;
+    const uint32_t* work;  // [n_tiles] tile of each workgroup, longest lists first
     float* rgb;
     float* depth;
     float* alpha;
@@ -474,6 +476,7 @@ struct RasterBwdArgs {
     const float* records;
     const uint32_t* tile_pairs;
     const uint32_t* ranges;
+    const uint32_t* work;  // as in RasterArgs
     const float* t_final;
     const uint32_t* last;
     // upstream mode

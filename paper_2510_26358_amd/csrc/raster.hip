@@ -182,7 +182,7 @@ template <int T, int PPT, int M, bool S2>
 __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ SRec srec[M];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = (int)a.work[blockIdx.x];
     const TileCoord tc = tile_coord(a.vt, tile);
     const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
     const uint32_t end = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile + 1]);
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     __shared__ SRec srec[M];
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = (int)a.work[blockIdx.x];
     const TileCoord tc = tile_coord(a.vt, tile);
     const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
     const int tid = threadIdx.x;
