@@ -128,7 +128,7 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.s_pair_count = o; o = align_up(o + (size_t)Qs * 4);
     L.s_tile_pairs = o; o = align_up(o + (size_t)caps * 4);
     L.s_ranges = o; o = align_up(o + (size_t)(tiles > 0 ? tiles : 1) * 8);
-    L.s_work = o; o = align_up(o + (size_t)(tiles > 0 ? tiles : 1) * 4);
+    L.s_work = o; o = align_up(o + (size_t)(tiles > 0 ? tiles + 8 * (kWorkStrip + 1) : 1) * 4);
     L.s_t_final = o; o = align_up(o + (size_t)pix * 4);
     L.s_last = o; o = align_up(o + (size_t)pix * 4);
     L.s_total = o;

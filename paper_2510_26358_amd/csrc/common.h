@@ -497,6 +497,11 @@ struct RasterBwdArgs {
 };
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
 int raster_blocks(const ViewTable& vt);
+// Raster work list: strips of kWorkStrip consecutive tiles go round-robin to the eight XCDs
+// (workgroup g runs on XCD g % 8); each XCD takes its strips' tiles longest list first.
+// raster_blocks() workgroups, some of them (at most 8 (kWorkStrip + 1)) with no tile.
+constexpr int kWorkStrip = 8;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 
 struct SsimArgs {
     ViewTable vt;

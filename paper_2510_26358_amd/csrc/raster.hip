@@ -182,7 +182,9 @@ template <int T, int PPT, int M, bool S2>
 __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
     constexpr int NT = T * T / PPT;
     __shared__ SRec srec[M];
-    const int tile = (int)a.work[blockIdx.x];
+    const uint32_t wt = a.work[blockIdx.x];
+    if (wt == kNoTile) return;  // padding of a shorter XCD list (whole workgroup)
+    const int tile = (int)wt;
     const TileCoord tc = tile_coord(a.vt, tile);
     const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
     const uint32_t end = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile + 1]);
@@ -294,7 +296,9 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     __shared__ SRec srec[M];
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
-    const int tile = (int)a.work[blockIdx.x];
+    const uint32_t wt = a.work[blockIdx.x];
+    if (wt == kNoTile) return;  // padding of a shorter XCD list (whole workgroup)
+    const int tile = (int)wt;
     const TileCoord tc = tile_coord(a.vt, tile);
     const uint32_t start = __builtin_amdgcn_readfirstlane(a.ranges[2 * tile]);
     const int tid = threadIdx.x;
@@ -459,7 +463,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     }
 }
 
-int raster_blocks(const ViewTable& vt) { return vt.tile_base[vt.n_views]; }
+int raster_blocks(const ViewTable& vt) {
+    const int n = vt.tile_base[vt.n_views];
+    if (n <= 0) return 0;
+    const int strips = (n + kWorkStrip - 1) / kWorkStrip;
+    return 8 * ((strips + 7) / 8) * kWorkStrip;  // 8 XCD lists of equal (maximum) length
+}
 
 #define AGS_RASTER_CONFIGS(X) \
     X(8, 1, 64)               \
