@@ -164,39 +164,44 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* keys, const
 
 // Raster work order (see kWorkStrip): per XCD, its tiles by descending list length in 64
 // buckets of 4 log2(length + 1), so the few heavy tiles start early instead of trailing the
-// launch, while neighbouring tiles (which share records) stay on one XCD's L2.  One workgroup:
-// the list is cleared to kNoTile, bucket counts per XCD in LDS, their scans in descending
-// bucket order, then each tile claims a slot of its (XCD, bucket) (the order inside a bucket
-// is that of the claims; any order gives the same image); XCD x's k-th tile goes to
-// workgroup 8 k + x.
+// launch, while neighbouring tiles (which share records) stay on one XCD's L2.  Workgroup x
+// builds XCD x's list, the slots 8 k + x: it clears them to kNoTile, counts its tiles per
+// bucket in LDS, scans the counts in descending bucket order, and lets each tile claim a
+// slot of its bucket (the order inside a bucket is that of the claims; any order gives the
+// same image).
 constexpr int kWorkThreads = 1024, kWorkBuckets = 64;
 __global__ __launch_bounds__(kWorkThreads) void work_list_kernel(const uint32_t* ranges, int n_tiles, int n_slots,
                                                                  uint32_t* work) {
-    __shared__ uint32_t cnt[8][kWorkBuckets];
-    const int t = threadIdx.x;
-    for (int e = t; e < 8 * kWorkBuckets; e += kWorkThreads) (&cnt[0][0])[e] = 0;
-    for (int g = t; g < n_slots; g += kWorkThreads) work[g] = kNoTile;
+    __shared__ uint32_t cnt[kWorkBuckets];
+    const int t = threadIdx.x, x = blockIdx.x;
+    const int per = n_slots / 8;  // slots of one XCD list (a whole number of strips)
+    if (t < kWorkBuckets) cnt[t] = 0;
+    for (int k = t; k < per; k += kWorkThreads) work[8 * k + x] = kNoTile;
     __syncthreads();
+    // i-th tile of XCD x: strip x + 8 (i / kWorkStrip), position i % kWorkStrip in it
+    auto tile_of = [&](int i) { return (x + 8 * (i / kWorkStrip)) * kWorkStrip + i % kWorkStrip; };
     auto bucket = [&](int tile) {
         const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
         const int b = (int)(4.f * log2f((float)len + 1.f));
         return b < kWorkBuckets - 1 ? b : kWorkBuckets - 1;
     };
-    auto xcd = [](int tile) { return (tile / kWorkStrip) & 7; };
-    for (int tile = t; tile < n_tiles; tile += kWorkThreads) atomicAdd(&cnt[xcd(tile)][bucket(tile)], 1u);
+    for (int i = t; i < per; i += kWorkThreads) {
+        const int tile = tile_of(i);
+        if (tile < n_tiles) atomicAdd(&cnt[bucket(tile)], 1u);
+    }
     __syncthreads();
-    if (t < 8) {  // exclusive ranks per XCD, largest bucket first
+    if (t == 0) {  // exclusive ranks, largest bucket first
         uint32_t run = 0;
         for (int b = kWorkBuckets - 1; b >= 0; --b) {
-            const uint32_t c = cnt[t][b];
-            cnt[t][b] = run;
+            const uint32_t c = cnt[b];
+            cnt[b] = run;
             run += c;
         }
     }
     __syncthreads();
-    for (int tile = t; tile < n_tiles; tile += kWorkThreads) {
-        const int x = xcd(tile);
-        work[8 * atomicAdd(&cnt[x][bucket(tile)], 1u) + x] = (uint32_t)tile;
+    for (int i = t; i < per; i += kWorkThreads) {
+        const int tile = tile_of(i);
+        if (tile < n_tiles) work[8 * atomicAdd(&cnt[bucket(tile)], 1u) + x] = (uint32_t)tile;
     }
 }
 
@@ -264,7 +269,7 @@ int launch_binning(BinArgs& a, hipStream_t s) {
                        (uint32_t)n_tiles, a.ranges);
     // 7. raster work order
     if (n_tiles > 0)
-        hipLaunchKernelGGL(work_list_kernel, dim3(1), dim3(kWorkThreads), 0, s, a.ranges, (int)n_tiles,
+        hipLaunchKernelGGL(work_list_kernel, dim3(8), dim3(kWorkThreads), 0, s, a.ranges, (int)n_tiles,
                            raster_blocks(a.vt), a.work);
     (void)tv;
     return (int)hipGetLastError();
