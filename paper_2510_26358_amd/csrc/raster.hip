@@ -46,15 +46,6 @@ __device__ __forceinline__ TileCoord tile_coord(const ViewTable& vt, int tile) {
     return c;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs on XCD g % 8).
-// Give each XCD one contiguous band of tiles instead of every 8th tile, so the Gaussians
-// (records and adjoint lines) a workgroup touches stay in its own XCD's L2.  A bijection
-// on [0, n_tiles).
-__device__ __forceinline__ int xcd_tile(int g, int n_tiles) {
-    const int q = n_tiles >> 3, r = n_tiles & 7, x = g & 7;
-    return x * q + (x < r ? x : r) + (g >> 3);
-}
-
 // Each wave owns a rectangular block of the tile: 8 columns x 8 PPT rows when the tile has
 // enough waves for its 8-wide column strips, else the full tile width.  Lane l covers
 // column l % BW and PPT vertically adjacent rows.  The per-record wave mask below lets a
