@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define AGS_ABI_VERSION 3
+#define AGS_ABI_VERSION 4
 #define AGS_MAX_VIEWS 32
 
 enum {
@@ -206,6 +206,11 @@ typedef struct ags_sizes {
     size_t off_t_final;      /* float[P]: final transmittance */
     size_t off_last;         /* uint32[P]: tile-list entries up to the last contributor */
     size_t off_tile_keys;    /* (forward workspace) uint32[capacity]: sorted global tile ids */
+    size_t off_work;         /* uint32[n_work]: the tile of each raster workgroup (see below) */
+    int64_t n_work;          /* raster workgroups: strips of 8 tiles go round-robin to eight
+                                lists (workgroup g in list g mod 8), each list holds its tiles
+                                by descending list length (4 log2(length + 1) buckets) and is
+                                padded to equal length with 0xFFFFFFFF (no tile) */
 } ags_sizes;
 
 typedef struct ags_ctx ags_ctx;

@@ -97,7 +97,7 @@ class Sizes(C.Structure):
                 ("off_records", C.c_size_t), ("off_pair_count", C.c_size_t),
                 ("off_tile_pairs", C.c_size_t), ("off_ranges", C.c_size_t),
                 ("off_t_final", C.c_size_t), ("off_last", C.c_size_t),
-                ("off_tile_keys", C.c_size_t)]
+                ("off_tile_keys", C.c_size_t), ("off_work", C.c_size_t), ("n_work", C.c_int64)]
 
 
 class Adam(C.Structure):
@@ -107,7 +107,7 @@ class Adam(C.Structure):
                 ("eps", C.c_float)]
 
 
-ABI_VERSION = 3  # include/agsplat.h AGS_ABI_VERSION
+ABI_VERSION = 4  # include/agsplat.h AGS_ABI_VERSION
 
 _lib = None
 

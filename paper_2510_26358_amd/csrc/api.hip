@@ -368,6 +368,8 @@ int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_ga
     // keys and values ping-pong together and the values end in `saved` (buffer 0 of the
     // tile sort), so the sorted keys end in the workspace's first key buffer
     out->off_tile_keys = L.f_tkeys0;
+    out->off_work = L.s_work;
+    out->n_work = raster_blocks(L.vt);
     return AGS_OK;
 }
 

@@ -46,10 +46,11 @@ def saved_arrays(buf, views: ViewSpec):
     pairs = buf.view(s.off_tile_pairs, n_list, torch.int32).cpu().numpy().astype(np.int64)
     ranges = buf.view(s.off_ranges, 2 * s.n_tiles, torch.int32).view(-1, 2).cpu().numpy().astype(np.int64)
     keys = buf.fwd_ws[s.off_tile_keys:s.off_tile_keys + 4 * n_list].view(torch.int32).cpu().numpy()
+    work = buf.view(s.off_work, s.n_work, torch.int32).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
     return {"K": int(k), "V": int(v), "overflow": int(over), "K_kept": int(keff), "n_listed": n_list,
             "t_final": t_final,
             "last": last, "records": recs, "pair_count": cnt, "tile_pairs": pairs, "ranges": ranges,
-            "tile_keys": keys.astype(np.int64) & 0xFFFFFFFF}
+            "tile_keys": keys.astype(np.int64) & 0xFFFFFFFF, "work": work}
 
 
 def run_loss_backward(scene, ras: Rasterizer, masks=None, w_l1=1.0, lam=1.0, capacity=None, ssim_w=0.0,

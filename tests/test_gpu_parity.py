@@ -149,6 +149,31 @@ def test_binning_bit_exact_on_seeded_records(tile, sizes):
     gkeys = (sv["tile_keys"].astype(np.uint64) << np.uint64(32)) | zb
     assert np.array_equal(gkeys, keys)
     assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
+    _check_work_list(sv["work"], sv["ranges"])
+
+
+def _check_work_list(work, ranges):
+    """The raster work list: every tile exactly once; strips of 8 consecutive tiles dealt
+    round-robin to 8 interleaved lists (workgroup g in list g % 8); each list by descending
+    4 log2(length + 1) bucket (a float32 bucket boundary may differ from the float64 one by
+    rounding, so pairs within 1e-4 of an integer are not held to it); padding only at the
+    ends of the lists."""
+    NO = 0xFFFFFFFF
+    n_t = len(ranges)
+    strips = -(-n_t // 8)
+    assert len(work) == 8 * (-(-strips // 8)) * 8
+    assert sorted(work[work != NO].tolist()) == list(range(n_t))
+    level = 4 * np.log2((ranges[:, 1] - ranges[:, 0]).astype(np.float64) + 1)
+    for x in range(8):
+        lst = work[x::8]
+        real = lst[lst != NO]
+        assert np.all(lst[len(real):] == NO)  # padding is a suffix
+        assert np.all((real // 8) % 8 == x)
+        lv = level[real]
+        b = np.minimum(63, np.floor(lv))
+        up = np.nonzero(b[1:] > b[:-1])[0]
+        near = np.abs(lv - np.round(lv)) < 1e-4
+        assert all(near[i] or near[i + 1] for i in up), (x, up[:5])
 
 
 def test_misaligned_buffers_are_rejected_before_any_launch():
