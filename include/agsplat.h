@@ -99,9 +99,10 @@ typedef struct ags_views {
  *   opacity_logits [n] (opacity = sigmoid), sh [K][3][n] (coefficient k, channel c of
  *   Gaussian i at (k * 3 + c) * n + i; real SH, l-major, m = -l..l, Condon-Shortley phase;
  *   colour = max(0, sum_k Y_k(d) sh_k + 0.5), d the unit direction camera centre -> mean).
- * All arithmetic is float32: keep world coordinates near the origin of the frame they are
- * rendered in (e.g. one frame per sub-map); hundreds of metres out, float32 spacing moves
- * projected centres by hundredths of a pixel once the camera transform cancels them. */
+ * Arithmetic is float32 except the world -> camera transform R mu + t and the camera-centre
+ * offset mu + R^T t, which are evaluated in float64 and rounded once, so Gaussians and
+ * cameras far from the frame origin (one global map, kilometres across) project as the
+ * float32 inputs define, without the cancellation a float32 transform would suffer. */
 typedef struct ags_gaussians {
     int32_t n;
     int32_t sh_degree;        /* 0 .. 3 */

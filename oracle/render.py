@@ -112,6 +112,11 @@ def project(p, cam, delta, s: RenderSettings, sh_degree: int):
     v = cam.fy * y / zs + cam.cy
     o = torch.sigmoid(p["opacity_logits"][g0:g1])
     valid = valid & (o >= s.alpha_min).detach()
+    # bound on the rounding error of z = R_2 . mu + t_2 in any float64 evaluation order
+    # (each product exact, a few roundings of at most 2^-53 of the running sum): 2^-44 times
+    # the sum of the terms' magnitudes leaves a wide margin
+    with torch.no_grad():
+        z_err = 2.0 ** -44 * (mu.abs() @ R[2].abs() + t[2].abs())
     centre = -(R.T @ t)
     dvec = mu - centre
     d = dvec / torch.linalg.norm(dvec, dim=-1, keepdim=True)
@@ -123,7 +128,7 @@ def project(p, cam, delta, s: RenderSettings, sh_degree: int):
         lnterm = torch.where(valid, 2.0 * torch.log(255.0 * o.clamp_min(1e-30)), zero)
         ext = torch.stack([torch.sqrt(lnterm.clamp_min(0) * a), torch.sqrt(lnterm.clamp_min(0) * c)], -1)
     return {"u": u, "v": v, "conic": conic, "o": o, "rgb": rgb, "z": z, "valid": valid,
-            "cov2d": S2, "ext": ext, "g0": g0}
+            "cov2d": S2, "ext": ext, "g0": g0, "z_err": z_err}
 
 
 @dataclass
@@ -136,12 +141,31 @@ class Decisions:
     touched: list          # per pixel: local indices processed (contributors + stopper)
 
 
-def composite_decisions(proj, px, py, s: RenderSettings, rel_margin=1e-5, ulps=4,
+def depth_key_range(z64, z_err):
+    """The float32 depth keys another float64 evaluation of z (error at most `z_err`) could
+    round to: (lo, hi), equal to float32(z) unless z lies within z_err of a rounding
+    boundary (the midpoint between adjacent float32 values), where the two float32 values
+    beside that boundary are both possible."""
+    z64 = np.asarray(z64, np.float64)
+    err = np.asarray(z_err, np.float64)
+    lo = (z64 - err).astype(np.float32)
+    hi = (z64 + err).astype(np.float32)
+    return lo, hi
+
+
+def depth_key_uncertain(z64, z_err):
+    """Whether float32(z) could round differently in another float64 evaluation of z."""
+    lo, hi = depth_key_range(z64, z_err)
+    return lo != hi
+
+
+def composite_decisions(proj, px, py, s: RenderSettings, rel_margin=1e-5,
                         budget=4_000_000) -> Decisions:
     """Brute force over every valid Gaussian for each pixel: which Gaussians contribute and
-    in what order.  Also flags pixels whose result depends on a decision that float32
-    rounding could flip (alpha near alpha_min or alpha_max, T' near t_min, near-equal
-    depths among processed Gaussians)."""
+    in what order.  Also flags pixels whose result depends on a decision that rounding could
+    flip (alpha within rel_margin of alpha_min or alpha_max, T' within rel_margin of t_min, a
+    processed Gaussian whose float32 depth key is uncertain (`depth_key_range`) next to
+    another processed Gaussian whose key could equal or pass it)."""
     with torch.no_grad():
         vidx = torch.nonzero(proj["valid"]).flatten()
         u = proj["u"][vidx]
@@ -149,7 +173,9 @@ def composite_decisions(proj, px, py, s: RenderSettings, rel_margin=1e-5, ulps=4
         A, B, C = proj["conic"][vidx].unbind(-1)
         o = proj["o"][vidx]
         z64 = proj["z"][vidx].numpy()
+        zlo, zhi = depth_key_range(z64, proj["z_err"][vidx].numpy())
     z32 = z64.astype(np.float32)
+    zunc = zlo != zhi
     vidx_np = vidx.numpy()
     P = len(px)
     lists, clamps, amb, touched = [], [], np.zeros(P, bool), []
@@ -191,11 +217,14 @@ def composite_decisions(proj, px, py, s: RenderSettings, rel_margin=1e-5, ulps=4
                 cl.append(bool(araw_np[r, j] > s.alpha_max))
                 T = Tn
             if len(tch) > 1:
-                zt = z32[np.array(tch)]
-                gaps = np.diff(zt.astype(np.float64))
-                tol = ulps * np.spacing(np.maximum(np.abs(zt[1:]), np.abs(zt[:-1])))
-                if np.any(np.abs(gaps) <= tol):
-                    ambig = True
+                # the order of two processed Gaussians can change only if one's key is
+                # uncertain and the other's possible keys meet its range
+                ta = np.array(tch)
+                for j in ta[zunc[ta]]:
+                    others = ta[ta != j]
+                    if np.any((zhi[others] >= zlo[j]) & (zlo[others] <= zhi[j])):
+                        ambig = True
+                        break
             lists.append(vidx_np[np.array(out, dtype=np.int64)] if out else np.zeros(0, np.int64))
             clamps.append(np.array(cl, dtype=bool))
             touched.append(vidx_np[np.array(tch, dtype=np.int64)] if tch else np.zeros(0, np.int64))

@@ -237,6 +237,30 @@ __device__ __forceinline__ T* opaque_ptr(T* p) {
 }
 
 // Unit quaternion (w, x, y, z) -> row-major rotation matrix.
+// World -> camera point x_c = R mu + t of camera `cam`, evaluated in float64 and rounded
+// once.  Far from the frame origin (one global map, sub-maps hundreds of metres apart) R mu
+// and t nearly cancel, and a float32 evaluation would keep only |t| 2^-24 (1e-4 m at 1.4 km)
+// of the metre-scale difference; each float32 x float32 product is exact in float64.
+__device__ __forceinline__ void world_to_cam(const ags_camera& cam, float mx, float my, float mz, float& x,
+                                             float& y, float& z) {
+    const double X = mx, Y = my, Z = mz;
+    const float* R = cam.R;
+    x = (float)fma((double)R[0], X, fma((double)R[1], Y, fma((double)R[2], Z, (double)cam.t[0])));
+    y = (float)fma((double)R[3], X, fma((double)R[4], Y, fma((double)R[5], Z, (double)cam.t[1])));
+    z = (float)fma((double)R[6], X, fma((double)R[7], Y, fma((double)R[8], Z, (double)cam.t[2])));
+}
+
+// mu - C, the vector from camera `cam`'s centre C = -R^T t to the mean (the SH viewing
+// direction before normalisation), in float64 for the same reason.
+__device__ __forceinline__ void centre_to_mean(const ags_camera& cam, float mx, float my, float mz, float& dx,
+                                               float& dy, float& dz) {
+    const double t0 = cam.t[0], t1 = cam.t[1], t2 = cam.t[2];
+    const float* R = cam.R;
+    dx = (float)fma((double)R[0], t0, fma((double)R[3], t1, fma((double)R[6], t2, (double)mx)));
+    dy = (float)fma((double)R[1], t0, fma((double)R[4], t1, fma((double)R[7], t2, (double)my)));
+    dz = (float)fma((double)R[2], t0, fma((double)R[5], t1, fma((double)R[8], t2, (double)mz)));
+}
+
 __device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
     R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
     R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);

@@ -3,7 +3,7 @@
 // One thread per Gaussian reads its parameters once (coalesced structure-of-arrays loads)
 // and loops over the views whose Gaussian range contains it, so a rig of B cameras costs
 // one parameter read instead of B.  Per view it computes (Sec. III-B):
-//   x_c = R_b mu + t_b; Sigma = R(q) diag(e^{2s}) R(q)^T;
+//   x_c = R_b mu + t_b (in float64, rounded once); Sigma = R(q) diag(e^{2s}) R(q)^T;
 //   Sigma' = J R_b Sigma R_b^T J^T + blur I; conic = Sigma'^{-1};
 //   (u, v) = (fx x/z + cx, fy y/z + cy); o = sigmoid(omega);
 //   colour = max(0, SH(d) . f + 0.5) with d the unit direction from the camera centre;
@@ -54,9 +54,8 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
         const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
         const ags_camera cam = a.cams[b];
         const float* R = cam.R;
-        const float x = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
-        const float y = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
-        const float z = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
+        float x, y, z;
+        world_to_cam(cam, mx, my, mz, x, y, z);
         uint32_t cnt = 0;
         if (o_ok && z >= a.st.z_near) {
             const int W = vt.width[b], H = vt.height[b];
@@ -117,12 +116,9 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
         vis &= vis - 1u;
         const long long q = vt.pair_base[b] + (i - vt.g_begin[b]);
         const ags_camera cam = a.cams[b];
-        const float* R = cam.R;
         // camera centre C = -R^T t; direction d = (mu - C) / |mu - C|
-        const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
-        const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
-        const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
-        float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+        float dx, dy, dz;
+        centre_to_mean(cam, mx, my, mz, dx, dy, dz);
         const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
         dx *= il; dy *= il; dz *= il;
         float Y[16];

@@ -86,9 +86,8 @@ __device__ __forceinline__ void geometry_bwd(const ProjectBwdArgs& a) {
             const float g_o = g2[5], g_zd = g2[9];
             const ags_camera cam = opaque_ptr(a.cams)[b];
             const float* R = cam.R;
-            const float x = R[0] * mx + R[1] * my + R[2] * mz + cam.t[0];
-            const float y = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
-            const float z = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
+            float x, y, z;
+            world_to_cam(cam, mx, my, mz, x, y, z);
             const float rz = 1.f / z, rz2 = rz * rz;
             const float limx = a.st.fov_clamp * (float)vt.width[b] / (2.f * cam.fx);
             const float limy = a.st.fov_clamp * (float)vt.height[b] / (2.f * cam.fy);
@@ -302,10 +301,8 @@ __device__ __forceinline__ void colour_bwd(const ProjectBwdArgs& a) {
             const float gcol[3] = {rc.y > 0.f ? g67.x : 0.f, rc.z > 0.f ? g67.y : 0.f, rc.w > 0.f ? g89.x : 0.f};
             const ags_camera cam = a.cams[b];
             const float* R = cam.R;
-            const float Cx = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
-            const float Cy = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
-            const float Cz = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
-            float dx = mx - Cx, dy = my - Cy, dz = mz - Cz;
+            float dx, dy, dz;
+            centre_to_mean(cam, mx, my, mz, dx, dy, dz);
             const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
             dx *= il; dy *= il; dz *= il;
             float Y[16];

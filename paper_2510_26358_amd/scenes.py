@@ -315,20 +315,20 @@ SUBMAP_SIZES = (50_000, 100_000, 150_000, 250_000, 400_000, 500_000, 650_000, 80
 SUBMAP_RES = ((640, 400), (800, 500), (960, 600), (1120, 700), (1280, 800))
 
 
-def submap_scene(seed: int = 2514, sizes=SUBMAP_SIZES, with_targets: bool = True) -> Scene:
+def submap_scene(seed: int = 2514, sizes=SUBMAP_SIZES, with_targets: bool = True,
+                 spacing: float = 0.0, name: str = "submaps_2.9M") -> Scene:
     """Eight independent orchard patches of uneven size, concatenated into one Gaussian
     array; each patch is seen by 1-4 views (seeded) whose Gaussian range is that patch.
-    Each patch is given in its own submap frame (origin at the patch): sub-maps are rendered
-    and optimised independently, and one shared frame with patches hundreds of metres apart
-    would put float32 world coordinates where their spacing (1.2e-4 m at 1.4 km) moves
-    projected centres by hundredths of a pixel after the camera transform cancels them."""
+    Patch k sits at x = spacing * k of one shared world frame: spacing 0 gives every patch
+    its own submap frame (origin at the patch), spacing 200 m lays the patches out along one
+    global map, 1.4 km end to end (float32 world coordinates there are spaced 1.2e-4 m)."""
     rng = np.random.default_rng(seed)
     vrng = np.random.default_rng(seed + 200)
     parts, cams = [], []
     g0 = 0
-    for n in sizes:
-        # each patch is a 12 m slice of orchard, in its own submap frame
-        ox = 0.0
+    for k, n in enumerate(sizes):
+        # each patch is a 12 m slice of orchard
+        ox = spacing * k
         m, ls, q, lo, sh = orchard_gaussians(rng, n, 3, x_range=(-6.0, 6.0), origin=(ox, 0.0))
         parts.append((m, ls, q, lo, sh))
         n_views = int(vrng.integers(1, 5))
@@ -340,12 +340,19 @@ def submap_scene(seed: int = 2514, sizes=SUBMAP_SIZES, with_targets: bool = True
         g0 += n
     cat = [np.concatenate([p[j] for p in parts]) for j in range(5)]
     scene = Scene(_f32(cat[0]), _f32(cat[1]), _f32(cat[2]), _f32(cat[3]), _f32(cat[4]), 3,
-                  cams, name="submaps_2.9M")
+                  cams, name=name)
     if with_targets:
+        offsets = np.cumsum([0] + list(sizes))
         for c in cams:
+            k = int(np.searchsorted(offsets, c.g_begin, side="right") - 1)
             scene.gt_rgb.append(procedural_image(c.width, c.height, rng))
-            scene.lidar.append(simulate_lidar(c, rng, x_range=(-6.0, 6.0), origin=(0.0, 0.0)))
+            scene.lidar.append(simulate_lidar(c, rng, x_range=(-6.0, 6.0), origin=(spacing * k, 0.0)))
     return scene
+
+
+def submap_far_scene(seed: int = 2514) -> Scene:
+    """The sub-map workload with the eight patches 200 m apart in one global frame."""
+    return submap_scene(seed, spacing=200.0, name="submaps_far_2.9M")
 
 
 def perturb(scene: Scene, seed: int, mean_std=0.01, rho_std=0.02, phi_deg=0.5) -> Scene:
@@ -371,5 +378,6 @@ CONFIGS = {
     "single_view": single_view_scene,
     "multi_view": multi_view_scene,
     "submaps": submap_scene,
+    "submaps_far": submap_far_scene,
     "refine": refinement_scene,
 }

@@ -26,6 +26,20 @@ def ras():
     return Rasterizer(0)
 
 
+# Launch shapes of the full-size checks: the library default for both passes, and the pair
+# the autotuner picks on the 4-view workload (forward (16, 256, 1), backward (16, 128, 2)),
+# the configuration the throughput figure is timed in.
+SHAPES = {"default": dict(tile=16, batch=256, px_per_thread=1, batch_bwd=0, px_per_thread_bwd=0),
+          "tuned": dict(tile=16, batch=256, px_per_thread=1, batch_bwd=128, px_per_thread_bwd=2)}
+
+# Share of sampled pixels that may be set aside as ambiguous (a decision within rounding of
+# a cutoff, or a depth key on a float32 rounding boundary next to an equal key; decided by
+# the oracle alone), over all views and per view.  The seeded samples hold at most 0.25 %
+# over all views (6 of 2,432 on the refinement workload) and 4 of 608 pixels in one view.
+AMBIG_ALL = 0.005
+AMBIG_VIEW = 0.01
+
+
 def _sample_pixels(cam, rng, n_tiles=2, n_rand=96, T=16):
     ntx, nty = (cam.width + T - 1) // T, (cam.height + T - 1) // T
     pix = []
@@ -42,15 +56,27 @@ def _restrict_lidar(lid, pix):
     return {k: np.asarray(v)[keep] for k, v in lid.items()}
 
 
-@pytest.mark.parametrize("maker", ["single_view", "multi_view", "submaps", "refine"])
-def test_full_size_forward_and_gradients_on_pixel_samples(ras, maker):
+@pytest.mark.parametrize("maker,shape", [("single_view", "default"), ("single_view", "tuned"),
+                                         ("multi_view", "default"), ("multi_view", "tuned"),
+                                         ("submaps", "tuned"), ("submaps_far", "default"),
+                                         ("submaps_far", "tuned"), ("refine", "tuned")])
+def test_full_size_forward_and_gradients_on_pixel_samples(ras, maker, shape, record_property):
+    """Forward on seeded pixel samples and every gradient (L1 on the sample, LiDAR inside it)
+    at full size; `submaps_far` puts the eight sub-maps 200 m apart in one global frame
+    (coordinates up to 1.4 km), where the world-to-camera transform must not cancel."""
+    ras.set_config(**SHAPES[shape])
     sc = scenes.CONFIGS[maker]()
     rng = np.random.default_rng(4242)
     samples = [_sample_pixels(c, rng) for c in sc.cameras]
     sc.lidar = [_restrict_lidar(l, p) for l, p in zip(sc.lidar, samples)]
-    g = run_loss_backward(sc, ras, masks=samples, w_l1=1.0, lam=0.1)
+    try:
+        g = run_loss_backward(sc, ras, masks=samples, w_l1=1.0, lam=0.1)
+    finally:
+        ras.set_config(**SHAPES["default"])
     ref = loss_and_grads(sc, RenderSettings(), masks=samples, w_l1=1.0, lam=0.1)
     # forward on the sampled pixels
+    worst = {"rgb": 0.0, "alpha": 0.0, "depth_rel": 0.0}
+    n_amb = n_pix = 0
     for b, (gv, rv) in enumerate(zip(g["fwd"], ref["views"])):
         pix = rv["pix"]
         ok = ~rv["ambiguous"]
@@ -59,16 +85,26 @@ def test_full_size_forward_and_gradients_on_pixel_samples(ras, maker):
         e_a = np.abs(gv["alpha"].reshape(-1)[pix] - rv["alpha"])[ok].max(initial=0)
         e_d = (np.abs(gv["depth"].reshape(-1)[pix] - rv["depth"]) / np.maximum(1, np.abs(rv["depth"])))[ok].max(initial=0)
         print(f"view {b}: {len(pix)} px, ambiguous {rv['ambiguous'].sum()}, rgb {e_rgb:.2e} alpha {e_a:.2e} depth {e_d:.2e}")
+        worst = {"rgb": max(worst["rgb"], e_rgb), "alpha": max(worst["alpha"], e_a),
+                 "depth_rel": max(worst["depth_rel"], e_d)}
+        n_amb += int(rv["ambiguous"].sum())
+        n_pix += len(pix)
         assert e_rgb <= TOL_RGB and e_a <= TOL_ALPHA and e_d <= TOL_DEPTH_REL
-        assert rv["ambiguous"].mean() <= 0.02
+        assert rv["ambiguous"].mean() <= AMBIG_VIEW
+    record_property("pixels", n_pix)
+    record_property("ambiguous", n_amb)
+    record_property("max_err", {k: float(f"{v:.3g}") for k, v in worst.items()})
+    assert n_amb <= AMBIG_ALL * n_pix
     print("loss", g["loss"], ref["loss"], "excluded gaussians", ref["amb_gauss"].sum())
     assert abs(g["loss"] - ref["loss"]) <= 1e-4 * max(1.0, abs(ref["loss"]))
     for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
         ok, msg = grad_close(g["grads"][name], ref["grads"][name], ref["amb_gauss"])
         print(name, msg)
+        record_property(f"grad_{name}", msg)
         assert ok, (name, msg)
     ok, msg = grad_close(g["pose"], ref["pose"])
     print("pose", msg)
+    record_property("grad_pose", msg)
     assert ok, msg
 
 

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.render import composite_decisions, composite_eval, leaves, project, render
+from oracle.render import (composite_decisions, composite_eval, depth_key_uncertain, leaves, project,
+                           render)
 from oracle.settings import RenderSettings
 from paper_2510_26358_amd.scenes import tiny_scene
 from tests.oracle_helpers import camera, logit, scene
@@ -153,6 +154,46 @@ def test_two_gaussians_over_operator_in_depth_order():
     assert np.allclose(r["rgb"][0], expect, atol=1e-14)
     assert np.allclose(r["depth"], o_near * 2.0 + (1 - o_near) * o_far * 4.0, atol=1e-14)
     assert np.allclose(r["alpha"], o_near + (1 - o_near) * o_far, atol=1e-15)
+
+
+def test_equal_depths_composite_in_index_order_and_are_not_ambiguous():
+    """Two Gaussians at exactly the same depth are ordered by index (the depth key is the
+    float32 depth, ties broken by the Gaussian index), whatever their colours: swapping the
+    array order swaps which one is in front.  Every float64 evaluation of an exactly
+    representable depth rounds to the same key, so the pixel is not ambiguous."""
+    cam = camera(width=32, height=24, cx=16.5, cy=12.5)
+    red, blue = np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    for first, second in [(red, blue), (blue, red)]:
+        sc = scene([[0, 0, 3.0], [0, 0, 3.0]], logits=[logit(0.5), logit(0.4)], rgb=[first, second],
+                   cams=[cam], dtype=np.float32)
+        r = _render_pixels(sc, [16], [12])
+        assert not r["ambiguous"][0]
+        assert np.allclose(r["rgb"][0], 0.5 * first + 0.5 * 0.4 * second, atol=1e-7)
+
+
+def test_depth_on_a_float32_rounding_boundary_is_ambiguous():
+    """mu_z = 1 + 2^-23 (a float32) seen from t_z = 2 has depth 3 + 2^-23, the midpoint of
+    the float32 values 3 and 3 + 2^-22: its key depends on the last bit of the evaluation.
+    Next to a Gaussian at depth exactly 3 the order of the two can change, so the pixel is
+    flagged; next to one at 2.5 it cannot, and a depth one float32 step away is certain."""
+    z_mid = 3.0 + 2.0 ** -23
+    assert depth_key_uncertain([z_mid], [1e-15])[0]
+    assert not depth_key_uncertain([3.0], [1e-15])[0]
+    assert not depth_key_uncertain([3.0 + 2.0 ** -22], [1e-15])[0]
+    assert not depth_key_uncertain([z_mid + 1e-12], [1e-15])[0]
+    cam = camera(t=[0.0, 0.0, 2.0], width=32, height=24, cx=16.5, cy=12.5, dtype=np.float32)
+
+    def pixel(mu_first, mu_second):
+        sc = scene([[0, 0, mu_first], [0, 0, mu_second]], logits=[logit(0.5), logit(0.4)], cams=[cam],
+                   dtype=np.float32)
+        assert sc.means[0, 2] == np.float32(mu_first)
+        r = _render_pixels(sc, [16], [12])
+        assert r["count"][0] == 2
+        return bool(r["ambiguous"][0])
+
+    assert pixel(1.0 + 2.0 ** -23, 1.0)
+    assert not pixel(1.0 + 2.0 ** -23, 0.5)
+    assert not pixel(1.0 + 2.0 ** -22, 1.0)
 
 
 def test_transmittance_stop_excludes_the_crossing_gaussian():
