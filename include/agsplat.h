@@ -348,6 +348,25 @@ int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussian
                        ags_gaussians* out_m, ags_gaussians* out_v, int32_t* n_out_dev,
                        uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ags_lifecycle_step with its scratch
+ * (per-Gaussian output counts, first output slots and scan block sums) in a static device
+ * array of the library instead of the `ws` argument.  That array is AGS_LIFECYCLE_NOALLOC_BYTES
+ * (32 MiB + 64 KiB) on every GPU the library runs on, held until the process ends; its
+ * address is looked up in ags_ctx_create.  Allocates nothing and does not synchronise.
+ * in->n must be <= AGS_LIFECYCLE_NOALLOC_MAX_N (2^22) or the call returns
+ * AGS_ERR_WORKSPACE; other arguments and errors as ags_lifecycle_step, with the same results.
+ * All calls on one GPU share the array and nothing in it needs clearing (every call writes
+ * what it reads): calls that can overlap on one GPU (several streams or host threads) race
+ * and must be serialised by the caller. */
+#define AGS_LIFECYCLE_NOALLOC_MAX_N (1 << 22)
+#define AGS_LIFECYCLE_NOALLOC_BYTES ((32u << 20) + (64u << 10))
+int ags_lifecycle_step_noalloc(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in,
+                               const ags_gaussians* in_m, const ags_gaussians* in_v, const float* stat_grad,
+                               const float* stat_count, const float* split_noise, ags_gaussians* out,
+                               ags_gaussians* out_m, ags_gaussians* out_v, int32_t* n_out_dev,
+                               uint8_t* actions_dev, void* stream);
+
 /* ---- Voxel-hashed Gaussian map with a bounded GPU-resident set (Sec. III-B "Incremental
  * Gaussian Mapping": the voxel key equation; "Memory Management": least-recently-used
  * offload to host memory above a threshold tau, reload when a key is met again).

@@ -18,13 +18,14 @@ AGS_ERR_CAPACITY = -3
 AGS_ERR_HIP = -4
 AGS_ERR_NOT_SUPPORTED = -5
 AGS_MAX_VIEWS = 32
+LIFECYCLE_NOALLOC_MAX_N = 1 << 22
 
 EXPORTED = [
     "ags_version", "ags_error_string", "ags_last_hip_error", "ags_config_default",
     "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
     "ags_render_fwd", "ags_render_bwd", "ags_render_bwd_adam", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
-    "ags_lifecycle_step", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
+    "ags_lifecycle_step", "ags_lifecycle_step_noalloc", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
     "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
 ]
 
@@ -162,6 +163,8 @@ def load(path: str = LIB_PATH):
     lib.ags_lifecycle_workspace.argtypes = [C.c_int64, P(C.c_size_t)]
     lib.ags_lifecycle_step.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp,
                                        P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, C.c_size_t, vp]
+    lib.ags_lifecycle_step_noalloc.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp,
+                                               vp, P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp]
     for name in EXPORTED:
         if lib.ags_version and not hasattr(lib, name):
             raise ImportError(f"libagsplat.so lacks {name}")

@@ -24,6 +24,8 @@ static const char* kStageNames[ST_COUNT] = {"project_fwd", "binning",     "raste
 struct ags_ctx {
     int device;
     ags_config cfg;
+    void* static_scratch;      // device address of the lifecycle pass's static scratch
+    size_t static_scratch_bytes;
     int last_hip;
     bool prof;
     std::vector<ProfEvent> pending;
@@ -317,6 +319,11 @@ int ags_ctx_create(ags_ctx** out, int device, const ags_config* cfg) {
     c->cfg = *cfg;
     c->last_hip = 0;
     c->prof = false;
+    rc = lifecycle_static_scratch(device, &c->static_scratch, &c->static_scratch_bytes);
+    if (rc) {
+        delete c;
+        return rc;
+    }
     for (int k = 0; k < ST_COUNT; ++k) {
         c->total_ms[k] = 0.0;
         c->launches[k] = 0;
@@ -698,10 +705,12 @@ int ags_lifecycle_workspace(int64_t n, size_t* bytes) {
     return AGS_OK;
 }
 
-int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in, const ags_gaussians* in_m,
-                       const ags_gaussians* in_v, const float* stat_grad, const float* stat_count,
-                       const float* split_noise, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
-                       int32_t* n_out_dev, uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+int lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in, const ags_gaussians* in_m,
+                   const ags_gaussians* in_v, const float* stat_grad, const float* stat_count,
+                   const float* split_noise, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
+                   int32_t* n_out_dev, uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || !lp || !in || !in_m || !in_v || !out || !out_m || !out_v || !n_out_dev || !ws)
         return AGS_ERR_INVALID_ARG;
     if (check_gaussians(in) || check_gaussians(in_m) || check_gaussians(in_v) || check_gaussians(out) ||
@@ -766,6 +775,28 @@ int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussian
     Scope sc(ctx, ST_LIFECYCLE, s);
     launch_lifecycle(a, s);
     return hip_status(ctx);
+}
+
+}  // namespace
+
+int ags_lifecycle_step(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in, const ags_gaussians* in_m,
+                       const ags_gaussians* in_v, const float* stat_grad, const float* stat_count,
+                       const float* split_noise, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
+                       int32_t* n_out_dev, uint8_t* actions_dev, void* ws, size_t ws_bytes, void* stream) {
+    return lifecycle_step(ctx, lp, in, in_m, in_v, stat_grad, stat_count, split_noise, out, out_m, out_v, n_out_dev,
+                          actions_dev, ws, ws_bytes, stream);
+}
+
+int ags_lifecycle_step_noalloc(ags_ctx* ctx, const ags_lifecycle* lp, const ags_gaussians* in,
+                               const ags_gaussians* in_m, const ags_gaussians* in_v, const float* stat_grad,
+                               const float* stat_count, const float* split_noise, ags_gaussians* out,
+                               ags_gaussians* out_m, ags_gaussians* out_v, int32_t* n_out_dev,
+                               uint8_t* actions_dev, void* stream) {
+    if (!ctx || !in || !ctx->static_scratch) return AGS_ERR_INVALID_ARG;
+    if (in->n > AGS_LIFECYCLE_NOALLOC_MAX_N) return AGS_ERR_WORKSPACE;
+    // the static array's device address (never the host-side name of the array)
+    return lifecycle_step(ctx, lp, in, in_m, in_v, stat_grad, stat_count, split_noise, out, out_m, out_v, n_out_dev,
+                          actions_dev, ctx->static_scratch, ctx->static_scratch_bytes, stream);
 }
 
 int ags_check_finite(ags_ctx* ctx, const ags_gaussians* g, int32_t* n_bad_dev, void* stream) {

@@ -625,6 +625,9 @@ struct LifecycleArgs {
     ScanTemp scan_tmp;
 };
 void launch_lifecycle(const LifecycleArgs& a, hipStream_t s);
+// Device address and size of the lifecycle pass's static scratch array on `device` (looked
+// up on the first call for that device, with the device made current meanwhile).
+int lifecycle_static_scratch(int device, void** ptr, size_t* bytes);
 
 // Profiled stages (ags_profile_read reports their times under these indices).
 enum Stage {

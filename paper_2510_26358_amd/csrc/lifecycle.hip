@@ -10,9 +10,44 @@
 //    the moment arrays) loads the rows, then writes the Gaussian's outputs; split children get
 //    mu + R(q) diag(s) eps and log-scales - ln(split_scale), copies and children zero Adam
 //    moments, survivors keep theirs.
+#include <mutex>
+
 #include "common.h"
 
 namespace ags {
+
+namespace {
+
+// Scratch of ags_lifecycle_step_noalloc: a static device array, one copy on every GPU the
+// library runs on, alive until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address comes from hipGetSymbolAddress, looked up
+// once per device (lifecycle_static_scratch) and passed to the kernels like a workspace.
+constexpr size_t kStaticScratchBytes = (size_t)AGS_LIFECYCLE_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+}  // namespace
+
+int lifecycle_static_scratch(int device, void** ptr, size_t* bytes) {
+    if (device < 0 || device >= kMaxDevices || !ptr || !bytes) return AGS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return AGS_ERR_HIP;
+        if (cur != device && hipSetDevice(device) != hipSuccess) return AGS_ERR_HIP;
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return AGS_ERR_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = kStaticScratchBytes;
+    return AGS_OK;
+}
 
 enum { LC_KEEP = 0, LC_PRUNE = 1, LC_CLONE = 2, LC_SPLIT = 3 };
 
