@@ -27,11 +27,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd Mpixel/s, batched multi-view vs per-view loop, at oracle tolerance"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_PUBLISHED_TFLOPS = 157.3   # MI355X vector FP32 with packed (2-wide) FP32 instructions
+FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32 peak (packed, 2-wide FP32 instructions)
 # Attainable without packed FP32 (disabled for all device code in this build): a wave64
 # FP32 instruction occupies a 16-lane SIMD for 4 cycles, so 256 CU x 4 SIMD x 16 lanes x
-# 2 FLOP (FMA) x 2.4 GHz.
-FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s; reported beside the published peak.
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TRIALS = 5  # timing: median over this many trials of `steps` replays each
 # Algorithmic FLOP per (pixel, Gaussian) pair evaluated (scope table): forward ~20 + 1 exp,
 # backward ~60 + 1 exp; the exp is counted as one FLOP.
 FLOP_PER_PAIR = {"raster_fwd": 21, "raster_bwd": 61}
@@ -94,6 +95,8 @@ def calibrate(ras, p, cams, views, headroom=1.15):
 
 
 def time_steps(fn, steps, warmup):
+    """Seconds per step of exactly `steps` steps after `warmup` untimed ones, bracketed by a
+    device synchronisation on both sides (the headline timing)."""
     import torch
     for _ in range(warmup):
         fn()
@@ -103,6 +106,25 @@ def time_steps(fn, steps, warmup):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def time_trials(fn, steps, trials=TRIALS):
+    """The measurement rule of the throughput table: `trials` trials of `steps` replays, each
+    bracketed by HIP events on the current stream; the median trial's ms per step, and every
+    trial's (called after the warm-up of `time_steps`)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    per = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) / steps)
+    return {"rule": f"median of {trials} trials x {steps} replays (HIP events)",
+            "median_ms": round(float(np.median(per)), 4), "trials_ms": [round(x, 4) for x in per]}
 
 
 def measure_lifecycle(ras, p, cams, views, buf, out, grads, pose, tg, loss, args, t_b):
@@ -299,9 +321,10 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
     traffic = measured_traffic(name, workload, launch)
     if name in FLOP_PER_PAIR:
         achieved = evals * FLOP_PER_PAIR[name] / (ms_avg * 1e-3) / 1e12
-        rf = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_PEAK_TFLOPS, 2),
+        rf = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
               "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
-              "peak_published": FP32_PEAK_PUBLISHED_TFLOPS,
+              "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 2),
+              "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
               "work": f"{evals} (pixel, Gaussian) pairs x {FLOP_PER_PAIR[name]} FLOP"}
     else:
         # HBM-bound stages: algorithmic bytes per launch
@@ -348,7 +371,8 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
         if name in FLOP_PER_PAIR:
             a = evals * FLOP_PER_PAIR[name] / (ms * 1e-3) / 1e12
             out[name] = {"ms": ms, "bound": "alu", "achieved": round(a, 2), "unit": "TFLOP/s",
-                         "frac": round(a / FP32_PEAK_TFLOPS, 3)}
+                         "frac": round(a / FP32_PEAK_TFLOPS, 3),
+                         "frac_nonpacked": round(a / FP32_NONPACKED_TFLOPS, 3)}
         elif name in byts:
             a = byts[name] / (ms * 1e-3) / 1e9
             out[name] = {"ms": ms, "bound": "hbm", "achieved": round(a, 1), "unit": "GB/s",
@@ -360,28 +384,227 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
     return out
 
 
-def cpu_baseline(sc, sample_px=8192, seed=5):
-    """The FP64 oracle (unmodified) timed on the host: fwd + bwd of the same loss on a seeded
-    sample of view 0's pixels (L1 mask = the sample, LiDAR targets inside it)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def sample_pixels(sc, px_per_view, seed):
+    """Seeded pixel sample per view (sorted flat indices) and the scene restricted to it: the
+    L1 mask is the sample and only the LiDAR targets inside it are kept."""
+    rng = np.random.default_rng(seed)
+    samples = [np.sort(rng.choice(c.width * c.height, min(px_per_view, c.width * c.height), replace=False))
+               for c in sc.cameras]
+    sub = sc.copy()
+    sub.lidar = []
+    for lid, pix in zip(sc.lidar, samples):
+        keep = np.isin(lid["pix"], pix)
+        sub.lidar.append({k: np.asarray(v)[keep] for k, v in lid.items()})
+    return sub, samples
+
+
+def gpu_masked_step(ras, sub, samples, lam):
+    """The HIP path on the sampled objective in the rasteriser's current launch configuration:
+    forward outputs at the sample, loss, every gradient and the poses (generator inputs only)."""
+    import torch
+    from paper_2510_26358_amd.rasterizer import LossTargets, SplatParams, ViewSpec, cameras_tensor
+    views = ViewSpec.from_scene(sub)
+    p = SplatParams.from_scene(sub)
+    cams = cameras_tensor(sub.cameras)
+    out, buf = ras.render(p, cams, views)
+    tg = LossTargets.from_scene(sub, views, masks=samples, w_l1=1.0, lambda_lidar=lam)
+    grads = p.zeros_like()
+    pose = torch.zeros(views.n_views, 6, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+    torch.cuda.synchronize()
+    pb = views.pix_base
+    fwd = []
+    for b, pix in enumerate(samples):
+        rgb = out[0][3 * pb[b]:3 * pb[b + 1]].view(3, -1)[:, torch.from_numpy(pix).cuda()].T.cpu().numpy()
+        fwd.append({"rgb": rgb, "depth": out[1][pb[b]:pb[b + 1]][torch.from_numpy(pix).cuda()].cpu().numpy(),
+                    "alpha": out[2][pb[b]:pb[b + 1]][torch.from_numpy(pix).cuda()].cpu().numpy()})
+    names = ["means", "log_scales", "quats", "opacity_logits", "sh"]
+    res = {"loss": float(loss.item()), "grads": dict(zip(names, grads.to_numpy_aos())), "pose": pose.cpu().numpy(),
+           "fwd": fwd}
+    del out, buf, grads, p
+    return res
+
+
+def parity_report(gpu, ref, samples):
+    """Element-wise comparison at the stated tolerances (colour / alpha 1e-4, depth
+    1e-4 max(1, D), gradients 1e-3 relative per tensor, the same for the poses); pixels whose
+    result hinges on a decision rounding could flip (flagged by the oracle) and the Gaussians
+    they touch are set aside and counted."""
+    worst = {"rgb": 0.0, "alpha": 0.0, "depth_rel": 0.0}
+    n_amb = 0
+    for g, r, pix in zip(gpu["fwd"], ref["views"], samples):
+        idx = np.searchsorted(r["pix"], pix)
+        ok = ~r["ambiguous"][idx]
+        n_amb += int((~ok).sum())
+        worst["rgb"] = max(worst["rgb"], float(np.abs(g["rgb"] - r["rgb"][idx])[ok].max(initial=0)))
+        worst["alpha"] = max(worst["alpha"], float(np.abs(g["alpha"] - r["alpha"][idx])[ok].max(initial=0)))
+        worst["depth_rel"] = max(worst["depth_rel"], float(
+            (np.abs(g["depth"] - r["depth"][idx]) / np.maximum(1.0, np.abs(r["depth"][idx])))[ok].max(initial=0)))
+    keep = ~ref["amb_gauss"]
+    gn = {}
+    for name, g in gpu["grads"].items():
+        rr = np.asarray(ref["grads"][name], np.float64)[keep]
+        d = np.asarray(g, np.float64)[keep] - rr
+        gn[name] = float(np.linalg.norm(d) / max(np.linalg.norm(rr), 1e-30))
+    pose_rel = float(np.linalg.norm(gpu["pose"] - ref["pose"]) / max(np.linalg.norm(ref["pose"]), 1e-30))
+    loss_rel = abs(gpu["loss"] - ref["loss"]) / max(1.0, abs(ref["loss"]))
+    n_px = int(sum(len(x) for x in samples))
+    ok = (worst["rgb"] <= 1e-4 and worst["alpha"] <= 1e-4 and worst["depth_rel"] <= 1e-4 and loss_rel <= 1e-4
+          and all(v <= 1e-3 for v in gn.values()) and pose_rel <= 1e-3 and n_amb <= 0.005 * n_px)
+    return {"pass": bool(ok), "pixels": n_px, "ambiguous": n_amb,
+            "excluded_gaussians": int(ref["amb_gauss"].sum()),
+            "max_rgb": float(f"{worst['rgb']:.3g}"), "max_alpha": float(f"{worst['alpha']:.3g}"),
+            "max_depth_rel": float(f"{worst['depth_rel']:.3g}"), "loss_rel": float(f"{loss_rel:.3g}"),
+            "grad_norm_rel": {k: float(f"{v:.3g}") for k, v in gn.items()}, "pose_rel": float(f"{pose_rel:.3g}")}
+
+
+def oracle_leg(sc, ras, px_per_view, seed=5, lam=1.0, single_thread_px=0):
+    """Parity of the HIP path in its timed launch configuration against the FP64 oracle on a
+    seeded pixel sample of every view, and the oracle's own time for that sample (all host
+    threads), plus, if asked, the oracle on one thread over a smaller sample of view 0."""
     import torch
     from oracle.render import loss_and_grads
     from oracle.settings import RenderSettings
-    rng = np.random.default_rng(seed)
-    cam = sc.cameras[0]
-    pix = np.sort(rng.choice(cam.width * cam.height, sample_px, replace=False))
-    sub = sc.copy()
-    sub.cameras = [sub.cameras[0]]
-    sub.gt_rgb = [sub.gt_rgb[0]] if sub.gt_rgb else [np.zeros((3, cam.height, cam.width), np.float32)]
-    lid = sc.lidar[0] if sc.lidar else {"pix": np.zeros(0, np.int32)}
-    keep = np.isin(lid["pix"], pix)
-    sub.lidar = [{k: np.asarray(v)[keep] for k, v in lid.items()}]
+    sub, samples = sample_pixels(sc, px_per_view, seed)
+    gpu = gpu_masked_step(ras, sub, samples, lam)
+    threads = torch.get_num_threads()
     t0 = time.perf_counter()
-    loss_and_grads(sub, RenderSettings(), masks=[pix])
+    ref = loss_and_grads(sub, RenderSettings(), masks=samples, lam=lam)
     dt = time.perf_counter() - t0
-    return {"value": round(sample_px / dt / 1e6, 8), "unit": "Mpixel/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{sample_px} seeded pixels of view 0 (L1 + LiDAR inside the sample), fwd+bwd over all "
-                      f"{sc.n} Gaussians, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+    parity = parity_report(gpu, ref, samples)
+    n_px = parity["pixels"]
+    cpu = {"value": round(n_px / dt / 1e6, 8), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_px} seeded pixels over the {len(sc.cameras)} views (L1 on the sample, LiDAR targets "
+                     f"inside it), fwd+bwd over all {sc.n} Gaussians, {dt:.1f} s",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if single_thread_px:
+        one, samples1 = sample_pixels(sc, single_thread_px, seed + 1)
+        one.cameras, one.lidar, one.gt_rgb = one.cameras[:1], one.lidar[:1], one.gt_rgb[:1]
+        torch.set_num_threads(1)
+        try:
+            t1 = time.perf_counter()
+            loss_and_grads(one, RenderSettings(), masks=samples1[:1], lam=lam)
+            d1 = time.perf_counter() - t1
+        finally:
+            torch.set_num_threads(threads)
+        cpu["single_thread"] = {"value": round(len(samples1[0]) / d1 / 1e6, 8), "cores": 1,
+                                "sample": f"{len(samples1[0])} seeded pixels of view 0, {d1:.1f} s"}
+    return parity, cpu
+
+
+def per_view_loop(ras, p, cams, views, tg, grads, loss, steps, warmup):
+    """The comparator: the same kernels launched once per view in a host loop (each view its
+    own projection, binning and sorts; gradients accumulated across views; eager launches)."""
+    import torch
+    from paper_2510_26358_amd.rasterizer import LossTargets
+    per = []
+    pb = views.pix_base
+    for b in range(views.n_views):
+        vb = views.subset(b)
+        cb = cams[b:b + 1].contiguous()
+        capb, _, _ = calibrate(ras, p, cb, vb)
+        bb = ras.buffers(vb, p.n, p.sh_degree, capb)
+        ob = ras.outputs(vb)
+        o0, o1 = tg.depth_offsets[b], tg.depth_offsets[b + 1]
+        tgb = LossTargets(tg.gt_rgb[3 * pb[b]:3 * pb[b + 1]], None, [tg.l1_count[b]], tg.depth_pix[o0:o1],
+                          tg.depth_val[o0:o1], tg.depth_sigma[o0:o1], [0, o1 - o0], tg.w_l1, tg.lambda_lidar)
+        per.append((vb, cb, bb, ob, tgb, torch.zeros(1, 6, device="cuda")))
+
+    def loop_step():
+        for b, (vb, cb, bb, ob, tgb, pz) in enumerate(per):
+            ras.forward_into(p, cb, vb, bb, ob)
+            ras.backward_into(p, cb, vb, bb, ob, grads, pz, loss=tgb, loss_out=loss, accumulate=b > 0)
+
+    t = time_steps(loop_step, steps, warmup)
+    tr = time_trials(loop_step, steps)
+    del per
+    return t, tr
+
+
+def capture(step, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    return g
+
+
+def measure_workload(name, args, loop=True, px_per_view=0):
+    """A further workload of the configuration table as a sub-record of the bench line: its
+    own autotuned launch shapes, the graph-captured batched step (for `refine` the whole
+    refinement step: forward, backward with Adam fused in, pose update), the per-view loop
+    where asked, and oracle parity on a seeded pixel sample in the timed configuration."""
+    import torch
+    from paper_2510_26358_amd.rasterizer import Rasterizer
+    from paper_2510_26358_amd.tune import tune
+    t0 = time.perf_counter()
+    sc = make_workload(name)
+    ras = Rasterizer(0)
+    p, cams, views, tg = setup(sc, ras)
+    tuned = tune(ras, p, cams, views, tg, use_cache=False)
+    cap, K, V = calibrate(ras, p, cams, views)
+    P = views.n_pixels
+    rec = {"workload": sc.name, "n_gaussians": sc.n, "views": views.n_views, "pixels": P,
+           "resolution": sorted({f"{w}x{h}" for w, h in zip(views.widths, views.heights)}),
+           "launch": tuned["best"], "visible_pairs": V, "intersections": K}
+    grads = p.zeros_like()
+    pose = torch.zeros(views.n_views, 6, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    if name == "refine":
+        from paper_2510_26358_amd.refine import Refiner
+        # parity first: the refinement step updates the parameters in place
+        if px_per_view:
+            rec["parity"], _ = oracle_leg(sc, ras, px_per_view, seed=6)
+        refiner = Refiner(ras, p, cams, views, tg, capacity=cap)
+        step = refiner.step
+        rec["step"] = "forward + fused-loss backward with Adam fused in + pose Adam and retraction (graph)"
+    else:
+        buf = ras.buffers(views, p.n, p.sh_degree, cap)
+        out = ras.outputs(views)
+
+        def step():
+            ras.forward_into(p, cams, views, buf, out)
+            ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+        rec["step"] = "forward + fused-loss backward (graph)"
+    g = capture(step, args.warmup)
+    t = time_steps(g.replay, args.steps, args.warmup)
+    rec["ms_per_step"] = round(t * 1e3, 4)
+    rec["value"] = round(P / t / 1e6, 2)
+    rec["timing_rule"] = time_trials(g.replay, args.steps)
+    if name == "refine":
+        assert refiner.check_capacity(), "capacity overflow during timing"
+    if loop and views.n_views > 1 and name != "refine":
+        t_l, tr_l = per_view_loop(ras, p, cams, views, tg, grads, loss, args.steps, args.warmup)
+        rec["per_view_loop"] = {"value": round(P / t_l / 1e6, 2), "ms_per_step": round(t_l * 1e3, 4),
+                                "speedup_batched": round(t_l / t, 3),
+                                "speedup_batched_median": round(tr_l["median_ms"] / rec["timing_rule"]["median_ms"], 3),
+                                "timing_rule": tr_l}
+    if px_per_view and name != "refine":
+        rec["parity"], _ = oracle_leg(sc, ras, px_per_view, seed=6)
+    rec["wall_s"] = round(time.perf_counter() - t0, 1)
+    log(f"[bench] {sc.name}: {rec['ms_per_step']} ms/step, {rec['value']} Mpixel/s "
+        f"{'(loop speedup ' + str(rec['per_view_loop']['speedup_batched']) + 'x) ' if 'per_view_loop' in rec else ''}"
+        f"parity {rec.get('parity', {}).get('pass')}")
+    del g, p, grads, sc
+    if name != "refine":
+        del buf, out
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main():
@@ -396,7 +619,9 @@ def main():
     ap.add_argument("--batch-bwd", type=int, default=0)
     ap.add_argument("--ppt-bwd", type=int, default=0)
     ap.add_argument("--no-loop", action="store_true", help="skip the per-view loop comparator")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (parity + CPU baseline)")
+    ap.add_argument("--oracle-px", type=int, default=2048,
+                    help="seeded pixels per view of the oracle leg (parity and CPU baseline)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
     ap.add_argument("--ssim", type=float, default=0.2,
@@ -409,6 +634,8 @@ def main():
                          "pass (prune / split / duplicate / reset) over the Gaussians (0: skip)")
     ap.add_argument("--voxel-map", type=int, default=1,
                     help="also time voxel-map insertion calls (2^20 points each, resident bound 2^20; 0: skip)")
+    ap.add_argument("--sub-workloads", default="submaps,refine",
+                    help="further workloads reported as sub-records of the line (comma list; '' for none)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -469,21 +696,17 @@ def main():
         log(f"[bench] batched (eager launches): {t_eager * 1e3:.3f} ms/step")
     timed = step
     if not args.no_graph:
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        timed = graph.replay
+        timed = capture(step, args.warmup).replay
     t_b = time_steps(timed, args.steps, args.warmup)
+    rule = time_trials(timed, args.steps)
     P = views.n_pixels
     mpx = P / t_b / 1e6
     lval = (refiner.loss if refiner is not None else loss).item()
     log(f"[bench] batched{' (graph)' if not args.no_graph else ''}: {t_b * 1e3:.3f} ms/step, {mpx:.1f} Mpixel/s, "
-        f"loss {lval:.5f}")
+        f"loss {lval:.5f}; {rule}")
     over_buf = refiner.buf if refiner is not None else buf
     assert over_buf.counters()[2] == 0, "capacity overflow during timing"
+    n_listed = over_buf.n_listed()
 
     # per-stage times over a second timed pass with events enabled
     roof, info = None, None
@@ -506,21 +729,13 @@ def main():
                                          over_buf.sizes.n_pairs, info["V"], info["K"],
                                          int(tg.depth_pix.numel()), t_b * 1e3,
                                          fused_adam=refiner is not None and refiner.fused_adam)
+        roof["step_hbm_frac"] = info["stages"]["step"]["frac"]
 
     # the same step with the D-SSIM part of the photometric loss switched on
     with_ssim = None
     if args.ssim > 0 and refiner is None:
         tg.ssim_weight = args.ssim
-        if not args.no_graph:
-            for _ in range(args.warmup):
-                step()
-            torch.cuda.synchronize()
-            graph_s = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph_s):
-                step()
-            timed_s = graph_s.replay
-        else:
-            timed_s = step
+        timed_s = capture(step, args.warmup).replay if not args.no_graph else step
         t_s = time_steps(timed_s, args.steps, args.warmup)
         with_ssim = {"ssim_weight": args.ssim, "ms_per_step": round(t_s * 1e3, 4),
                      "value": round(P / t_s / 1e6, 2), "loss": round(loss.item(), 6)}
@@ -537,11 +752,11 @@ def main():
                 achieved = SSIM_FLOP_PER_PIXEL_CHANNEL * 3 * P / (ms * 1e-3) / 1e12
                 with_ssim["ssim_stage_ms"] = round(ms, 4)
                 with_ssim["ssim_roofline"] = {
-                    "bound": "alu", "achieved": round(achieved, 3), "peak": round(FP32_PEAK_TFLOPS, 2),
+                    "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "frac_nonpacked": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                     "work": f"{3 * P} pixel-channels x {SSIM_FLOP_PER_PIXEL_CHANNEL} FLOP"}
-        log(f"[bench] with D-SSIM (weight {args.ssim}): {t_s * 1e3:.3f} ms/step, {P / t_s / 1e6:.1f} Mpixel/s, "
-            f"{with_ssim}")
+        log(f"[bench] with D-SSIM (weight {args.ssim}): {t_s * 1e3:.3f} ms/step, {P / t_s / 1e6:.1f} Mpixel/s")
         tg.ssim_weight = 0.0
 
     # the same step with the rendered-variance reading of the LiDAR term
@@ -554,15 +769,7 @@ def main():
             ras.forward_into(p, cams, views, buf, out_v)
             ras.backward_into(p, cams, views, buf, out_v, grads, pose, loss=tg, loss_out=loss)
 
-        timed_v = step_v
-        if not args.no_graph:
-            for _ in range(args.warmup):
-                step_v()
-            torch.cuda.synchronize()
-            graph_v = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph_v):
-                step_v()
-            timed_v = graph_v.replay
+        timed_v = capture(step_v, args.warmup).replay if not args.no_graph else step_v
         t_v = time_steps(timed_v, args.steps, args.warmup)
         with_rv = {"sigma_floor": args.rendered_variance, "ms_per_step": round(t_v * 1e3, 4),
                    "value": round(P / t_v / 1e6, 2), "loss": round(loss.item(), 6)}
@@ -580,45 +787,36 @@ def main():
 
     loop = None
     if not args.no_loop and views.n_views > 1 and refiner is None:
-        from paper_2510_26358_amd.rasterizer import LossTargets
-        per = []
-        for b in range(views.n_views):
-            vb = views.subset(b)
-            cb = cams[b:b + 1].contiguous()
-            capb, _, _ = calibrate(ras, p, cb, vb)
-            bb = ras.buffers(vb, p.n, p.sh_degree, capb)
-            ob = ras.outputs(vb)
-            pb = views.pix_base
-            tgb = LossTargets(tg.gt_rgb[3 * pb[b]:3 * pb[b + 1]], None, [tg.l1_count[b]],
-                              tg.depth_pix[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
-                              tg.depth_val[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
-                              tg.depth_sigma[tg.depth_offsets[b]:tg.depth_offsets[b + 1]],
-                              [0, tg.depth_offsets[b + 1] - tg.depth_offsets[b]], tg.w_l1, tg.lambda_lidar)
-            per.append((vb, cb, bb, ob, tgb, torch.zeros(1, 6, device="cuda")))
-
-        def loop_step():
-            for b, (vb, cb, bb, ob, tgb, pz) in enumerate(per):
-                ras.forward_into(p, cb, vb, bb, ob)
-                ras.backward_into(p, cb, vb, bb, ob, grads, pz, loss=tgb, loss_out=loss, accumulate=b > 0)
-
-        t_l = time_steps(loop_step, args.steps, args.warmup)
+        t_l, tr_l = per_view_loop(ras, p, cams, views, tg, grads, loss, args.steps, args.warmup)
         loop = {"value": round(P / t_l / 1e6, 2), "ms_per_step": round(t_l * 1e3, 4),
                 "speedup_batched": round(t_l / t_b, 3),
-                "speedup_batched_eager": round(t_l / t_eager, 3) if t_eager else None}
+                "speedup_batched_eager": round(t_l / t_eager, 3) if t_eager else None,
+                "speedup_batched_median": round(tr_l["median_ms"] / rule["median_ms"], 3),
+                "timing_rule": tr_l}
         log(f"[bench] per-view loop: {t_l * 1e3:.3f} ms/step, {P / t_l / 1e6:.1f} Mpixel/s "
             f"(batched speedup {t_l / t_b:.2f}x)")
 
-    cpu = None
+    parity, cpu = None, None
     if not args.no_cpu:
-        log("[bench] timing the FP64 oracle on a pixel sample (host CPU)...")
-        cpu = cpu_baseline(sc)
+        log("[bench] oracle leg: parity of the timed configuration on a seeded sample, and the FP64 oracle's "
+            "time on the host...")
+        parity, cpu = oracle_leg(sc, ras, args.oracle_px, single_thread_px=512)
+        log(f"[bench] parity {parity}")
         log(f"[bench] cpu oracle: {cpu}")
+
+    del buf, out, grads, refiner, over_buf, timed, step
+    torch.cuda.empty_cache()
+    subs = {}
+    for name in [w for w in args.sub_workloads.split(",") if w and w != args.workload]:
+        subs[name] = measure_workload(name, args, loop=not args.no_loop,
+                                      px_per_view=0 if args.no_cpu else (256 if name == "submaps" else 1024))
 
     rec = {
         "metric": METRIC, "value": round(mpx, 2), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "timing": "HIP graph replay" if not args.no_graph else "eager launches",
+        "timing_rule": rule,
         "ms_per_step_eager": round(t_eager * 1e3, 4) if t_eager else None,
         "data": "synthetic",
         "config": {"workload": sc.name, "n_gaussians": sc.n, "views": views.n_views,
@@ -627,8 +825,9 @@ def main():
                    "tile": tile, "lds_batch": batch, "px_per_thread": ppt, "lds_batch_bwd": batch_b,
                    "px_per_thread_bwd": ppt_b,
                    "autotuned": None if tuned is None else tuned["ms"],
-                   "visible_pairs": V, "intersections": K, "tile_list_entries": over_buf.n_listed()},
-        "per_view_loop": loop, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
+                   "visible_pairs": V, "intersections": K, "tile_list_entries": n_listed},
+        "per_view_loop": loop, "parity": parity, "roofline": roof, "dominant": info, "cpu_baseline": cpu,
+        "workloads": subs,
         "with_ssim": with_ssim, "with_rendered_variance": with_rv, "lifecycle": lifecycle,
         "voxel_map": vmap,
     }

@@ -168,7 +168,10 @@ typedef struct ags_loss {
     const float* gt_rgb;          /* device, rgb layout */
     const uint8_t* mask;          /* device [P] (1 = pixel enters the L1 term) or NULL */
     const int64_t* l1_count;      /* host [n_views]; required when mask != NULL */
-    const int32_t* depth_pix;     /* device [n_targets]: pixel index y * W + x in its view */
+    const int32_t* depth_pix;     /* device [n_targets]: pixel index y * W + x in its view, in
+                                     [0, W_b H_b).  The call cannot read device data to refuse a
+                                     target outside its view: such a target gets no adjoint and
+                                     makes the loss (loss_out) NaN, so it cannot pass unnoticed */
     const float* depth_val;       /* device [n_targets]: LiDAR depth D_j (camera z) */
     const float* depth_sigma;     /* device [n_targets]: s_j > 0 */
     const int64_t* depth_offsets; /* host [n_views + 1]: targets of view b are
@@ -293,6 +296,32 @@ int ags_render_bwd_adam(ags_ctx* ctx, const ags_views* views, ags_gaussians* par
 int ags_pose_step(ags_ctx* ctx, const ags_adam* hp, ags_camera* cams, int32_t n_views,
                   const float* pose_grad, float* pose_m, float* pose_v, int32_t* step,
                   int32_t advance_step, void* stream);
+
+/* Autotuner for the raster launch shapes (tiling is "standard 3DGS" in Sec. III-B; the paper
+ * names no tile size or batch).  For every tile size in {8, 16, 32} and every (LDS batch,
+ * pixels per thread) shape compiled for it (the list under ags_config), times `steps`
+ * forward + fused-loss backward steps of this workload (views, g, cams, loss as for
+ * ags_render_fwd / ags_render_bwd), after `warmup` untimed ones, on `stream` with HIP events
+ * per stage.  Per tile size it takes the forward shape with the fastest raster forward and
+ * the backward shape with the fastest raster backward, predicts the step as the rest of the
+ * first shape's step plus those two, and picks the tile size with the fastest prediction.
+ * The pick (other fields from the context's configuration) is written to *best and set on
+ * the context; *predicted_step_ms (nullable) receives its predicted step time.  report
+ * (nullable unless n_report_max > 0) receives up to n_report_max per-shape timings and
+ * *n_report (nullable) the number of shapes timed.  Off the hot path: it allocates its trial
+ * buffers (device memory for outputs, gradients and the saved state at each tile size's
+ * intersection capacity, freed before it returns) and synchronises with the host; g is only
+ * read.  The caller's profile totals are kept.  Errors: INVALID_ARG, CAPACITY (more than
+ * 2^31 intersections), HIP (allocation or launch; the context keeps its configuration). */
+typedef struct ags_tune_entry {
+    int32_t tile, batch, px_per_thread;
+    float step_ms, raster_fwd_ms, raster_bwd_ms;
+    int64_t intersections;  /* K at this tile size */
+} ags_tune_entry;
+
+int ags_tune(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const ags_camera* cams,
+             const ags_loss* loss, int32_t steps, int32_t warmup, ags_config* best, float* predicted_step_ms,
+             ags_tune_entry* report, int32_t n_report_max, int32_t* n_report, void* stream);
 
 /* Debug aid, off the hot path: the number of non-finite values (NaN, +-inf) among all of
  * g's parameters, written to *n_bad_dev (device int32).  Enqueued on the stream, no host

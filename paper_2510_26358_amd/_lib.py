@@ -25,7 +25,7 @@ EXPORTED = [
     "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
     "ags_render_fwd", "ags_render_bwd", "ags_render_bwd_adam", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
-    "ags_lifecycle_step", "ags_lifecycle_step_noalloc", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
+    "ags_lifecycle_step", "ags_lifecycle_step_noalloc", "ags_tune", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
     "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
 ]
 
@@ -70,6 +70,12 @@ class Lifecycle(C.Structure):
                 ("tau_opa", C.c_float), ("s_min", C.c_float), ("s_max", C.c_float),
                 ("grad_threshold", C.c_float), ("kappa", C.c_float), ("s_init", C.c_float),
                 ("tau_reset", C.c_float), ("split_scale", C.c_float)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("batch", C.c_int32), ("px_per_thread", C.c_int32),
+                ("step_ms", C.c_float), ("raster_fwd_ms", C.c_float), ("raster_bwd_ms", C.c_float),
+                ("intersections", C.c_int64)]
 
 
 class FwdOut(C.Structure):
@@ -165,6 +171,8 @@ def load(path: str = LIB_PATH):
                                        P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, C.c_size_t, vp]
     lib.ags_lifecycle_step_noalloc.argtypes = [vp, P(Lifecycle), P(Gaussians), P(Gaussians), P(Gaussians), vp, vp,
                                                vp, P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp]
+    lib.ags_tune.argtypes = [vp, P(Views), P(Gaussians), vp, P(Loss), C.c_int32, C.c_int32, P(Config),
+                             P(C.c_float), P(TuneEntry), C.c_int32, P(C.c_int32), vp]
     for name in EXPORTED:
         if lib.ags_version and not hasattr(lib, name):
             raise ImportError(f"libagsplat.so lacks {name}")

@@ -872,4 +872,242 @@ int ags_profile_reset(ags_ctx* ctx) {
     return rc;
 }
 
+extern "C++" {
+namespace {
+
+// Device buffers of one tuning trial (freed when the trial set ends).
+struct TrialBuffers {
+    std::vector<void*> ptrs;
+    ~TrialBuffers() { release(); }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+    template <typename T>
+    T* get(size_t count) {
+        void* p = nullptr;
+        if (hipMalloc(&p, (count > 0 ? count : 1) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return static_cast<T*>(p);
+    }
+};
+
+// Buffers of every trial at one tile size (capacity fixed for that tile size).
+struct TileTrial {
+    TrialBuffers mem;
+    size_t ws_bytes = 0;
+    void *saved = nullptr, *fwd_ws = nullptr, *bwd_ws = nullptr;
+    ags_fwd_out out{};
+    ags_grads gr{};
+    float* loss = nullptr;
+    int64_t cap = 0;
+
+    int alloc(const Layout& L, const ags_gaussians* g, int n_views) {
+        mem.release();
+        cap = L.cap;
+        saved = mem.get<char>(L.s_total);
+        fwd_ws = mem.get<char>(L.f_total);
+        bwd_ws = mem.get<char>(L.b_total);
+        const size_t P = (size_t)L.P, n = (size_t)g->n, k3 = 3 * (size_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+        out.rgb = mem.get<float>(3 * P);
+        out.depth = mem.get<float>(P);
+        out.alpha = mem.get<float>(P);
+        out.depth_var = nullptr;
+        gr.means = mem.get<float>(3 * n);
+        gr.log_scales = mem.get<float>(3 * n);
+        gr.quats = mem.get<float>(4 * n);
+        gr.opacity_logits = mem.get<float>(n);
+        gr.sh = mem.get<float>(k3 * n);
+        gr.pose = mem.get<float>(6 * (size_t)n_views);
+        gr.accumulate = 0;
+        gr.stat_grad = gr.stat_count = nullptr;
+        loss = mem.get<float>(1);
+        if (!saved || !fwd_ws || !bwd_ws || !out.rgb || !out.depth || !out.alpha || !gr.means || !gr.log_scales ||
+            !gr.quats || !gr.opacity_logits || !gr.sh || !gr.pose || !loss)
+            return AGS_ERR_HIP;
+        return AGS_OK;
+    }
+};
+
+}  // namespace
+}  // extern "C++"
+
+int ags_tune(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const ags_camera* cams,
+             const ags_loss* loss, int32_t steps, int32_t warmup, ags_config* best, float* predicted_step_ms,
+             ags_tune_entry* report, int32_t n_report_max, int32_t* n_report, void* stream) {
+    if (!ctx || !views || !g || !cams || !loss || !best || steps < 1 || warmup < 0) return AGS_ERR_INVALID_ARG;
+    if (n_report_max > 0 && !report) return AGS_ERR_INVALID_ARG;
+    int rc = check_gaussians(g);
+    if (rc) return rc;
+    Layout L0;
+    rc = build_layout(&ctx->cfg, views, g->n, 0, L0);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+
+    int sh_tile[32], sh_ppt[32], sh_batch[32];
+    const int n_shapes = raster_shapes(sh_tile, sh_ppt, sh_batch, 32);
+    const ags_config base = ctx->cfg;
+    // the caller's profile totals are set aside while the tuner uses the context's timers
+    rc = drain(ctx);
+    if (rc) return rc;
+    const bool prof_was = ctx->prof;
+    double saved_ms[ST_COUNT];
+    long long saved_launches[ST_COUNT];
+    for (int k = 0; k < ST_COUNT; ++k) {
+        saved_ms[k] = ctx->total_ms[k];
+        saved_launches[k] = ctx->launches[k];
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int n_rep = 0;
+    ags_config pick = base;
+    double pick_total = 1e300;
+    bool found = false;
+    rc = AGS_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = AGS_ERR_HIP;
+    const int tiles[3] = {8, 16, 32};
+    for (int ti = 0; ti < 3 && rc == AGS_OK; ++ti) {
+        const int T = tiles[ti];
+        int first = -1;
+        for (int k = 0; k < n_shapes; ++k)
+            if (sh_tile[k] == T) {
+                first = k;
+                break;
+            }
+        if (first < 0) continue;
+        ags_config cfg = base;
+        cfg.tile = T;
+        cfg.batch = sh_batch[first];
+        cfg.px_per_thread = sh_ppt[first];
+        cfg.batch_bwd = cfg.px_per_thread_bwd = 0;
+        ctx->cfg = cfg;
+        ctx->prof = false;
+        // intersection capacity of this tile size: grow until the forward fits, then 15 % headroom
+        TileTrial tr;
+        int64_t cap = L0.P / 2 > (1 << 16) ? L0.P / 2 : (1 << 16);
+        int64_t K = 0;
+        for (int attempt = 0; attempt < 4 && rc == AGS_OK; ++attempt) {
+            Layout L;
+            rc = build_layout(&ctx->cfg, views, g->n, cap, L);
+            if (rc) break;
+            rc = tr.alloc(L, g, views->n_views);
+            if (rc) break;
+            rc = ags_render_fwd(ctx, views, g, cams, cap, &tr.out, tr.saved, tr.fwd_ws, L.f_total, stream);
+            if (rc) break;
+            uint32_t cnt[3] = {0, 0, 0};
+            if (hipMemcpyAsync(cnt, at<char>(tr.saved, L.s_counters), sizeof(cnt), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = hip_status(ctx);
+                break;
+            }
+            K = cnt[CNT_K];
+            const int64_t want = (int64_t)((double)K * 1.15) + 4096;
+            if (!cnt[CNT_OVERFLOW] && cap >= want) break;
+            if (want > 0x7fffffffLL) {
+                rc = AGS_ERR_CAPACITY;
+                break;
+            }
+            cap = want;
+        }
+        if (rc) break;
+        Layout L;
+        rc = build_layout(&ctx->cfg, views, g->n, cap, L);
+        if (rc) break;
+        double t_first = 0.0, f_first = 0.0, b_first = 0.0;
+        double best_f = 1e300, best_b = 1e300;
+        int bf = first, bb = first;
+        for (int k = 0; k < n_shapes && rc == AGS_OK; ++k) {
+            if (sh_tile[k] != T) continue;
+            ctx->cfg.batch = sh_batch[k];
+            ctx->cfg.px_per_thread = sh_ppt[k];
+            ctx->cfg.batch_bwd = ctx->cfg.px_per_thread_bwd = 0;
+            ctx->prof = false;
+            for (int w = 0; w < warmup && rc == AGS_OK; ++w) {
+                rc = ags_render_fwd(ctx, views, g, cams, cap, &tr.out, tr.saved, tr.fwd_ws, L.f_total, stream);
+                if (!rc)
+                    rc = ags_render_bwd(ctx, views, g, cams, cap, &tr.out, tr.saved, nullptr, loss, &tr.gr, tr.loss,
+                                        tr.bwd_ws, L.b_total, stream);
+            }
+            if (rc) break;
+            for (int st = 0; st < ST_COUNT; ++st) {
+                ctx->total_ms[st] = 0.0;
+                ctx->launches[st] = 0;
+            }
+            ctx->prof = true;
+            if (hipEventRecord(e0, s) != hipSuccess) rc = hip_status(ctx);
+            for (int it = 0; it < steps && rc == AGS_OK; ++it) {
+                rc = ags_render_fwd(ctx, views, g, cams, cap, &tr.out, tr.saved, tr.fwd_ws, L.f_total, stream);
+                if (!rc)
+                    rc = ags_render_bwd(ctx, views, g, cams, cap, &tr.out, tr.saved, nullptr, loss, &tr.gr, tr.loss,
+                                        tr.bwd_ws, L.b_total, stream);
+            }
+            if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = hip_status(ctx);
+            if (!rc) rc = drain(ctx);
+            ctx->prof = false;
+            if (rc) break;
+            float wall = 0.f;
+            (void)hipEventElapsedTime(&wall, e0, e1);
+            const double step_ms = wall / steps;
+            const double f_ms = ctx->total_ms[ST_RASTER_FWD] / steps;
+            const double b_ms = ctx->total_ms[ST_RASTER_BWD] / steps;
+            if (n_rep < n_report_max) {
+                ags_tune_entry& e = report[n_rep];
+                e.tile = T;
+                e.batch = sh_batch[k];
+                e.px_per_thread = sh_ppt[k];
+                e.step_ms = (float)step_ms;
+                e.raster_fwd_ms = (float)f_ms;
+                e.raster_bwd_ms = (float)b_ms;
+                e.intersections = K;
+            }
+            ++n_rep;
+            if (k == first) {
+                t_first = step_ms;
+                f_first = f_ms;
+                b_first = b_ms;
+            }
+            if (f_ms < best_f) {
+                best_f = f_ms;
+                bf = k;
+            }
+            if (b_ms < best_b) {
+                best_b = b_ms;
+                bb = k;
+            }
+        }
+        if (rc) break;
+        // the rest of the first shape's step, plus the fastest forward and backward shapes
+        const double total = (t_first - f_first - b_first) + best_f + best_b;
+        if (total < pick_total) {
+            pick_total = total;
+            pick = base;
+            pick.tile = T;
+            pick.batch = sh_batch[bf];
+            pick.px_per_thread = sh_ppt[bf];
+            pick.batch_bwd = sh_batch[bb];
+            pick.px_per_thread_bwd = sh_ppt[bb];
+            found = true;
+        }
+    }
+    // tear down: the caller's profile totals and setting return, the pick is applied
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (int k = 0; k < ST_COUNT; ++k) {
+        ctx->total_ms[k] = saved_ms[k];
+        ctx->launches[k] = saved_launches[k];
+    }
+    ctx->prof = prof_was;
+    if (rc || !found) {
+        ctx->cfg = base;
+        return rc ? rc : AGS_ERR_NOT_SUPPORTED;
+    }
+    ctx->cfg = pick;
+    *best = pick;
+    if (predicted_step_ms) *predicted_step_ms = (float)pick_total;
+    if (n_report) *n_report = n_rep;
+    return AGS_OK;
+}
+
 }  // extern "C"

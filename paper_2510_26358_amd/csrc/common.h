@@ -492,6 +492,9 @@ struct RasterArgs {
     float* t_final;
     uint32_t* last;
 };
+// The (tile, pixels per thread, LDS batch) launch shapes compiled for both raster kernels:
+// writes up to n_max of them and returns how many there are.
+int raster_shapes(int* tile, int* ppt, int* batch, int n_max);
 int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_t s);
 
 struct RasterBwdArgs {

@@ -28,7 +28,12 @@ __global__ __launch_bounds__(kLidarThreads) void lidar_adjoint_kernel(LidarArgs 
         for (int k = 1; k < a.vt.n_views; ++k)
             if (j >= a.target_off[k]) b = k;
         const int pj = a.pix[j];
-        if (pj < 0 || (long long)pj >= (long long)a.vt.width[b] * a.vt.height[b]) continue;
+        if (pj < 0 || (long long)pj >= (long long)a.vt.width[b] * a.vt.height[b]) {
+            // a target outside its view: no adjoint, and the loss becomes NaN so that the
+            // caller sees the bad input (the host cannot read device targets without a sync)
+            part = __builtin_nanf("");
+            continue;
+        }
         const long long gp = a.vt.pix_base[b] + pj;
         const float mu = a.depth[gp];
         const float s = a.sigma[j];

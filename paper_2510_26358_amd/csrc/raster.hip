@@ -472,6 +472,20 @@ int raster_blocks(const ViewTable& vt) {
     X(32, 4, 256)             \
     X(32, 2, 512)
 
+int raster_shapes(int* tile, int* ppt, int* batch, int n_max) {
+    int n = 0;
+#define X(t_, p_, m_)             \
+    if (n < n_max) {              \
+        tile[n] = t_;             \
+        ppt[n] = p_;              \
+        batch[n] = m_;            \
+    }                             \
+    ++n;
+    AGS_RASTER_CONFIGS(X)
+#undef X
+    return n;
+}
+
 int launch_raster_fwd(const RasterArgs& a, int T, int batch, int ppt, hipStream_t s) {
     const int nb = raster_blocks(a.vt);
     if (nb <= 0) return 0;

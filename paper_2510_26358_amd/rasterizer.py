@@ -188,6 +188,13 @@ class LossTargets:
                 counts.append(int(m.sum()))
                 mk.append(m)
             mask_t = torch.from_numpy(np.concatenate(mk)).to(device)
+        for b, d in enumerate(lidar or []):
+            pb = np.asarray(d["pix"], np.int64)
+            if b >= views.n_views and len(pb):
+                raise ValueError(f"LiDAR targets given for view {b}, but there are {views.n_views} views")
+            if len(pb) and (pb.min() < 0 or pb.max() >= views.widths[b] * views.heights[b]):
+                raise ValueError(f"view {b}: LiDAR target pixel outside the {views.widths[b]}x{views.heights[b]} "
+                                 f"image")
         pix = np.concatenate([np.asarray(d["pix"], np.int32) for d in lidar]) if lidar else np.zeros(0, np.int32)
         val = np.concatenate([np.asarray(d["depth"], np.float32) for d in lidar]) if lidar else np.zeros(0, np.float32)
         sig = np.concatenate([np.asarray(d["sigma"], np.float32) for d in lidar]) if lidar else np.zeros(0, np.float32)

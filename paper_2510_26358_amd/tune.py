@@ -1,25 +1,19 @@
-"""Autotuner for the raster launch shapes: tile edge T (shared by binning, forward and
-backward), and for each raster kernel its Gaussians per LDS batch and pixels per thread.
+"""Autotuner front end for the raster launch shapes: tile edge T (shared by binning, forward
+and backward), and for each raster kernel its Gaussians per LDS batch and pixels per thread.
 
-For every tile size and every launch shape compiled for it, a few full forward + backward
-steps of the caller's workload are timed with the library's per-stage HIP events; the
-forward and backward shapes are then chosen independently (they only share T) and the tile
-size with the smallest resulting step time wins.  Results are cached in a JSON file keyed
-by device name and workload shape, so a shape is tuned once per machine.  The tile size
-changes the binning, so every tile size recalibrates its intersection capacity.
+The search runs in the library (`ags_tune`): for every tile size and every launch shape
+compiled for it, a few full forward + backward steps of the caller's workload are timed with
+per-stage HIP events; the forward and backward shapes are chosen independently (they only
+share T) and the tile size with the smallest resulting step time wins.  This module keeps
+the host policy: picks are cached in a JSON file keyed by device name and workload shape,
+so a shape is tuned once per machine.
 """
 from __future__ import annotations
 
 import json
 import os
-import time
 
 import torch
-
-# (batch, pixels per thread) launch shapes compiled for each tile size
-SHAPES = {8: [(64, 1), (128, 1)],
-          16: [(128, 1), (256, 1), (128, 2), (256, 2), (64, 4)],
-          32: [(256, 4), (512, 2)]}
 
 
 def _cache_path():
@@ -59,67 +53,40 @@ def _apply(ras, best):
                    batch_bwd=best["batch_bwd"], px_per_thread_bwd=best["ppt_bwd"])
 
 
-def time_shape(ras, params, cams, views, targets, tile, batch, ppt, steps=4, warmup=2, headroom=1.15):
-    """Per-stage ms of a fwd+bwd step with one launch shape for both raster kernels."""
-    ras.set_config(tile=tile, batch=batch, px_per_thread=ppt, batch_bwd=0, px_per_thread_bwd=0)
-    out, buf = ras.render(params, cams, views)
-    k = int(buf.counters()[0])
-    buf = ras.buffers(views, params.n, params.sh_degree, int(k * headroom) + 4096)
-    out = ras.outputs(views)
-    grads = params.zeros_like()
-    pose = torch.zeros(views.n_views, 6, device=params.means.device)
-    loss = torch.zeros(1, device=params.means.device)
-
-    def step():
-        ras.forward_into(params, cams, views, buf, out)
-        ras.backward_into(params, cams, views, buf, out, grads, pose, loss=targets, loss_out=loss)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    ras.profile(True)
-    ras.profile_reset()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps * 1e3
-    prof = ras.profile_read()
-    ras.profile(False)
-    stages = {name: tot / steps for name, (tot, cnt) in prof.items() if cnt}
-    return wall, stages, k
-
-
-def tune(ras, params, cams, views, targets, tiles=(8, 16, 32), steps=4, warmup=2, use_cache=True, log=None):
-    """Choose and set the fastest tile size and per-kernel launch shapes.  Returns
-    {"best": {...}, "ms": {...}, "cached": bool}."""
+def tune(ras, params, cams, views, targets, steps=4, warmup=2, use_cache=True, log=None):
+    """Choose and set the fastest tile size and per-kernel launch shapes with the library's
+    autotuner (`ags_tune`: the search and its timing run behind the C ABI), caching the pick
+    per device and workload shape.  Returns {"best": {...}, "ms": {...}, "cached": bool}."""
+    import ctypes as C
+    from . import _lib as L
     key = shape_key(views, params.n, params.sh_degree)
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         _apply(ras, cache[key]["best"])
         return {"best": cache[key]["best"], "ms": cache[key]["ms"], "cached": True}
-    table, best, best_total = {}, None, float("inf")
-    for t in tiles:
-        per = []
-        for (m, p) in SHAPES[t]:
-            wall, st, k = time_shape(ras, params, cams, views, targets, t, m, p, steps, warmup)
-            table[f"T{t}_M{m}_P{p}"] = {"step_ms": round(wall, 4), "raster_fwd": round(st.get("raster_fwd", 0), 4),
-                                        "raster_bwd": round(st.get("raster_bwd", 0), 4), "K": k}
-            per.append(((m, p), wall, st))
-            if log:
-                log(f"[tune] tile {t} batch {m} ppt {p}: step {wall:.3f} ms, fwd {st.get('raster_fwd', 0):.3f}, "
-                    f"bwd {st.get('raster_bwd', 0):.3f} (K={k})")
-        f_best = min(per, key=lambda e: e[2].get("raster_fwd", 0))
-        b_best = min(per, key=lambda e: e[2].get("raster_bwd", 0))
-        base = per[0]
-        rest = base[1] - base[2].get("raster_fwd", 0) - base[2].get("raster_bwd", 0)
-        total = rest + f_best[2].get("raster_fwd", 0) + b_best[2].get("raster_bwd", 0)
-        if total < best_total:
-            best_total = total
-            best = {"tile": t, "batch": f_best[0][0], "ppt": f_best[0][1], "batch_bwd": b_best[0][0],
-                    "ppt_bwd": b_best[0][1], "predicted_step_ms": round(total, 4)}
-    _apply(ras, best)
+    best = L.Config()
+    pred = C.c_float()
+    entries = (L.TuneEntry * 32)()
+    n_rep = C.c_int32()
+    g = params.c()
+    lc = targets.c()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = ras.lib.ags_tune(ras.ctx, C.byref(views.c), C.byref(g), C.c_void_p(cams.data_ptr()), C.byref(lc), steps,
+                          warmup, C.byref(best), C.byref(pred), entries, 32, C.byref(n_rep), stream)
+    L.check(rc, "ags_tune", ras.ctx)
+    table = {}
+    for e in entries[:min(n_rep.value, 32)]:
+        table[f"T{e.tile}_M{e.batch}_P{e.px_per_thread}"] = {
+            "step_ms": round(e.step_ms, 4), "raster_fwd": round(e.raster_fwd_ms, 4),
+            "raster_bwd": round(e.raster_bwd_ms, 4), "K": int(e.intersections)}
+        if log:
+            log(f"[tune] tile {e.tile} batch {e.batch} ppt {e.px_per_thread}: step {e.step_ms:.3f} ms, "
+                f"fwd {e.raster_fwd_ms:.3f}, bwd {e.raster_bwd_ms:.3f} (K={e.intersections})")
+    pick = {"tile": best.tile, "batch": best.batch, "ppt": best.px_per_thread, "batch_bwd": best.batch_bwd,
+            "ppt_bwd": best.px_per_thread_bwd, "predicted_step_ms": round(pred.value, 4)}
+    # ags_tune already set the pick on the context; keep the binding's copy in step
+    ras.cfg = best
     if use_cache:
-        cache[key] = {"best": best, "ms": table}
+        cache[key] = {"best": pick, "ms": table}
         _store_cache(cache)
-    return {"best": best, "ms": table, "cached": False}
+    return {"best": pick, "ms": table, "cached": False}

@@ -123,3 +123,29 @@ def test_lifecycle_and_map_host_calls(lib):
                               None, None) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_map_sync(None) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_map_destroy(None) == L.AGS_ERR_INVALID_ARG
+
+
+def test_tune_and_noalloc_refuse_bad_arguments_without_a_device(lib):
+    from paper_2510_26358_amd import _lib as L
+    best = L.Config()
+    assert lib.ags_tune(None, None, None, None, None, 4, 2, C.byref(best), None, None, 0, None,
+                        None) == L.AGS_ERR_INVALID_ARG
+    assert lib.ags_lifecycle_step_noalloc(None, None, None, None, None, None, None, None, None, None, None, None,
+                                          None, None) == L.AGS_ERR_INVALID_ARG
+
+
+def test_loss_targets_refuse_lidar_pixels_outside_their_view():
+    """The binding checks LiDAR target pixels on the host (where they are host arrays)."""
+    import numpy as np
+    from paper_2510_26358_amd.rasterizer import LossTargets, ViewSpec
+    from tests.oracle_helpers import random_scene
+    sc = random_scene(17, n=10, n_views=2)
+    views = ViewSpec.from_scene(sc)
+    LossTargets.from_scene(sc, views, device="cpu")  # valid targets pass
+    for bad in (-1, sc.cameras[1].width * sc.cameras[1].height):
+        lid = [dict(d) for d in sc.lidar]
+        lid[1]["pix"] = np.append(np.asarray(lid[1]["pix"]), bad).astype(np.int32)
+        lid[1]["depth"] = np.append(lid[1]["depth"], 3.0)
+        lid[1]["sigma"] = np.append(lid[1]["sigma"], 0.5)
+        with pytest.raises(ValueError):
+            LossTargets.from_scene(sc, views, device="cpu", lidar=lid)
