@@ -21,6 +21,8 @@ that order as a plain definition so the kernel's lists can be compared bit for b
       minimiser (tested without division, see `tile_reached`); every step is one rounded
       float32 operation in the order written there, so the decision is reproducible bit for
       bit.
+  (`tile_min_q_f64` / `membership_f64` state the same rule in float64 for the independent
+  gate: the float32 steps decide only candidates within rounding of the level)
   one intersection per (view b, Gaussian i, kept tile) with global tile id
       tile_base[b] + ty * ntx_b + tx and key (tile_id << 32) | bits(float32 depth)
   emitted in (b, i, ty, tx) order and stably sorted by key; ranges[tile] = [first, last+1).
@@ -99,6 +101,66 @@ def tile_reached(u, v, a, b, c, tau2, tx, ty, T, W, H):
             m = -(b * Y)
             hit = hit | ((a * lx <= m) & (m <= a * hx) & ~((Y * Y) * det > tau2 * a))
     return hit
+
+
+def tile_min_q_f64(u, v, a, b, c, tx, ty, T, W, H):
+    """Float64 minimum of Q(d) = a dx^2 + 2 b dx dy + c dy^2 over the pixel centres' rectangle
+    of tile (tx, ty), d = point - (u, v): zero when (u, v) lies inside, else the least of the
+    four edge minima (on an edge the quadratic is a parabola whose minimiser is clipped to
+    the edge).  Independent of the float32 decision rule of `tile_reached`: the plain
+    geometric statement that rule approximates."""
+    u, v, a, b, c = (float(x) for x in (u, v, a, b, c))
+    lx = tx * T + 0.5 - u
+    hx = min((tx + 1) * T, W) - 0.5 - u
+    ly = ty * T + 0.5 - v
+    hy = min((ty + 1) * T, H) - 0.5 - v
+    if lx <= 0.0 <= hx and ly <= 0.0 <= hy:
+        return 0.0
+
+    def q(x, y):
+        return a * x * x + 2.0 * b * x * y + c * y * y
+
+    best = np.inf
+    for X in (lx, hx):
+        y = min(max(-b * X / c, ly), hy)
+        best = min(best, q(X, y))
+    for Y in (ly, hy):
+        x = min(max(-b * Y / a, lx), hx)
+        best = min(best, q(x, Y))
+    return best
+
+
+def tile_level_f64(a, b, c, ex):
+    """1.001 ex^2 (a c - b^2) / c + 0.001 in float64."""
+    a, b, c, ex = (float(x) for x in (a, b, c, ex))
+    return 1.001 * ex * ex * (a * c - b * b) / c + 0.001
+
+
+def membership_f64(records, views, T: int, rel=1e-4):
+    """Tile membership by the float64 statement of the tile rule: the candidate tiles of each
+    valid record's footprint rectangle (`pixel_rect_f32`) whose float64 minimum of Q
+    (`tile_min_q_f64`) is at most the float64 level.  Returns (kept, ambiguous): sets of
+    (global tile, Gaussian index); a candidate whose minimum lies within rel (relative) of
+    the level is ambiguous -- float32 rounding may decide it either way."""
+    kept, amb = set(), set()
+    base = 0
+    for (W, H, g0), rec in zip(views, records):
+        ntx, nty = tile_grid(W, H, T)
+        x0, y0, x1, y1, ne = pixel_rect_f32(rec["u"], rec["v"], rec["ex"], rec["ey"], W, H)
+        ok = ne & np.asarray(rec["valid"], bool)
+        for i in np.nonzero(ok)[0]:
+            lev = tile_level_f64(rec["a"][i], rec["b"][i], rec["c"][i], rec["ex"][i])
+            for ty in range(y0[i] // T, y1[i] // T + 1):
+                for tx in range(x0[i] // T, x1[i] // T + 1):
+                    m = tile_min_q_f64(rec["u"][i], rec["v"][i], rec["a"][i], rec["b"][i], rec["c"][i],
+                                       tx, ty, T, W, H)
+                    key = (base + ty * ntx + tx, g0 + int(i))
+                    if abs(m - lev) <= rel * max(1.0, lev):
+                        amb.add(key)
+                    elif m <= lev:
+                        kept.add(key)
+        base += ntx * nty
+    return kept, amb
 
 
 def bin_reference(records, views, T: int):

@@ -5,7 +5,10 @@ upstream gradient through `ags_render_bwd` (upstream mode).  `render_loss(...)` 
 the fused L1 + LiDAR-KL loss of Sec. III-C in the backward kernels and returns it as a
 scalar whose backward scales the already computed gradients.  In both, the camera poses
 receive a gradient through a zero "pose_delta" input (B, 6): the derivative with respect to
-a left perturbation W_b <- Exp(delta_b) W_b, delta = (rho, phi).
+a left perturbation W_b <- Exp(delta_b) W_b, delta = (rho, phi).  That input is the point at
+which the pose gradient is taken and must hold zeros: a non-zero value raises ValueError
+instead of silently rendering at delta = 0 (move a camera by updating `cams`, e.g. with the
+library's pose step).
 """
 from __future__ import annotations
 
@@ -21,6 +24,14 @@ class _State:
         self.buf = None
 
 
+def _check_pose_delta(nonzero):
+    """Raise if the pose input held a non-zero entry (`nonzero`: a device count taken before
+    the render, read after the render's own synchronisation)."""
+    if int(nonzero.item()) != 0:
+        raise ValueError("pose_delta must be zero: it marks where the pose gradient is taken; "
+                         "update the cameras to move them")
+
+
 def _params(means, log_scales, quats, logits, sh, deg):
     return SplatParams(means.detach().contiguous(), log_scales.detach().contiguous(),
                        quats.detach().contiguous(), logits.detach().contiguous(),
@@ -30,8 +41,10 @@ def _params(means, log_scales, quats, logits, sh, deg):
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, logits, sh, pose_delta, st: _State):
+        nonzero = torch.count_nonzero(pose_delta.detach())
         p = _params(means, log_scales, quats, logits, sh, st.sh_degree)
         out, buf = st.ras.render(p, st.cams, st.views, capacity=st.capacity, buf=st.buf)
+        _check_pose_delta(nonzero)
         st.buf = buf
         st.capacity = buf.capacity
         ctx.st = st
@@ -61,8 +74,10 @@ class _RenderLossFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, logits, sh, pose_delta, st: _State,
                 targets: LossTargets):
+        nonzero = torch.count_nonzero(pose_delta.detach())
         p = _params(means, log_scales, quats, logits, sh, st.sh_degree)
         out, buf = st.ras.render(p, st.cams, st.views, capacity=st.capacity, buf=st.buf)
+        _check_pose_delta(nonzero)
         st.buf = buf
         grads = p.zeros_like()
         pose = torch.zeros(st.views.n_views, 6, device=p.means.device)

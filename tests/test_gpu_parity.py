@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.binning import bin_reference
+from oracle.binning import bin_reference, membership_f64
 from oracle.render import loss_and_grads, render
 from oracle.settings import RenderSettings
 from paper_2510_26358_amd import scenes
@@ -87,14 +87,15 @@ def test_projection_records_match_oracle(ras):
         base += n
 
 
-def _synthetic_records(rng, n_views, n, sizes, T):
-    """Seeded records: centre, conic of a random positive-definite screen covariance,
-    opacity, quantised depth (exact ties) and the half-widths of the alpha = 1/255 level."""
+def _synthetic_records(rng, n_views, n, sizes, T, margin=30):
+    """Seeded records: centre (up to `margin` px outside the view), conic of a random
+    positive-definite screen covariance, opacity, quantised depth (exact ties) and the
+    half-widths of the alpha = 1/255 level."""
     recs, valid, ref_in = [], [], []
     for b in range(n_views):
         W, H = sizes[b]
-        u = rng.uniform(-30, W + 30, n).astype(np.float32)
-        v = rng.uniform(-30, H + 30, n).astype(np.float32)
+        u = rng.uniform(-margin, W + margin, n).astype(np.float32)
+        v = rng.uniform(-margin, H + margin, n).astype(np.float32)
         sx = rng.exponential(3.0, n) + 0.3
         sy = rng.exponential(3.0, n) + 0.3
         rho = rng.uniform(-0.95, 0.95, n)
@@ -144,10 +145,49 @@ def test_binning_bit_exact_on_seeded_records(tile, sizes):
     assert kept <= n_cand and sv["n_listed"] == kept
     # pair ids -> Gaussian ids (view b's pairs start at pair_base[b] = b n and map to b n + local)
     gauss = sv["tile_pairs"]  # here pair id == Gaussian id because ranges are [b n, (b+1) n)
+    # main gate, independent of the float32 decision steps: tile membership equals the float64
+    # statement of the tile rule up to candidates within rounding of the level, and every
+    # tile's list is in (float32 depth bits, Gaussian index) order
+    f64_kept, f64_amb = membership_f64(ref_in, [(w, h, b * n) for b, (w, h) in enumerate(sizes)], tile)
+    zbits = recs[:, 6].view(np.uint32).astype(np.int64)
+    got = set()
+    for t, (s0, s1) in enumerate(sv["ranges"]):
+        lst = gauss[s0:s1]
+        got |= {(t, int(g)) for g in lst}
+        order = sorted(lst.tolist(), key=lambda g: (zbits[g], g))
+        assert lst.tolist() == order, t
+    assert len(got) == sv["n_listed"]
+    assert got - f64_amb == f64_kept
+    # and bit for bit with the float32 steps of the rule (the definition the kernel evaluates)
     assert np.array_equal(gauss, vals.astype(np.int64))
     zb = recs[:, 6].view(np.uint32).astype(np.uint64)[gauss]
     gkeys = (sv["tile_keys"].astype(np.uint64) << np.uint64(32)) | zb
     assert np.array_equal(gkeys, keys)
+    assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
+    _check_work_list(sv["work"], sv["ranges"])
+
+
+def test_binning_bit_exact_with_long_tile_lists():
+    """Two views of one and six tiles, each seen by 14,000 Gaussians: lists of thousands of
+    entries (over 10,000 in one tile) in the order (float32 depth bits, then pair id; the
+    quantised depths tie often)."""
+    from paper_2510_26358_amd.rasterizer import Rasterizer, ViewSpec
+    r = Rasterizer(0, tile=16, batch=256, px_per_thread=1)
+    rng = np.random.default_rng(1099)
+    n, sizes = 14_000, [(16, 16), (40, 20)]
+    recs, valid, ref_in = _synthetic_records(rng, len(sizes), n, sizes, 16, margin=0)
+    N = n * len(sizes)
+    views = ViewSpec([w for w, _ in sizes], [h for _, h in sizes], [0, n], [n, 2 * n])
+    keys, vals, ranges, counts, base = bin_reference(ref_in, [(w, h, b * n) for b, (w, h) in enumerate(sizes)], 16)
+    lengths = ranges[:, 1] - ranges[:, 0]
+    assert lengths.max() > 8192
+    cap = int(sum(int(c.sum()) for c in counts))
+    buf = r.buffers(views, N, 0, cap)
+    r.bin_records(views, N, torch.from_numpy(recs).cuda(), torch.from_numpy(valid.astype(np.uint8)).cuda(), buf)
+    torch.cuda.synchronize()
+    sv = saved_arrays(buf, views)
+    assert sv["K"] == cap and sv["n_listed"] == len(keys)
+    assert np.array_equal(sv["tile_pairs"], vals.astype(np.int64))
     assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
     _check_work_list(sv["work"], sv["ranges"])
 

@@ -176,6 +176,34 @@ def test_autograd_function_matches_fused_loss(ras):
     assert abs(loss.item() - loss2.item()) <= 1e-5 * max(1, abs(loss.item()))
     for a, b in zip(g1, [t.grad for t in leaves2] + [pose2.grad]):
         assert torch.allclose(a, b, rtol=1e-4, atol=1e-7 * max(1.0, float(b.abs().max())))
+    # the Function's gradients (torch's L1 upstream through ags_render_bwd) against the oracle:
+    # mean |rgb - gt| over 3 x pixels is the oracle's L1 term with w_l1 = 1 and no LiDAR term
+    ref = loss_and_grads(sc, RenderSettings(), w_l1=1.0, lam=0.0)
+    assert abs(loss.item() - ref["loss"]) <= 1e-5 * max(1.0, abs(ref["loss"]))
+    for name, g in zip(["means", "log_scales", "quats", "opacity_logits", "sh"], g1[:5]):
+        gg = g.cpu().numpy()
+        gg = gg.T if gg.ndim == 2 else (gg if gg.ndim == 1 else np.transpose(gg, (2, 0, 1)))
+        ok, msg = grad_close(gg, ref["grads"][name], ref["amb_gauss"])
+        assert ok, (name, msg)
+    ok, msg = grad_close(g1[5].cpu().numpy(), ref["pose"])
+    assert ok, msg
+
+
+def test_autograd_refuses_a_non_zero_pose_delta(ras):
+    """The pose input marks where the pose gradient is taken; rendering at a non-zero value
+    is refused instead of silently rendering at zero."""
+    from paper_2510_26358_amd.autograd import render, render_loss
+    sc = random_scene(322, n=50, sh_degree=0, n_views=1, width=32, height=24, f=30.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    bad = torch.zeros(1, 6, device="cuda")
+    bad[0, 3] = 1e-3
+    with pytest.raises(ValueError):
+        render(*p.tensors(), bad, ras, cams, views, sc.sh_degree)
+    tg = LossTargets.from_scene(sc, views)
+    with pytest.raises(ValueError):
+        render_loss(*p.tensors(), bad, ras, cams, views, sc.sh_degree, tg)
 
 
 def test_empty_and_degenerate_inputs(ras):

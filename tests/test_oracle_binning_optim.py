@@ -107,6 +107,43 @@ def test_binning_reference_equals_brute_force_enumeration():
         assert (e - s) == (tiles == t).sum()
 
 
+def test_float64_tile_minimum_equals_bounded_least_squares():
+    """The closed-form float64 minimum of the conic's quadratic form over a tile's pixel
+    centres (interior, else the clipped parabola minima of the four edges) equals scipy's
+    bounded least-squares solution on random ellipses and tiles."""
+    from oracle.binning import tile_min_q_f64
+    rng = np.random.default_rng(73)
+    recs = _random_records(rng, 200, 64, 40)
+    T, W, H = 8, 64, 40
+    n_checked = 0
+    for i in range(200):
+        A, B, C = (float(recs[k][i]) for k in ("a", "b", "c"))
+        for _ in range(4):
+            tx, ty = int(rng.integers(0, 8)), int(rng.integers(0, 5))
+            got = tile_min_q_f64(recs["u"][i], recs["v"][i], A, B, C, tx, ty, T, W, H)
+            lo = np.array([tx * T + 0.5 - float(recs["u"][i]), ty * T + 0.5 - float(recs["v"][i])])
+            hi = np.array([min(W, tx * T + T) - 0.5 - float(recs["u"][i]),
+                           min(H, ty * T + T) - 0.5 - float(recs["v"][i])])
+            ref = _box_min(A, B, C, lo, hi)
+            assert abs(got - ref) <= 1e-9 * max(1.0, ref), (i, tx, ty, got, ref)
+            n_checked += 1
+    assert n_checked == 800
+
+
+def test_float32_tile_rule_agrees_with_its_float64_statement():
+    """The reference's float32 decision steps keep exactly the candidates the float64
+    statement keeps, except candidates within 1e-4 (relative) of the level."""
+    from oracle.binning import membership_f64
+    rng = np.random.default_rng(74)
+    T = 8
+    views = [(64, 40, 0), (50, 30, 400)]
+    recs = [_random_records(rng, 400, 64, 40), _random_records(rng, 300, 50, 30)]
+    keys, vals, ranges, counts, base = bin_reference(recs, views, T)
+    got = {(int(k) >> 32, int(g)) for k, g in zip(keys, vals)}
+    kept, amb = membership_f64(recs, views, T)
+    assert kept and (got - amb) == kept
+
+
 def test_every_contributing_pixel_lies_in_its_gaussians_tiles():
     """The opacity-aware bounding box, and the ellipse test on its tiles, must cover every
     pixel where the brute-force compositing keeps the Gaussian (alpha >= 1/255), for each
