@@ -504,6 +504,62 @@ def oracle_leg(sc, ras, px_per_view, seed=5, lam=1.0, single_thread_px=0):
     return parity, cpu
 
 
+def oracle_time(sc, samples, threads, lam=1.0):
+    """Seconds the FP64 oracle takes for fwd + bwd of the sampled objective on `threads`
+    host threads (None: all of torch's)."""
+    import torch
+    from oracle.render import loss_and_grads
+    from oracle.settings import RenderSettings
+    before = torch.get_num_threads()
+    if threads:
+        torch.set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        loss_and_grads(sc, RenderSettings(), masks=samples, lam=lam)
+        return time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(before)
+
+
+def oracle_other_configs():
+    """The oracle's time on the tiny configuration's full image (2,000 Gaussians, 12,288 px) and
+    on seeded 16 x 16 tiles of the single-view configuration (300k Gaussians; 16 tiles on all
+    host threads, 4 of them on one thread), in Mpixel/s."""
+    import torch
+    from paper_2510_26358_amd import scenes
+    out = {}
+    tiny = scenes.tiny_scene()
+    full = [np.arange(tiny.cameras[0].width * tiny.cameras[0].height)]
+    sv = scenes.single_view_scene()
+    cam = sv.cameras[0]
+    rng = np.random.default_rng(7)
+    T, ntx = 16, (cam.width + 15) // 16
+    tiles = rng.choice(ntx * ((cam.height + 15) // 16), 16, replace=False)
+    pix = []
+    for t in tiles:
+        ys, xs = np.mgrid[(t // ntx) * T:min(cam.height, (t // ntx) * T + T), (t % ntx) * T:min(cam.width, (t % ntx) * T + T)]
+        pix.append((ys * cam.width + xs).ravel())
+    samp16 = [np.unique(np.concatenate(pix))]
+    samp4 = [np.unique(np.concatenate(pix[:4]))]
+    keep = np.isin(sv.lidar[0]["pix"], samp16[0])
+    sv.lidar = [{k: np.asarray(v)[keep] for k, v in sv.lidar[0].items()}]
+    runs = (("tiny_full_image", tiny, full, full), ("single_view_tiles", sv, samp16, samp4))
+    for name, sc, smp_all, smp_one in runs:
+        rec = {"n_gaussians": sc.n}
+        for label, th, smp in (("all_threads", None, smp_all), ("one_thread", 1, smp_one)):
+            n_px = int(sum(len(x) for x in smp))
+            if th == 1 and smp is not smp_all:
+                lid = sc.lidar[0]
+                sc = sc.copy()
+                k1 = np.isin(lid["pix"], smp[0])
+                sc.lidar = [{k: np.asarray(v)[k1] for k, v in lid.items()}]
+            dt = oracle_time(sc, smp, th)
+            rec[label] = {"value": round(n_px / dt / 1e6, 8), "unit": "Mpixel/s", "pixels": n_px,
+                          "cores": th or torch.get_num_threads(), "seconds": round(dt, 2)}
+        out[name] = rec
+    return out
+
+
 def per_view_loop(ras, p, cams, views, tg, grads, loss, steps, warmup):
     """The comparator: the same kernels launched once per view in a host loop (each view its
     own projection, binning and sorts; gradients accumulated across views; eager launches)."""
@@ -801,6 +857,7 @@ def main():
         log("[bench] oracle leg: parity of the timed configuration on a seeded sample, and the FP64 oracle's "
             "time on the host...")
         parity, cpu = oracle_leg(sc, ras, args.oracle_px, single_thread_px=512)
+        cpu["other_configs"] = oracle_other_configs()
         log(f"[bench] parity {parity}")
         log(f"[bench] cpu oracle: {cpu}")
 

@@ -238,18 +238,33 @@ int ags_ctx_set_config(ags_ctx* ctx, const ags_config* cfg);
 int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_gaussians,
                      int32_t sh_degree, int64_t isect_capacity, ags_sizes* out);
 
-/* Forward render of all views in one batch (projection, binning, depth/tile sort, tile
- * ranges, compositing).  cams: device [n_views].  saved: device, saved_bytes; ws: device,
+/* The same query keyed on a context (its configuration): the workspace sizes of
+ * ags_render_fwd / ags_render_bwd for this batch shape under the context's tile size. */
+int ags_workspace_query(const ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, int32_t sh_degree,
+                        int64_t isect_capacity, ags_sizes* out);
+
+/* Forward render of all views in one batch (Sec. III-B: the splats projected through each
+ * camera, Sigma' = J W Sigma W^T J^T, its 2 x 2 block rendered; the B synchronised views of
+ * the multi-view setting rendered together, the batch rasterisation of the abstract; colour,
+ * expected depth (the mean of the rendered depth distribution of Sec. III-C) and alpha
+ * composited front to back): projection, binning, depth/tile sort, tile ranges,
+ * compositing.  cams: device [n_views].  saved: device, saved_bytes; ws: device,
  * fwd_ws_bytes.  If the intersections exceed isect_capacity the overflow counter in
- * `saved` is set and the outputs are not valid: enlarge the capacity and run again. */
+ * `saved` is set and the outputs are not valid: enlarge the capacity and run again.  Errors:
+ * INVALID_ARG (null or misaligned buffers, bad shapes), WORKSPACE (ws_bytes too small),
+ * NOT_SUPPORTED (a launch shape not compiled), HIP. */
 int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* out,
                    void* saved, void* ws, size_t ws_bytes, void* stream);
 
-/* Backward: exactly one of `up` (upstream gradients) or `loss` (fused loss; then
- * `loss_out`, device float[1] or NULL, receives the loss value) is non-NULL.  `fwd` holds
- * the outputs of the matching forward (read in loss mode).  saved: from that forward.
- * ws: device, bwd_ws_bytes.  Gradients per ags_grads. */
+/* Backward (Sec. III-C: the multimodal loss back-propagated to every splat parameter and,
+ * through the projection model, to each camera pose; the views' gradients summed into the one
+ * shared splat set of Sec. III-B).  Exactly one of `up` (upstream gradients) or `loss` (fused
+ * loss; then `loss_out`, device float[1] or NULL, receives the loss value) is non-NULL.
+ * `fwd` holds the outputs of the matching forward (read in loss mode).  saved: from that
+ * forward (transmittance is recomputed from it, no per-pixel blend lists are kept).  ws:
+ * device, bwd_ws_bytes.  Gradients per ags_grads.  Errors: INVALID_ARG, WORKSPACE,
+ * NOT_SUPPORTED, HIP. */
 int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
                    const void* saved, const ags_upstream* up, const ags_loss* loss,

@@ -22,7 +22,7 @@ LIFECYCLE_NOALLOC_MAX_N = 1 << 22
 
 EXPORTED = [
     "ags_version", "ags_error_string", "ags_last_hip_error", "ags_config_default",
-    "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes",
+    "ags_ctx_create", "ags_ctx_destroy", "ags_ctx_set_config", "ags_buffer_sizes", "ags_workspace_query",
     "ags_render_fwd", "ags_render_bwd", "ags_render_bwd_adam", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
     "ags_lifecycle_step", "ags_lifecycle_step_noalloc", "ags_tune", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
@@ -144,6 +144,7 @@ def load(path: str = LIB_PATH):
     lib.ags_ctx_destroy.restype = None
     lib.ags_ctx_set_config.argtypes = [vp, P(Config)]
     lib.ags_buffer_sizes.argtypes = [P(Config), P(Views), C.c_int32, C.c_int32, C.c_int64, P(Sizes)]
+    lib.ags_workspace_query.argtypes = [vp, P(Views), C.c_int32, C.c_int32, C.c_int64, P(Sizes)]
     lib.ags_render_fwd.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp, vp,
                                    C.c_size_t, vp]
     lib.ags_render_bwd.argtypes = [vp, P(Views), P(Gaussians), vp, C.c_int64, P(FwdOut), vp,

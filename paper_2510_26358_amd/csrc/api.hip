@@ -380,6 +380,12 @@ int ags_buffer_sizes(const ags_config* cfg, const ags_views* views, int32_t n_ga
     return AGS_OK;
 }
 
+int ags_workspace_query(const ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, int32_t sh_degree,
+                        int64_t isect_capacity, ags_sizes* out) {
+    if (!ctx) return AGS_ERR_INVALID_ARG;
+    return ags_buffer_sizes(&ctx->cfg, views, n_gaussians, sh_degree, isect_capacity, out);
+}
+
 int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* out,
                    void* saved, void* ws, size_t ws_bytes, void* stream) {

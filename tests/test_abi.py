@@ -101,6 +101,8 @@ def test_buffer_sizes_rejects_bad_arguments(lib, case):
 def test_null_context_is_rejected_without_touching_a_device(lib):
     from paper_2510_26358_amd import _lib as L
     assert lib.ags_render_fwd(None, None, None, None, 0, None, None, None, 0, None) == L.AGS_ERR_INVALID_ARG
+    s = L.Sizes()
+    assert lib.ags_workspace_query(None, None, 0, 0, 0, C.byref(s)) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_profile_enable(None, 1) == L.AGS_ERR_INVALID_ARG
 
 

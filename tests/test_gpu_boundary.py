@@ -56,6 +56,10 @@ def test_too_small_workspaces_are_refused_before_any_launch():
     out, buf = ras.render(p, cams, views)
     torch.cuda.synchronize()
     s = buf.sizes
+    # the context-keyed query gives the sizes of the configuration-keyed one
+    q = L.Sizes()
+    assert ras.lib.ags_workspace_query(ras.ctx, C.byref(views.c), p.n, p.sh_degree, buf.capacity, C.byref(q)) == 0
+    assert (q.saved_bytes, q.fwd_ws_bytes, q.bwd_ws_bytes) == (s.saved_bytes, s.fwd_ws_bytes, s.bwd_ws_bytes)
     g = p.c()
     fo = L.FwdOut(out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), None)
     null = C.c_void_p(0)
