@@ -523,8 +523,8 @@ def oracle_time(sc, samples, threads, lam=1.0):
 
 def oracle_other_configs():
     """The oracle's time on the tiny configuration's full image (2,000 Gaussians, 12,288 px) and
-    on seeded 16 x 16 tiles of the single-view configuration (300k Gaussians; 16 tiles on all
-    host threads, 4 of them on one thread), in Mpixel/s."""
+    on seeded 16 x 16 tiles of the single-view configuration (300k Gaussians; 64 tiles, 16,384
+    px, on all host threads, 16 of them on one thread), in Mpixel/s."""
     import torch
     from paper_2510_26358_amd import scenes
     out = {}
@@ -534,16 +534,16 @@ def oracle_other_configs():
     cam = sv.cameras[0]
     rng = np.random.default_rng(7)
     T, ntx = 16, (cam.width + 15) // 16
-    tiles = rng.choice(ntx * ((cam.height + 15) // 16), 16, replace=False)
+    tiles = rng.choice(ntx * ((cam.height + 15) // 16), 64, replace=False)
     pix = []
     for t in tiles:
         ys, xs = np.mgrid[(t // ntx) * T:min(cam.height, (t // ntx) * T + T), (t % ntx) * T:min(cam.width, (t % ntx) * T + T)]
         pix.append((ys * cam.width + xs).ravel())
-    samp16 = [np.unique(np.concatenate(pix))]
-    samp4 = [np.unique(np.concatenate(pix[:4]))]
-    keep = np.isin(sv.lidar[0]["pix"], samp16[0])
+    samp64 = [np.unique(np.concatenate(pix))]
+    samp16 = [np.unique(np.concatenate(pix[:16]))]
+    keep = np.isin(sv.lidar[0]["pix"], samp64[0])
     sv.lidar = [{k: np.asarray(v)[keep] for k, v in sv.lidar[0].items()}]
-    runs = (("tiny_full_image", tiny, full, full), ("single_view_tiles", sv, samp16, samp4))
+    runs = (("tiny_full_image", tiny, full, full), ("single_view_tiles", sv, samp64, samp16))
     for name, sc, smp_all, smp_one in runs:
         rec = {"n_gaussians": sc.n}
         for label, th, smp in (("all_threads", None, smp_all), ("one_thread", 1, smp_one)):

@@ -2,26 +2,36 @@
 "Incremental Gaussian Mapping" (the voxel key equation) and "Memory Management" (LRU offload
 to host memory above a threshold tau, reload when a key is met again).
 
-A plain, slow, dictionary-based statement of what one insertion call computes.  The paper
-leaves v, P1..P3, tau, the initial splat and the order of the resident set unstated; the
-readings (recorded in DESIGN.md):
+A plain, slow, dictionary-based statement of what one insertion call, and the map's side of
+one lifecycle pass (Sec. III-B "Gaussian Splats Lifecycle Operations"), compute.  The paper
+leaves v, P1..P3, tau, the initial splat, the order of the resident set and how pruned and
+densified splats relate to the voxel keys unstated; the readings (recorded in the design doc):
   * key: c = floor(p / v) per axis with the division and the floor in float32 (the points'
-    precision), k = (c_x P1 + c_y P2 + c_z P3) mod 2^64.  Points with equal keys belong to the
-    same splat (two voxels whose keys collide are merged, as key matching implies).  The key
-    2^64 - 1 is reserved and replaced by 2^64 - 2.
-  * the points of one call are taken in order: a key already in the map marks its splat used;
-    a new key instantiates one splat from the first point carrying it: mean p, log-scales
-    ln(s_init) (float32), identity quaternion, logit of o_init (float32), SH DC
-    (rgb - 1/2) / C0 in float32 (so that a DC-only splat shows the point's colour), the rest of
-    the SH and both Adam moments zero.  New ids count up in that order.
-  * every splat whose key a point of call t carries has last_used = t.
+    precision), k = (c_x P1 + c_y P2 + c_z P3) mod 2^64.  Two voxels whose keys collide are
+    merged, as key matching implies.  The key 2^64 - 1 is reserved and replaced by 2^64 - 2.
+  * a key names a group of splats: the splat its first point instantiated and that splat's
+    descendants by densification (a copy or split child inherits its parent's key and
+    last_used); keys are not recomputed as means move.  Pruning retires a splat's id (ids are
+    never reused); a key whose group has no live member left is absent from the map.
+  * the points of one call are taken in order: a key present in the map marks every live
+    member of its group used; a key absent instantiates one splat from the first point
+    carrying it: mean p, log-scales ln(s_init) (float32), identity quaternion, logit of
+    o_init (float32), SH DC (rgb - 1/2) / C0 in float32 (so that a DC-only splat shows the
+    point's colour), the rest of the SH and both Adam moments zero.  New ids count up in
+    that order.  A point's id is the smallest live id of its group.
+  * every live splat in a group that a point of call t hits has last_used = t.
   * resident set: an ordered list of ids (the rows the GPU holds).  A call appends its new
-    splats (id order), then the splats it met that were offloaded (reloaded from the host
-    store, id order); then, while more than tau rows are listed, the least recently used ones
-    (smallest last_used; ties: earlier in the list) are offloaded, the rest keeping their
-    order.  Offloaded rows keep the values they had on the GPU.
-All values are float32 (copies and the float32 initialisation above): the GPU result is
-expected bit for bit.
+    splats (id order), then the members of the groups it hit that were offloaded (reloaded
+    from the host store, id order); then, while more than tau rows are listed, the least
+    recently used ones (smallest last_used; ties: earlier in the list) are offloaded, the
+    rest keeping their order.  Offloaded rows keep the values they had on the GPU.
+  * a lifecycle pass over the resident set, with one action per row (keep, prune, duplicate,
+    split): its output rows, in order, become the resident set; each input's first output
+    keeps the input's id, the second output of a duplicated or split input gets a new id
+    (counting up in input order); pruned inputs are retired.  The resident set may then
+    exceed tau until the next insertion call offloads the excess.
+Insertion values are float32 (copies and the float32 initialisation above): the GPU result is
+expected bit for bit; the rows a lifecycle pass computes are that pass's (oracle.lifecycle).
 """
 from __future__ import annotations
 
@@ -29,10 +39,13 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .lifecycle import CLONE, PRUNE, SPLIT
+
 EMPTY_KEY = (1 << 64) - 1
 MASK64 = (1 << 64) - 1
 SH_C0 = 0.28209479177387814   # Y_0^0 = 1 / (2 sqrt(pi))
 FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+OFFLOADED, RESIDENT, RETIRED = 0, 1, 2
 
 
 @dataclass
@@ -89,32 +102,38 @@ def new_splat(point, rgb, vp: VoxelMapParams):
 @dataclass
 class VoxelMap:
     vp: VoxelMapParams
-    table: dict = field(default_factory=dict)      # key -> id
+    table: dict = field(default_factory=dict)      # key -> live ids of its group, ascending
+    seen: set = field(default_factory=set)         # every key ever entered
     keys: list = field(default_factory=list)       # id -> key
     last_used: list = field(default_factory=list)  # id -> call index
     rows: dict = field(default_factory=dict)       # id -> row, for resident ids (the GPU copy)
     store: dict = field(default_factory=dict)      # id -> row, for offloaded ids (host store)
+    retired: set = field(default_factory=set)      # pruned ids
     resident: list = field(default_factory=list)   # ordered resident ids
+
+    def state(self, j):
+        return RESIDENT if j in self.rows else OFFLOADED if j in self.store else RETIRED
 
     def insert(self, points, colors, t):
         """One call: returns dict(point_id, new, reloaded, evicted) (id lists in order)."""
         cells = voxel_cells(points, self.vp.voxel)
-        point_id = np.empty(len(cells), np.int64)
-        new, met = [], []
-        for i, c in enumerate(cells):
-            k = voxel_key(c, self.vp.primes)
+        pkeys = [voxel_key(c, self.vp.primes) for c in cells]
+        new, hit = [], set()
+        for i, k in enumerate(pkeys):
             if k not in self.table:
                 j = len(self.keys)
-                self.table[k] = j
+                self.table[k] = [j]
+                self.seen.add(k)
                 self.keys.append(k)
                 self.last_used.append(t)
                 self.rows[j] = new_splat(points[i], colors[i], self.vp)
                 new.append(j)
-            j = self.table[k]
-            point_id[i] = j
+            hit.add(k)
+        point_id = np.array([self.table[k][0] for k in pkeys], np.int64)
+        met = sorted(j for k in hit for j in self.table[k])
+        for j in met:
             self.last_used[j] = t
-            met.append(j)
-        reloaded = sorted(set(j for j in met if j in self.store))
+        reloaded = [j for j in met if j in self.store]
         for j in reloaded:
             self.rows[j] = self.store.pop(j)
         listed = self.resident + new + reloaded
@@ -129,6 +148,40 @@ class VoxelMap:
                 self.store[j] = self.rows.pop(j)
         self.resident = listed
         return {"point_id": point_id, "new": new, "reloaded": reloaded, "evicted": evicted}
+
+    def lifecycle(self, actions, out_params, out_m, out_v):
+        """The map's side of one lifecycle pass over the resident set: actions[q] for resident
+        row q (oracle.lifecycle's codes); out_*: that pass's output rows (dicts of per-row
+        arrays, in output order).  Returns dict(ids, new, retired)."""
+        actions = np.asarray(actions)
+        assert len(actions) == len(self.resident)
+        ids, new, retired = [], [], []
+        for q, j in enumerate(self.resident):
+            a = int(actions[q])
+            if a == PRUNE:
+                retired.append(j)
+                continue
+            ids.append(j)
+            if a in (CLONE, SPLIT):
+                c = len(self.keys)
+                self.keys.append(self.keys[j])
+                self.last_used.append(self.last_used[j])
+                self.table[self.keys[j]].append(c)
+                ids.append(c)
+                new.append(c)
+        for j in retired:
+            group = self.table[self.keys[j]]
+            group.remove(j)
+            if not group:
+                del self.table[self.keys[j]]
+            del self.rows[j]
+            self.retired.add(j)
+        assert len(ids) == len(out_params["means"])
+        f32 = lambda d, r: {k: np.asarray(d[k][r], np.float32).copy() for k in FIELDS}
+        for r, j in enumerate(ids):
+            self.rows[j] = {"params": f32(out_params, r), "m": f32(out_m, r), "v": f32(out_v, r)}
+        self.resident = ids
+        return {"ids": ids, "new": new, "retired": retired}
 
     def resident_arrays(self, which="params"):
         """The resident rows stacked in resident order: dict field -> (n, ...) float32."""

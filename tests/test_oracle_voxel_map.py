@@ -2,13 +2,16 @@
 Management"): the key's cells at voxel boundaries and for negative coordinates, the key's
 linearity in the cell and a constructed key collision, the insertion rules on a hand-built
 frame, the DC colour of a new splat against the degree-0 harmonic, LRU offload and reload on
-hand-built sequences, and invariants of long random sequences."""
+hand-built sequences, the map's side of lifecycle passes (key groups, retired ids, emptied
+keys) on a hand-built sequence, and invariants of long random sequences with and without
+lifecycle passes."""
 import math
 
 import numpy as np
 
-from oracle.voxel_map import (EMPTY_KEY, MASK64, SH_C0, VoxelMap, VoxelMapParams, voxel_cells, voxel_key,
-                              voxel_keys)
+from oracle.lifecycle import CLONE, KEEP, PRUNE, SPLIT
+from oracle.voxel_map import (EMPTY_KEY, FIELDS, MASK64, OFFLOADED, RESIDENT, RETIRED, SH_C0, VoxelMap,
+                              VoxelMapParams, voxel_cells, voxel_key, voxel_keys)
 
 P = (73856093, 19349663, 83492791)
 
@@ -141,3 +144,92 @@ def test_vectorised_keys_equal_the_per_point_keys():
     ks = voxel_keys(pts, vp)
     assert ks.dtype == np.uint64
     assert [int(k) for k in ks] == [voxel_key(c, vp.primes) for c in voxel_cells(pts, vp.voxel)]
+
+
+def _pass_rows(m, actions, mark=100.0):
+    """Output rows of a stand-in lifecycle pass over m's resident set: every kept output copies
+    its input row; the second output of a duplicated or split input is marked (means[0] +
+    mark), so that the test can see where each row went."""
+    outs = {w: {k: [] for k in FIELDS} for w in ("params", "m", "v")}
+    for q, j in enumerate(m.resident):
+        n_out = {KEEP: 1, PRUNE: 0, CLONE: 2, SPLIT: 2}[int(actions[q])]
+        for c in range(n_out):
+            for w in outs:
+                for k in FIELDS:
+                    a = np.array(m.rows[j][w][k], np.float32)
+                    if c == 1 and w == "params" and k == "means":
+                        a[0] += np.float32(mark)
+                    outs[w][k].append(a)
+    return [{k: np.array(v) for k, v in outs[w].items()} for w in ("params", "m", "v")]
+
+
+def _lifecycle(m, actions):
+    return m.lifecycle(actions, *_pass_rows(m, actions))
+
+
+def test_lifecycle_passes_on_a_hand_built_sequence():
+    vp = VoxelMapParams(voxel=1.0, tau=3, sh_degree=0)
+    m = VoxelMap(vp)
+    z = lambda n: np.zeros((n, 3), np.float32)
+    key0 = voxel_key(voxel_cells(_cube(0), 1.0)[0], vp.primes)
+    m.insert(np.concatenate([_cube(0), _cube(1)]), z(2), 0)
+    # a duplicate: the copy takes the next id, the parent's key and its last use
+    r = _lifecycle(m, [CLONE, KEEP])
+    assert r == {"ids": [0, 2, 1], "new": [2], "retired": []}
+    assert m.keys[2] == m.keys[0] == key0 and m.last_used[2] == 0 and m.table[key0] == [0, 2]
+    assert m.rows[2]["params"]["means"][0] == np.float32(100.5)
+    # two new voxels: listed [0, 2, 1, 3, 4], tau 3: the two oldest, 0 and 2, leave
+    r = m.insert(np.concatenate([_cube(2), _cube(3)]), z(2), 1)
+    assert r["new"] == [3, 4] and r["evicted"] == [0, 2] and m.resident == [1, 3, 4]
+    # meeting voxel 0 reloads its whole group; the point's id is the group's smallest
+    r = m.insert(_cube(0), z(1), 2)
+    assert r["point_id"].tolist() == [0] and r["reloaded"] == [0, 2]
+    assert m.last_used[0] == m.last_used[2] == 2
+    # listed [1, 3, 4, 0, 2] with last uses 0, 1, 1, 2, 2
+    assert r["evicted"] == [1, 3] and m.resident == [4, 0, 2]
+    # prune the group's smallest member and split the other: the second child is new
+    r = _lifecycle(m, [KEEP, PRUNE, SPLIT])
+    assert r == {"ids": [4, 2, 5], "new": [5], "retired": [0]}
+    assert m.table[key0] == [2, 5] and m.keys[5] == key0 and m.last_used[5] == 2
+    assert m.state(0) == RETIRED and m.state(1) == OFFLOADED and m.state(5) == RESIDENT
+    # voxel 0's id is now 2; voxel 1's offloaded splat is reloaded; 4 is the oldest
+    r = m.insert(np.concatenate([_cube(0), _cube(1)]), z(2), 3)
+    assert r["point_id"].tolist() == [2, 1] and r["new"] == [] and r["reloaded"] == [1]
+    assert r["evicted"] == [4] and m.resident == [2, 5, 1]
+    # pruning every member empties the key: the next point there makes a new splat
+    r = _lifecycle(m, [PRUNE, PRUNE, KEEP])
+    assert r == {"ids": [1], "new": [], "retired": [2, 5]} and key0 not in m.table
+    r = m.insert(_cube(0), z(1), 4)
+    assert r["point_id"].tolist() == [6] and r["new"] == [6] and m.table[key0] == [6]
+    assert m.resident == [1, 6] and sorted(m.store) == [3, 4] and m.retired == {0, 2, 5}
+    assert m.seen == {voxel_key(voxel_cells(_cube(i), 1.0)[0], vp.primes) for i in range(4)}
+
+
+def test_invariants_of_random_sequences_with_lifecycle_passes():
+    rng = np.random.default_rng(12)
+    vp = VoxelMapParams(voxel=0.5, tau=40, sh_degree=0)
+    m = VoxelMap(vp)
+    for t in range(40):
+        if t % 3 == 2 and m.resident:
+            act = rng.choice([KEEP, PRUNE, CLONE, SPLIT], len(m.resident), p=[0.5, 0.2, 0.15, 0.15])
+            n_ids = len(m.keys)
+            r = _lifecycle(m, act)
+            assert len(r["ids"]) == int((act != PRUNE).sum() + (act >= CLONE).sum())
+            assert r["new"] == list(range(n_ids, len(m.keys)))
+        centre = np.array([0.3 * t, 0, 0])
+        pts = (centre + rng.normal(0, 1.5, (rng.integers(1, 60), 3))).astype(np.float32)
+        r = m.insert(pts, rng.random((len(pts), 3)).astype(np.float32), t)
+        keys = [voxel_key(c, vp.primes) for c in voxel_cells(pts, vp.voxel)]
+        # groups: the live ids of a key, ascending, each id's key its group's; no empty group
+        live = [j for j in range(len(m.keys)) if j not in m.retired]
+        assert sorted(j for g in m.table.values() for j in g) == live
+        assert all(g and g == sorted(g) and all(m.keys[j] == k for j in g) for k, g in m.table.items())
+        # a point's id is its group's smallest; every member of a hit group is used now
+        for k, j in zip(keys, r["point_id"].tolist()):
+            assert m.table[k][0] == j
+            assert all(m.last_used[i] == t for i in m.table[k])
+        # every id resident, stored or retired, once
+        assert sorted(m.resident + list(m.store) + list(m.retired)) == list(range(len(m.keys)))
+        assert len(set(m.resident)) == len(m.resident) <= vp.tau and set(m.rows) == set(m.resident)
+        if m.store and m.resident:
+            assert max(m.last_used[j] for j in m.store) <= min(m.last_used[j] for j in m.resident)
