@@ -413,20 +413,28 @@ int ags_lifecycle_step_noalloc(ags_ctx* ctx, const ags_lifecycle* lp, const ags_
 
 /* ---- Voxel-hashed Gaussian map with a bounded GPU-resident set (Sec. III-B "Incremental
  * Gaussian Mapping": the voxel key equation; "Memory Management": least-recently-used
- * offload to host memory above a threshold tau, reload when a key is met again).
+ * offload to host memory above a threshold tau, reload when a key is met again; with
+ * "Gaussian Splats Lifecycle Operations" for pruned and densified splats).
  *
  * Key of a point p: c = floor(p / v) per axis (float32 division and floor), k = (c_x P1 +
- * c_y P2 + c_z P3) mod 2^64; equal keys are one splat (two voxels whose keys collide are
- * merged); the key 2^64 - 1 is reserved and becomes 2^64 - 2.  |p / v| must stay below 2^62.
- * An insertion call takes its points in order: a known key marks its splat used; a new key
- * makes one splat from the first point carrying it (mean p, log-scales ln s_init, identity
- * quaternion, logit of o_init, SH DC (rgb - 1/2) / Y_0^0, other SH and Adam moments 0), ids
- * counting up in that order.  Every splat met by call t gets last_used = t.  The resident set
- * (the rows the caller renders and optimises) is rebuilt as: the input rows in order, then
- * the call's new splats (id order), then the splats it met that were offloaded (reloaded from
- * the host store, id order); while more than tau rows remain, the least recently used
- * (smallest last_used, ties: earlier row) are offloaded to the host store with their current
- * values, the others keeping their order. */
+ * c_y P2 + c_z P3) mod 2^64 (two voxels whose keys collide are merged); the key 2^64 - 1 is
+ * reserved and becomes 2^64 - 2.  |p / v| must stay below 2^62.  A key names a group of
+ * splats: the one its first point made and that splat's descendants by densification
+ * (ags_map_lifecycle: a copy or split child inherits its parent's key and last_used); keys
+ * are not recomputed as means move.  Each splat has an id (never reused) in one of three
+ * states: resident (a row of the resident set, the rows the caller renders and optimises),
+ * offloaded (its row in the host store) or retired (pruned).  A key whose group has no live
+ * member is absent from the map.
+ * An insertion call takes its points in order: a key present marks every live member of its
+ * group used; an absent key makes one splat from the first point carrying it (mean p,
+ * log-scales ln s_init, identity quaternion, logit of o_init, SH DC (rgb - 1/2) / Y_0^0,
+ * other SH and Adam moments 0), ids counting up in that order.  A point's id is its group's
+ * smallest live id.  Every live splat in a group hit by call t gets last_used = t.  The
+ * resident set is rebuilt as: the input rows in order, then the call's new splats (id order),
+ * then the members of the groups it hit that were offloaded (reloaded from the host store, id
+ * order); while more than tau rows remain, the least recently used (smallest last_used, ties:
+ * earlier row) are offloaded to the host store with their current values, the others keeping
+ * their order. */
 typedef struct ags_map ags_map;
 
 typedef struct ags_map_config {
@@ -441,9 +449,11 @@ typedef struct ags_map_config {
 } ags_map_config;
 
 typedef struct ags_map_counts {
-    int64_t n_ids;         /* splats in the map after the call */
+    int64_t n_ids;         /* ids handed out so far (all states) */
     int64_t n_resident;    /* rows of the output resident set */
-    int64_t n_new, n_reloaded, n_evicted;
+    int64_t n_new, n_reloaded, n_evicted;  /* by this call (n_new: new ids) */
+    int64_t n_offloaded;   /* ids in the host store after the call */
+    int64_t n_retired;     /* ids this call retired */
 } ags_map_counts;
 
 /* voxel 0.05, s_init 0.005, o_init 0.1, degree 3, primes 73856093, 19349663, 83492791,
@@ -459,40 +469,69 @@ int ags_map_destroy(ags_map* map);
 
 /* One insertion call (number `frame`, non-decreasing over calls, >= 0).  points / colors:
  * device float[n_points][3] (xyz; rgb in [0, 1]).  in / in_m / in_v / in_ids: the resident set
- * this map returned last (values may have changed, not rows or order; n = 0 before the
- * first call; in->n <= tau).  out / out_m / out_v / out_ids: other buffers receiving the new
- * resident set, packed with row stride counts->n_resident; their `n` gives the capacity in
- * rows, which must be >= min(in->n + n_points, tau).  point_id: device int32[n_points] (or
- * NULL): the splat id of each point.  evicted_ids: device int32[n_points] (or NULL): the ids
+ * this map returned last (by ags_map_insert or ags_map_lifecycle; values may have changed,
+ * not rows or order; n = 0 before the first call); in->n must equal that set's size and every
+ * id must be resident and appear once (checked on the device first: INVALID_ARG, nothing
+ * changed).  out / out_m / out_v / out_ids: other buffers receiving the new resident set,
+ * packed with row stride counts->n_resident; their `n` gives the capacity in rows, which
+ * must be >= min(in->n + n_points + n_offloaded, tau) (n_offloaded as the previous call
+ * reported it).  point_id: device int32[n_points] (or NULL): the id of each point.
+ * evicted_ids: device int32 (or NULL) with room for max(n_points, in->n + n_points +
+ * n_offloaded - tau) entries (n_points suffices while ags_map_lifecycle is not used): the ids
  * offloaded by this call, in row order.  Host-synchronous: returns after the stream's work
- * (two synchronisations: the reload list, then the new resident set).  The offloaded rows
- * leave for pinned memory on a copy stream of the map's own, which waits for them to be
- * staged and then overlaps whatever the caller enqueues next; a host thread waits for that
- * copy and writes the rows into the host store, and the next call on the map waits for it
- * first (so do ags_map_sync, ags_map_read_store and ags_map_destroy; a failed copy makes the
- * next of them return AGS_ERR_HIP).  INVALID_ARG for bad
- * pointers or sizes, CAPACITY when n_ids + n_points > max_ids (nothing changed); after
- * AGS_ERR_HIP the map's state is undefined (destroy it). */
+ * (three synchronisations: the ids check, the reload list, then the new resident set).  The
+ * offloaded rows leave for pinned memory on a copy stream of the map's own, which waits for
+ * them to be staged and then overlaps whatever the caller enqueues next; a host thread waits
+ * for that copy and writes the rows into the host store, and the next call on the map waits
+ * for it first (so do ags_map_sync, ags_map_read_store and ags_map_destroy; a failed copy
+ * makes the next of them return AGS_ERR_HIP).  When more than max_points rows are reloaded or
+ * offloaded, the rows go through the staging in chunks of max_points on the calling thread
+ * and are in the host store when the call returns.  INVALID_ARG for bad pointers, sizes or
+ * ids, CAPACITY when n_ids + n_points > max_ids (nothing changed); after AGS_ERR_HIP the
+ * map's state is undefined (destroy it). */
 int ags_map_insert(ags_map* map, const float* points, const float* colors, int64_t n_points, int32_t frame,
                    const ags_gaussians* in, const ags_gaussians* in_m, const ags_gaussians* in_v,
                    const int32_t* in_ids, ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v,
                    int32_t* out_ids, int32_t* point_id, int32_t* evicted_ids, ags_map_counts* counts,
                    void* stream);
 
+/* The map's side of a lifecycle pass (Sec. III-B "Gaussian Splats Lifecycle Operations" over
+ * the splats of "Incremental Gaussian Mapping") run on the resident set this map returned
+ * last: ids: device int32[n], that set's ids in row order (n = its size); actions: device
+ * uint8[n], the pass's action per row as ags_lifecycle_step writes them (0 keep, 1 prune,
+ * 2 duplicate, 3 split).  The pass's output rows, in its order, become the resident set:
+ * each input's first output keeps the input's id; the second output of a duplicated or split
+ * input gets a new id (counting up from n_ids in input order) with the input's key and
+ * last_used; a pruned input's id is retired, and a key whose group loses its last live member
+ * leaves the map.  rows / rows_m / rows_v: the pass's output rows and moments as
+ * ags_lifecycle_step wrote them (row stride = their `n`, its output capacity).  out / out_m /
+ * out_v / out_ids: other buffers receiving the new resident set, packed with row stride
+ * counts->n_resident (capacity in their `n`, >= that count; out_ids: device int32 with room for
+ * 2 n entries).  The resident set may now exceed tau; the next insertion call offloads the
+ * excess.  Host-synchronous (two synchronisations).  INVALID_ARG: bad pointers or sizes, n
+ * differs from the resident set's size, an id is not resident or appears twice, an action is
+ * above 3, or the rows' stride or the output capacity is below the output count (nothing
+ * changed); CAPACITY: n_ids + (new ids) > max_ids (nothing changed). */
+int ags_map_lifecycle(ags_map* map, const int32_t* ids, const uint8_t* actions, int64_t n,
+                      const ags_gaussians* rows, const ags_gaussians* rows_m, const ags_gaussians* rows_v,
+                      ags_gaussians* out, ags_gaussians* out_m, ags_gaussians* out_v, int32_t* out_ids,
+                      ags_map_counts* counts, void* stream);
+
 /* Waits until the host store holds the rows the last call offloaded; AGS_ERR_HIP if their
  * copy failed. */
 int ags_map_sync(ags_map* map);
 
 /* Copies per-id state to host memory (any pointer may be NULL): keys[n_ids], last_used[n_ids],
- * resident[n_ids] (1 on the GPU, 0 in the host store); and, for table_slots (>= the table's
- * slot count, reported in *n_slots), the table's keys and ids (empty slot: key 2^64 - 1,
- * id -1).  Synchronous. */
+ * resident[n_ids] (state: 0 offloaded, 1 resident, 2 retired); and, for table_slots (>= the
+ * table's slot count, reported in *n_slots), the table's keys and values (a slot keeps a key
+ * once entered; its value is the group's smallest live id, -1 while the group is empty; an
+ * empty slot: key 2^64 - 1, value -1).  Synchronous. */
 int ags_map_export(ags_map* map, uint64_t* keys, int32_t* last_used, uint8_t* resident, uint64_t* table_keys,
                    int32_t* table_ids, int64_t table_slots, int64_t* n_ids, int64_t* n_slots);
 
 /* Rows of offloaded ids from the host store into host memory rows[n][3 F] (F = 11 + 3 (deg+1)^2:
  * parameters, then Adam m, then v; each as means 3, log-scales 3, quaternion 4, logit 1,
- * SH (deg+1)^2 x 3).  INVALID_ARG if an id is out of range or resident. */
+ * SH (deg+1)^2 x 3).  INVALID_ARG if an id is out of range, resident or retired. */
 int ags_map_read_store(ags_map* map, const int32_t* ids, int64_t n, float* rows);
 
 #ifdef __cplusplus

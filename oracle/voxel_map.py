@@ -177,7 +177,9 @@ class VoxelMap:
             del self.rows[j]
             self.retired.add(j)
         assert len(ids) == len(out_params["means"])
-        f32 = lambda d, r: {k: np.asarray(d[k][r], np.float32).copy() for k in FIELDS}
+        K = (self.vp.sh_degree + 1) ** 2
+        shape = {"means": (3,), "log_scales": (3,), "quats": (4,), "opacity_logits": (1,), "sh": (K, 3)}
+        f32 = lambda d, r: {k: np.asarray(d[k][r], np.float32).reshape(shape[k]).copy() for k in FIELDS}
         for r, j in enumerate(ids):
             self.rows[j] = {"params": f32(out_params, r), "m": f32(out_m, r), "v": f32(out_v, r)}
         self.resident = ids

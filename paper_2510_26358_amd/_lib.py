@@ -26,7 +26,7 @@ EXPORTED = [
     "ags_render_fwd", "ags_render_bwd", "ags_render_bwd_adam", "ags_bin_records", "ags_adam_step", "ags_pose_step",
     "ags_profile_enable", "ags_profile_read", "ags_profile_reset", "ags_lifecycle_workspace",
     "ags_lifecycle_step", "ags_lifecycle_step_noalloc", "ags_tune", "ags_map_config_default", "ags_map_create", "ags_map_destroy", "ags_map_insert",
-    "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
+    "ags_map_lifecycle", "ags_map_export", "ags_map_read_store", "ags_map_sync", "ags_check_finite",
 ]
 
 
@@ -62,7 +62,8 @@ class MapConfig(C.Structure):
 
 class MapCounts(C.Structure):
     _fields_ = [("n_ids", C.c_int64), ("n_resident", C.c_int64), ("n_new", C.c_int64),
-                ("n_reloaded", C.c_int64), ("n_evicted", C.c_int64)]
+                ("n_reloaded", C.c_int64), ("n_evicted", C.c_int64), ("n_offloaded", C.c_int64),
+                ("n_retired", C.c_int64)]
 
 
 class Lifecycle(C.Structure):
@@ -163,6 +164,8 @@ def load(path: str = LIB_PATH):
     lib.ags_map_destroy.argtypes = [vp]
     lib.ags_map_insert.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, P(Gaussians), P(Gaussians), P(Gaussians), vp,
                                    P(Gaussians), P(Gaussians), P(Gaussians), vp, vp, vp, P(MapCounts), vp]
+    lib.ags_map_lifecycle.argtypes = [vp, vp, vp, C.c_int64, P(Gaussians), P(Gaussians), P(Gaussians),
+                                      P(Gaussians), P(Gaussians), P(Gaussians), vp, P(MapCounts), vp]
     lib.ags_map_export.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, P(C.c_int64), P(C.c_int64)]
     lib.ags_map_read_store.argtypes = [vp, vp, C.c_int64, vp]
     lib.ags_map_sync.argtypes = [vp]

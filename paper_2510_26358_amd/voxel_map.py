@@ -1,11 +1,15 @@
 """Voxel-hashed Gaussian map with a bounded GPU-resident set (Sec. III-B, "Incremental
-Gaussian Mapping" and "Memory Management"), over the ags_map_* calls of libagsplat.
+Gaussian Mapping" and "Memory Management", with the lifecycle operations over its splats),
+over the ags_map_* calls of libagsplat.
 
 Argument marshalling only: every step runs in the library (the rules are stated with
-ags_map_insert in include/agsplat.h).  The map keeps two buffer sets for the resident set
-(parameters, Adam moments, ids) of `tau` rows each and alternates between them; `params`,
-`m`, `v` and `ids` are views of the current set, packed with row stride `n`, ready for the
-rasteriser and the optimiser (which may change their values in place, not their rows).
+ags_map_insert and ags_map_lifecycle in include/agsplat.h).  The map keeps two buffer sets
+for the resident set (parameters, Adam moments, ids) of at least `tau` rows each and
+alternates between them; `params`, `m`, `v` and `ids` are views of the current set, packed
+with row stride `n`, ready for the rasteriser and the optimiser (which may change their
+values in place, not their rows).  A lifecycle pass writes its output rows into a scratch
+set, which ags_map_lifecycle packs into the other set (both grown to twice the resident rows
+when needed).
 """
 from __future__ import annotations
 
@@ -41,6 +45,8 @@ class VoxelMap:
         self.cur = 0
         self.n = 0
         self.n_ids = 0
+        self.n_offloaded = 0
+        self.scratch = None
 
     def _alloc(self, cap):
         rows = list(FIELD_ROWS) + [3 * self.K]
@@ -51,9 +57,9 @@ class VoxelMap:
         a = buf["arrays"][t]
         return L.Gaussians(n, self.sh_degree, *[x.data_ptr() for x in a])
 
-    def _view(self, t):
-        a = self.bufs[self.cur]["arrays"][t]
-        n = self.n
+    def _view(self, t, buf=None, n=None):
+        a = (buf or self.bufs[self.cur])["arrays"][t]
+        n = self.n if n is None else n
         return SplatParams(a[0][:3 * n].view(3, n), a[1][:3 * n].view(3, n), a[2][:4 * n].view(4, n), a[3][:n],
                            a[4][:3 * self.K * n].view(self.K, 3, n), self.sh_degree)
 
@@ -82,7 +88,8 @@ class VoxelMap:
         ins = [self._gaussians(src, t, self.n) for t in range(3)]
         outs = [self._gaussians(dst, t, dst["cap"]) for t in range(3)]
         point_id = torch.empty(max(M, 1), dtype=torch.int32, device=self.device)
-        ev = torch.empty(max(M, 1), dtype=torch.int32, device=self.device) if evicted else None
+        n_ev = max(M, self.n + M + self.n_offloaded - self.tau, 1)
+        ev = torch.empty(n_ev, dtype=torch.int32, device=self.device) if evicted else None
         cnt = L.MapCounts()
         rc = self.lib.ags_map_insert(self.h, points.data_ptr() if M else None, colors.data_ptr() if M else None, M,
                                      int(frame), C.byref(ins[0]), C.byref(ins[1]), C.byref(ins[2]),
@@ -90,19 +97,50 @@ class VoxelMap:
                                      dst["ids"].data_ptr(), point_id.data_ptr(),
                                      ev.data_ptr() if ev is not None else None, C.byref(cnt), _stream())
         L.check(rc, "ags_map_insert", self.ctx)
+        counts = self._advance(cnt)
+        res = (point_id[:M], counts)
+        return res + (ev[:counts["n_evicted"]],) if evicted else res
+
+    def _advance(self, cnt):
         self.cur = 1 - self.cur
         self.n = int(cnt.n_resident)
         self.n_ids = int(cnt.n_ids)
-        counts = {k: int(getattr(cnt, k)) for k, _ in L.MapCounts._fields_}
-        res = (point_id[:M], counts)
-        return res + (ev[:counts["n_evicted"]],) if evicted else res
+        self.n_offloaded = int(cnt.n_offloaded)
+        return {k: int(getattr(cnt, k)) for k, _ in L.MapCounts._fields_}
+
+    def lifecycle(self, ras: Rasterizer, lp, stats=None, noise=None):
+        """One lifecycle pass (prune / densify / reset, ags_lifecycle_step) over the resident
+        set, then the map's side of it (ags_map_lifecycle).  stats: (grad_accum, count) per
+        resident row, noise: (n, 2, 3) standard normals, as Rasterizer.lifecycle takes them.
+        Returns (actions (n,) uint8, counts dict, the pass's own output count)."""
+        n = self.n
+        if self.scratch is None or self.scratch["cap"] < 2 * n:
+            self.scratch = self._alloc(max(2 * n, 1))
+        if self.bufs[1 - self.cur]["cap"] < 2 * n:
+            self.bufs[1 - self.cur] = self._alloc(max(2 * n, self.tau))
+        sc, dst = self.scratch, self.bufs[1 - self.cur]
+        outs = [self._view(t, sc, sc["cap"]) for t in range(3)]
+        n_out = torch.zeros(1, dtype=torch.int32, device=self.device)
+        actions = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        ws = torch.empty(max(ras.lifecycle_workspace(n), 1), dtype=torch.uint8, device=self.device)
+        ras.lifecycle_into(self.params, self.m, self.v, lp, outs, n_out, actions, ws, stats=stats, noise=noise)
+        rows = [self._gaussians(sc, t, sc["cap"]) for t in range(3)]
+        dsts = [self._gaussians(dst, t, dst["cap"]) for t in range(3)]
+        cnt = L.MapCounts()
+        rc = self.lib.ags_map_lifecycle(self.h, self.ids.data_ptr() if n else None,
+                                        actions.data_ptr() if n else None, n, C.byref(rows[0]), C.byref(rows[1]),
+                                        C.byref(rows[2]), C.byref(dsts[0]), C.byref(dsts[1]), C.byref(dsts[2]),
+                                        dst["ids"].data_ptr(), C.byref(cnt), _stream())
+        L.check(rc, "ags_map_lifecycle", self.ctx)
+        return actions[:n], self._advance(cnt), int(n_out.item())
 
     def sync(self):
         """Wait until the host store holds the rows the last insertion offloaded."""
         L.check(self.lib.ags_map_sync(self.h), "ags_map_sync", self.ctx)
 
     def export(self):
-        """Per-id keys (uint64), last_used (int32), resident (bool), and the table's keys / ids."""
+        """Per-id keys (uint64), last_used (int32), state (uint8: 0 offloaded, 1 resident,
+        2 retired) and resident (bool), and the table's keys / values."""
         n_ids, n_slots = C.c_int64(), C.c_int64()
         L.check(self.lib.ags_map_export(self.h, None, None, None, None, None, 0, C.byref(n_ids), C.byref(n_slots)),
                 "ags_map_export", self.ctx)
@@ -114,8 +152,8 @@ class VoxelMap:
         ti = np.zeros(S, np.int32)
         L.check(self.lib.ags_map_export(self.h, keys.ctypes.data, last.ctypes.data, res.ctypes.data, tk.ctypes.data,
                                         ti.ctypes.data, S, None, None), "ags_map_export", self.ctx)
-        return {"keys": keys[:I], "last_used": last[:I], "resident": res[:I].astype(bool), "table_keys": tk,
-                "table_ids": ti}
+        return {"keys": keys[:I], "last_used": last[:I], "state": res[:I].copy(), "resident": res[:I] == 1,
+                "table_keys": tk, "table_ids": ti}
 
     def read_store(self, ids) -> np.ndarray:
         """Rows (n, 3, F) of offloaded ids from the host store: parameters, m, v."""

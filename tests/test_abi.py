@@ -123,6 +123,9 @@ def test_lifecycle_and_map_host_calls(lib):
     assert lib.ags_map_create(None, C.byref(cfg), C.byref(h)) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_map_insert(None, None, None, 0, 0, None, None, None, None, None, None, None, None, None, None,
                               None, None) == L.AGS_ERR_INVALID_ARG
+    cnt = L.MapCounts()
+    assert lib.ags_map_lifecycle(None, None, None, 0, None, None, None, None, None, None, None, C.byref(cnt),
+                                 None) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_map_sync(None) == L.AGS_ERR_INVALID_ARG
     assert lib.ags_map_destroy(None) == L.AGS_ERR_INVALID_ARG
 
