@@ -64,8 +64,9 @@ enum {
  * the diagonal of Sigma', z_near 0.2 (Gaussians closer are culled), fov_clamp 1.3 (x/z
  * and y/z clamped to +-1.3 half-FOV tangents inside J only), bg = 0, tile 16, batch 256,
  * one pixel per thread, backward shape = forward shape.  The supported (tile, batch,
- * pixels per thread) launch shapes are (8,64,1) (8,128,1) (16,128,1) (16,256,1) (16,128,2)
- * (16,256,2) (16,64,4) (32,256,4) (32,512,2); others give AGS_ERR_NOT_SUPPORTED at launch. */
+ * pixels per thread) launch shapes are (8,64,1) (8,128,1) (16,128,1) (16,256,1) (16,64,2)
+ * (16,128,2) (16,256,2) (16,64,4) (32,256,4) (32,512,2); others give AGS_ERR_NOT_SUPPORTED at
+ * launch. */
 typedef struct ags_config {
     float alpha_min, alpha_max, t_min, blur, z_near, fov_clamp;
     float bg[3];

@@ -516,7 +516,7 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
     float* partials = at<float>(ws, L.b_partials);
     {
         Scope sc(ctx, ST_CLEAR, s);
-        launch_fill_f32(grad2d, 0.f, L.Q * kGrad2dStride, s);
+        launch_clear_grad2d(grad2d, at<uint32_t>(saved, L.s_pair_count), L.Q, s);
         if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
         if (rendered_var && n_targets > 0) launch_fill_f32(ddepth2, 0.f, L.P, s);
         if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, lidar_blocks(0), s);

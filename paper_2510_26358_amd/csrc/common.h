@@ -13,7 +13,7 @@ constexpr int kRecFloats = 12;       // projected record: u v a b c o z ex ey r 
 // per-pair 2D adjoint: 5 pixel moments of dL/dpower (turned into the centre and conic
 // adjoints by the projection backward), then o, r, g, b, z
 constexpr int kGrad2d = 10;
-constexpr int kGrad2dStride = 10;
+constexpr int kGrad2dStride = 16;  // 64-byte rows: a row is one cache line
 
 // Static per-batch table passed by value to kernels (kernel arguments).
 struct ViewTable {
@@ -520,9 +520,11 @@ struct RasterBwdArgs {
     const uint8_t* mask;
     float l1_scale[kMaxViews];   // (1 - lambda_ssim) w_l1 / (3 n_b)
     float* loss_partials;        // one per block (loss mode)
-    float* grad2d;               // [n_pairs][10]
+    float* grad2d;               // [n_pairs][16] (ten used); rows of visible pairs cleared
 };
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
+// Zeroes grad2d's rows of the pairs with pair_count != 0 (the rows raster_bwd adds to).
+void launch_clear_grad2d(float* grad2d, const uint32_t* pair_count, long long n_pairs, hipStream_t s);
 int raster_blocks(const ViewTable& vt);
 // Raster work list: strips of kWorkStrip consecutive tiles go round-robin to the eight XCDs
 // (workgroup g runs on XCD g % 8); each XCD takes its strips' tiles longest list first.

@@ -22,8 +22,13 @@
 // it keeps five pixel moments without the factor o (sum h dx, h dy, h dx^2, h dx dy,
 // h dy^2); the projection backward applies o and turns them into the centre and conic
 // adjoints.  dL/drgb_k = w_k gC, dL/dz_k = w_k gD.  The ten per-Gaussian
-// sums of a wave are reduced with a transposing butterfly so one atomic instruction with
-// ten active lanes updates the pair's adjoint.
+// sums of a wave are reduced with a transposing butterfly to ten lanes.  With LDS batches of
+// at most 64 records those lanes add them into the batch's LDS accumulator of that Gaussian
+// (the workgroup's waves merge there), and after the batch one global atomic per (Gaussian,
+// non-zero sum) adds the workgroup's total into the pair's 64-byte adjoint row, so each row
+// is updated once per tile; with larger batches (where the accumulator's LDS would cut the
+// number of resident workgroups) one atomic instruction of the ten lanes per wave updates
+// the row.
 #include "common.h"
 
 namespace ags {
@@ -284,7 +289,11 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
 template <int T, int PPT, int M, bool GA, bool S2>
 __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a) {
     constexpr int NT = T * T / PPT;
+    // merge the waves' sums in LDS where that keeps the workgroup within 8 KB of LDS
+    constexpr bool MERGE = M <= 64 && NT > 64;
     __shared__ SRec srec[M];
+    __shared__ float sacc[MERGE ? M * kGrad2d : 1];  // per LDS slot: the workgroup's ten sums
+    __shared__ uint32_t sq[2][MERGE ? M : 1];        // the pairs of this batch and the previous
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
     const uint32_t wt = a.work[blockIdx.x];
@@ -361,6 +370,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         if (lane == 0) sred[tid >> 6] = s;
     }
     if (tid == 0) smax = 0;
+    if (MERGE)
+        for (int l = tid; l < M * kGrad2d; l += NT) sacc[l] = 0.f;
     __syncthreads();
     atomicMax(&smax, mylast);
     if (a.loss_mode && tid == 0) {
@@ -384,11 +395,28 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const bool red_lane = (lane & 3) == 0 && sl != 3 && sl < 6;
     const int red_val = (sl < 3 ? sl : sl - 1) + 5 * (slot >> 3);
 
-    for (int hi = (int)maxlast; hi > 0; hi -= M) {
+    // the batch's totals into the pairs' rows, one global atomic per (Gaussian, non-zero sum);
+    // the accumulator is left zero for the next batch
+    auto flush = [&](int n, const uint32_t* q) {
+        for (int l = tid; l < n * kGrad2d; l += NT) {
+            const float x = sacc[l];
+            if (x != 0.f) {
+                const int e = l / kGrad2d;
+                atomicAdd(a.grad2d + (long long)q[e] * kGrad2dStride + (l - e * kGrad2d), x);
+                sacc[l] = 0.f;
+            }
+        }
+    };
+    int prev_n = 0, buf = 0;
+    for (int hi = (int)maxlast; hi > 0; hi -= M, buf ^= 1) {
         const int lo = hi - M > 0 ? hi - M : 0;
-        for (int l = tid; l < hi - lo; l += NT)
-            stage_record<T, PPT, true>(a.records, a.tile_pairs[start + lo + l], amin, tc.W, tc.H, tc.px0,
-                                       tc.py0, srec[l]);
+        if (MERGE) flush(prev_n, sq[buf ^ 1]);  // the previous batch, while this one is staged
+        for (int l = tid; l < hi - lo; l += NT) {
+            const uint32_t q = a.tile_pairs[start + lo + l];
+            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
+            if (MERGE) sq[buf][l] = q;
+        }
+        prev_n = hi - lo;
         __syncthreads();
         const int jtop = min(hi, wl);  // wave-uniform
         int e = jtop - 1 - lo;         // LDS slot, advanced in a vector register
@@ -448,10 +476,51 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 for (int s = 0; s < 10; ++s) g[s] = k == 0 ? c[s] : g[s] + c[s];
             }
             const float tot = wave_transpose_sum10(g);
-            if (red_lane) atomicAdd(a.grad2d + (long long)r.q * kGrad2dStride + red_val, tot);
+            if (MERGE) {
+                if (red_lane) atomicAdd(&sacc[e * kGrad2d + red_val], tot);
+            } else {
+                if (red_lane) atomicAdd(a.grad2d + (long long)r.q * kGrad2dStride + red_val, tot);
+            }
         }
         __syncthreads();
     }
+    if (MERGE) flush(prev_n, sq[buf ^ 1]);
+}
+
+// Zeroes the adjoint rows of the pairs some tile lists (the only rows the backward adds to
+// and the projection backward reads).  A thread takes four consecutive pairs: one 16-byte
+// load of their counts, then the stores of the visible ones' 64-byte rows, so no store waits
+// on more than one load.
+static_assert(kGrad2dStride == 16, "four float4 stores per row");
+
+__global__ __launch_bounds__(256) void clear_grad2d_kernel(float* __restrict__ grad2d,
+                                                          const uint32_t* __restrict__ pair_count, long long n) {
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;  // pairs 4 g .. 4 g + 3
+    const long long q0 = 4 * g;
+    if (q0 >= n) return;
+    uint32_t c[4];
+    if (q0 + 4 <= n) {
+        const uint4 v = reinterpret_cast<const uint4*>(pair_count)[g];  // pair_count is 16-byte aligned
+        c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = q0 + j < n ? pair_count[q0 + j] : 0u;
+    }
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!c[j]) continue;
+        float4* row = reinterpret_cast<float4*>(grad2d + (q0 + j) * kGrad2dStride);
+#pragma unroll
+        for (int k = 0; k < kGrad2dStride / 4; ++k) row[k] = z;
+    }
+}
+
+void launch_clear_grad2d(float* grad2d, const uint32_t* pair_count, long long n_pairs, hipStream_t s) {
+    if (n_pairs <= 0) return;
+    const long long groups = (n_pairs + 3) / 4;
+    hipLaunchKernelGGL(clear_grad2d_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, grad2d,
+                       pair_count, n_pairs);
 }
 
 int raster_blocks(const ViewTable& vt) {
@@ -466,6 +535,7 @@ int raster_blocks(const ViewTable& vt) {
     X(8, 1, 128)              \
     X(16, 1, 128)             \
     X(16, 1, 256)             \
+    X(16, 2, 64)              \
     X(16, 2, 128)             \
     X(16, 2, 256)             \
     X(16, 4, 64)              \

@@ -16,8 +16,8 @@ from tests.oracle_helpers import random_scene
 
 pytestmark = pytest.mark.gpu
 
-SUPPORTED = {(8, 64, 1), (8, 128, 1), (16, 128, 1), (16, 256, 1), (16, 128, 2), (16, 256, 2), (16, 64, 4),
-             (32, 256, 4), (32, 512, 2)}
+SUPPORTED = {(8, 64, 1), (8, 128, 1), (16, 128, 1), (16, 256, 1), (16, 64, 2), (16, 128, 2), (16, 256, 2),
+             (16, 64, 4), (32, 256, 4), (32, 512, 2)}
 
 
 def _inputs(seed=501):

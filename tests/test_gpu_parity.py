@@ -293,12 +293,14 @@ def test_loss_and_gradients_sh3_lidar(ras, seed, n_views):
 
 
 # Every (tile, LDS batch, pixels per thread) launch shape the library accepts, each used for
-# both passes, and two forward/backward pairs of different shapes on one tile size: the
-# benchmark's autotuner may pick any of them.  Two 70x45 views (ragged tiles for 8, 16 and 32),
+# both passes, and three forward/backward pairs of different shapes on one tile size: the
+# benchmark's autotuner may pick any of them (backward batches of 64 records with two waves
+# merge the waves' sums in LDS; the others add them per wave).  Two 70x45 views (ragged tiles for 8, 16 and 32),
 # up to ~90 contributors per pixel, so the 64- and 128-record batches loop.
-_SHAPES = [(8, 64, 1), (8, 128, 1), (16, 128, 1), (16, 256, 1), (16, 128, 2), (16, 256, 2), (16, 64, 4),
-           (32, 256, 4), (32, 512, 2)]
-_SHAPE_CASES = [(s, s[1:]) for s in _SHAPES] + [((16, 256, 1), (128, 2)), ((16, 64, 4), (256, 1))]
+_SHAPES = [(8, 64, 1), (8, 128, 1), (16, 128, 1), (16, 256, 1), (16, 64, 2), (16, 128, 2), (16, 256, 2),
+           (16, 64, 4), (32, 256, 4), (32, 512, 2)]
+_SHAPE_CASES = [(s, s[1:]) for s in _SHAPES] + [((16, 256, 1), (128, 2)), ((16, 256, 1), (64, 2)),
+                                                ((16, 64, 4), (256, 1))]
 _shape_ref = {}
 
 
