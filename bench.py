@@ -356,7 +356,7 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
         "binning": 8 * Q + 84 * V + 44 * K,
         "lidar_adjoint": 16 * n_targets,
         "project_bwd": 2 * 4 * F * N + 56 * V + 24 * N,
-        "clear": 40 * Q + 4 * P,
+        "clear": 4 * Q + 64 * V + 4 * P,
         "raster_fwd": 28 * P,
         "raster_bwd": 44 * P,
     }
