@@ -242,6 +242,7 @@ def measure_voxel_map(ras, args, n_points=1 << 20, tau=1 << 20, warm_calls=8, ti
     prof = ras.profile_read()
     ras.profile(False)
     stage = {k: round(v[0] / timed_calls, 4) for k, v in prof.items() if k.startswith("map_") and v[1] > 0}
+    life = lifecycle_over_map(ras, gm, gen, warm_calls + timed_calls)
     mean = lambda k: sum(r[k] for r in recs) / len(recs)
     wall, flush, rebuild, pcie = mean(0), mean(1), mean(2), mean(3)
     reb_ms = stage.get("map_rebuild", float("nan"))
@@ -257,7 +258,8 @@ def measure_voxel_map(ras, args, n_points=1 << 20, tau=1 << 20, warm_calls=8, ti
            "pcie_gbs": round(pcie / (stage.get("map_copy", float("nan")) * 1e-3) / 1e9, 2),
            "roofline": {"kernel": "map_rebuild_kernel", "bound": "hbm", "achieved": round(gbs, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                        "bytes_per_launch": round(rebuild)}}
+                        "bytes_per_launch": round(rebuild)},
+           "lifecycle_pass": life}
     log(f"[bench] voxel map: {wall:.3f} ms/call wall, {res}")
     gm.close()
     del gm
@@ -558,6 +560,36 @@ def oracle_other_configs():
                           "cores": th or torch.get_num_threads(), "seconds": round(dt, 2)}
         out[name] = rec
     return out
+
+
+def lifecycle_over_map(ras, gm, gen, frame):
+    """A lifecycle pass over the map's full resident set (ags_lifecycle_step, then
+    ags_map_lifecycle: retirements, new ids keyed like their parents, the rows packed into the
+    resident set), then the next insertion call, which offloads the rows above tau.  The
+    densification statistic is seeded (every row seen once, |dL/d(u, v)| uniform in [0, 0.04]
+    px, so about half the rows pass gamma_g = 0.02 and, at the new splats' size, are
+    duplicated).  Wall times, host-synchronous (ags_map_lifecycle reads its counts back)."""
+    import torch
+    from paper_2510_26358_amd.rasterizer import LifecycleParams
+    n = gm.n
+    count = torch.ones(n, device="cuda")
+    accum = torch.rand(n, device="cuda", generator=gen) * 0.04
+    noise = torch.randn(n, 2, 3, device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    acts, c, _ = gm.lifecycle(ras, LifecycleParams(do_prune=True, do_densify=True, do_reset=False),
+                              stats=(accum, count), noise=noise)
+    life_ms = (time.perf_counter() - w0) * 1e3
+    pts = torch.rand(1 << 16, 3, device="cuda", generator=gen) * 3.0
+    cols = torch.rand(1 << 16, 3, device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    _, c2 = gm.insert(pts, cols, frame)
+    ins_ms = (time.perf_counter() - w0) * 1e3
+    gm.sync()
+    return {"rows_in": n, "rows_out": c["n_resident"], "new_ids": c["n_new"], "retired": c["n_retired"],
+            "ms_wall": round(life_ms, 4), "next_insert_points": 1 << 16, "next_insert_ms_wall": round(ins_ms, 4),
+            "next_insert_evicted": c2["n_evicted"], "resident_after": c2["n_resident"]}
 
 
 def per_view_loop(ras, p, cams, views, tg, grads, loss, steps, warmup):

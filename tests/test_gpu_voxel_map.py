@@ -384,3 +384,95 @@ def test_map_lifecycle_refusals(ras):
         assert gm.export()["keys"].tolist() == before["keys"].tolist()
     finally:
         gm.close()
+
+
+def _group_minimum(keys, state):
+    """Smallest live id of every key (numpy): dict key -> id."""
+    ids = np.nonzero(state != 2)[0]
+    k = keys[ids]
+    order = np.lexsort((ids, k))
+    k, ids = k[order], ids[order]
+    first = np.ones(len(k), bool)
+    first[1:] = k[1:] != k[:-1]
+    return dict(zip(k[first].tolist(), ids[first].tolist()))
+
+
+def test_map_lifecycle_at_full_size(ras):
+    """The bench's map size (2^20 points per call, resident bound 2^20, SH degree 3): after
+    three insertion calls, a lifecycle pass over the full resident set (every row's action
+    drawn: keep, prune, duplicate, split), then an insertion call revisiting the first call's
+    region.  Checked by the rules: the pass's output ids (first output keeps the id, second
+    outputs numbered in input order), the new ids' keys and last uses (their parents'),
+    retired states, every table value the smallest live id of its key (or -1), and after the
+    insertion every point's id its group's smallest, every member of a hit group used, and
+    the least-recently-used property of the resident set."""
+    from paper_2510_26358_amd.rasterizer import LifecycleParams
+    from paper_2510_26358_amd.voxel_map import VoxelMap
+    rng = np.random.default_rng(406)
+    vp = VoxelMapParams(voxel=0.05, tau=1 << 20, sh_degree=3)
+    gm = VoxelMap(ras, voxel=vp.voxel, sh_degree=3, tau=vp.tau, max_ids=1 << 23, max_points=1 << 20)
+    try:
+        first = None
+        for t in range(3):
+            pts, cols = _frame(rng, t, 1 << 20, spread=4.0, step=6.0)
+            if t == 0:
+                first = pts
+            gm.insert(torch.from_numpy(pts).cuda(), torch.from_numpy(cols).cuda(), t)
+        ex0 = gm.export()
+        ids0 = gm.ids.cpu().numpy().astype(np.int64)
+        n, n_ids0 = gm.n, len(ex0["keys"])
+        want = rng.choice([olc.KEEP, olc.PRUNE, olc.CLONE, olc.SPLIT], n, p=[0.5, 0.15, 0.2, 0.15])
+        ls = np.array([_FORCED[a][0] for a in range(4)], np.float32)[want]
+        logit = np.array([_FORCED[a][1] for a in range(4)], np.float32)[want]
+        accum = np.array([_FORCED[a][2] for a in range(4)], np.float32)[want]
+        count = np.where(accum > 0, 2.0, 0.0).astype(np.float32)
+        gm.params.log_scales.copy_(torch.from_numpy(np.repeat(ls[None, :], 3, 0)).cuda())
+        gm.params.opacity_logits.copy_(torch.from_numpy(logit).cuda())
+        noise = torch.from_numpy(rng.normal(size=(n, 2, 3)).astype(np.float32)).cuda()
+        acts, c, n_out = gm.lifecycle(ras, LifecycleParams(do_reset=False),
+                                      stats=(torch.from_numpy(accum).cuda(), torch.from_numpy(count).cuda()),
+                                      noise=noise)
+        assert np.array_equal(acts.cpu().numpy().astype(np.int64), want)
+        two = (want == olc.CLONE) | (want == olc.SPLIT)
+        new_ids = n_ids0 + np.cumsum(two) - 1                  # second output's id, where two
+        outs = np.zeros((n, 2), np.int64) - 1
+        outs[want != olc.PRUNE, 0] = ids0[want != olc.PRUNE]
+        outs[two, 1] = new_ids[two]
+        expect = outs[outs >= 0]                                # row-major: input order, first then second
+        assert c["n_resident"] == n_out == len(expect) and c["n_new"] == int(two.sum())
+        assert c["n_retired"] == int((want == olc.PRUNE).sum())
+        assert np.array_equal(gm.ids.cpu().numpy().astype(np.int64), expect)
+        ex1 = gm.export()
+        keys1, last1, st1 = ex1["keys"], ex1["last_used"], ex1["state"]
+        assert len(keys1) == n_ids0 + int(two.sum())
+        parents = ids0[two]
+        assert np.array_equal(keys1[new_ids[two]], ex0["keys"][parents])
+        assert np.array_equal(last1[new_ids[two]], ex0["last_used"][parents])
+        assert np.all(st1[new_ids[two]] == 1) and np.all(st1[ids0[want == olc.PRUNE]] == 2)
+        unchanged = np.ones(n_ids0, bool)
+        unchanged[ids0[want == olc.PRUNE]] = False
+        assert np.array_equal(st1[:n_ids0][unchanged], ex0["state"][unchanged])
+        gmin = _group_minimum(keys1, st1)
+        occ = ex1["table_keys"] != np.uint64(2 ** 64 - 1)
+        got = dict(zip(ex1["table_keys"][occ].tolist(), ex1["table_ids"][occ].tolist()))
+        assert got == {k: gmin.get(k, -1) for k in got}
+        assert set(gmin) <= set(got)
+        print("pass", c, "emptied keys", sum(1 for v in got.values() if v < 0))
+        # a revisit of the first call's region: group reloads and the group minimum
+        pts = first[rng.choice(len(first), 1 << 19, replace=False)]
+        pid, c2 = gm.insert(torch.from_numpy(pts).cuda(), torch.from_numpy(np.zeros_like(pts)).cuda(), 3)
+        pid = pid.cpu().numpy().astype(np.int64)
+        ex2 = gm.export()
+        gmin2 = _group_minimum(ex2["keys"], ex2["state"])
+        pk = voxel_keys(pts, vp)
+        assert np.array_equal(pid, np.array([gmin2[int(k)] for k in pk]))
+        hit = np.isin(ex2["keys"], np.unique(pk)) & (ex2["state"] != 2)
+        assert np.all(ex2["last_used"][hit] == 3)
+        assert c2["n_resident"] <= vp.tau and c2["n_reloaded"] > 0
+        res = ex2["state"] == 1
+        off = ex2["state"] == 0
+        assert ex2["last_used"][off].max() <= ex2["last_used"][res].min()
+        assert np.array_equal(np.sort(gm.ids.cpu().numpy()), np.nonzero(res)[0])
+        print("revisit", c2)
+    finally:
+        gm.close()
