@@ -476,3 +476,31 @@ def test_map_lifecycle_at_full_size(ras):
         print("revisit", c2)
     finally:
         gm.close()
+
+
+def test_map_lifecycle_edge_cases(ras):
+    """A pass over an empty resident set changes nothing; a pass that prunes every row empties
+    every key (the resident set becomes empty, every id retired); the next insertion call at
+    the same voxels makes new splats with new ids, as the oracle does."""
+    from paper_2510_26358_amd.rasterizer import LifecycleParams
+    from paper_2510_26358_amd.voxel_map import VoxelMap
+    vp = VoxelMapParams(voxel=1.0, tau=8, sh_degree=0, s_init=0.005, o_init=0.2)
+    om = OracleMap(vp)
+    gm = VoxelMap(ras, voxel=1.0, sh_degree=0, tau=8, max_ids=64, max_points=8, s_init=0.005, o_init=0.2)
+    try:
+        acts, c, n_out = gm.lifecycle(ras, LifecycleParams(do_reset=False))
+        assert c["n_resident"] == 0 and c["n_ids"] == 0 and n_out == 0 and len(acts) == 0
+        pts = (np.arange(18, dtype=np.float32).reshape(6, 3) * 3.0 + 0.5).astype(np.float32)
+        cols = np.full((6, 3), 0.5, np.float32)
+        r_ora = om.insert(pts, cols, 0)
+        r_gpu, counts, ev = gm.insert(torch.from_numpy(pts).cuda(), torch.from_numpy(cols).cuda(), 0, evicted=True)
+        _compare(gm, om, r_gpu, r_ora, counts, ev)
+        approx = _lifecycle_step(gm, om, ras, np.random.default_rng(1), [0.0, 1.0, 0.0, 0.0], set())
+        assert gm.n == 0 and not om.table and len(approx) == 0
+        assert (gm.export()["state"] == 2).all()
+        r_ora = om.insert(pts, cols, 1)
+        r_gpu, counts, ev = gm.insert(torch.from_numpy(pts).cuda(), torch.from_numpy(cols).cuda(), 1, evicted=True)
+        assert r_ora["new"] == list(range(6, 12))
+        _compare(gm, om, r_gpu, r_ora, counts, ev)
+    finally:
+        gm.close()

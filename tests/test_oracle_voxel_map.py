@@ -233,3 +233,16 @@ def test_invariants_of_random_sequences_with_lifecycle_passes():
         assert len(set(m.resident)) == len(m.resident) <= vp.tau and set(m.rows) == set(m.resident)
         if m.store and m.resident:
             assert max(m.last_used[j] for j in m.store) <= min(m.last_used[j] for j in m.resident)
+
+
+def test_pruning_every_splat_empties_the_map():
+    vp = VoxelMapParams(voxel=1.0, tau=4, sh_degree=0)
+    m = VoxelMap(vp)
+    z = lambda n: np.zeros((n, 3), np.float32)
+    m.insert(np.concatenate([_cube(0), _cube(1), _cube(0)]), z(3), 0)
+    r = _lifecycle(m, [PRUNE, PRUNE])
+    assert r == {"ids": [], "new": [], "retired": [0, 1]} and not m.table and m.resident == []
+    # the same voxels again: new splats, new ids (ids are never reused)
+    r = m.insert(np.concatenate([_cube(1), _cube(0)]), z(2), 1)
+    assert r["new"] == [2, 3] and r["point_id"].tolist() == [2, 3] and m.resident == [2, 3]
+    assert m.state(0) == RETIRED and m.state(2) == RESIDENT
