@@ -516,12 +516,22 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
     float* partials = at<float>(ws, L.b_partials);
     {
         Scope sc(ctx, ST_CLEAR, s);
-        launch_clear_grad2d(grad2d, at<uint32_t>(saved, L.s_pair_count), L.Q, s);
-        if (loss && n_targets > 0) launch_fill_f32(ddepth, 0.f, L.P, s);
-        if (rendered_var && n_targets > 0) launch_fill_f32(ddepth2, 0.f, L.P, s);
-        if (loss && n_targets == 0) launch_fill_f32(partials + L.n_tiles, 0.f, lidar_blocks(0), s);
-        if (loss && !(loss->ssim_weight > 0.f))
-            launch_fill_f32(partials + L.n_tiles + lidar_blocks(0), 0.f, L.n_ssim, s);
+        BwdClearArgs ca;
+        memset(&ca, 0, sizeof(ca));
+        ca.grad2d = grad2d;
+        ca.pair_count = at<uint32_t>(saved, L.s_pair_count);
+        ca.n_pairs = L.Q;
+        int r = 0;
+        auto zero = [&](float* p, long long n) {
+            ca.zero[r] = p;
+            ca.zero_n[r] = n;
+            ++r;
+        };
+        if (loss && n_targets > 0) zero(ddepth, L.P);
+        if (rendered_var && n_targets > 0) zero(ddepth2, L.P);
+        if (loss && n_targets == 0) zero(partials + L.n_tiles, lidar_blocks(0));
+        if (loss && !(loss->ssim_weight > 0.f)) zero(partials + L.n_tiles + lidar_blocks(0), L.n_ssim);
+        launch_bwd_clear(ca, s);
     }
     RasterBwdArgs ra;
     memset(&ra, 0, sizeof(ra));

@@ -523,8 +523,18 @@ struct RasterBwdArgs {
     float* grad2d;               // [n_pairs][16] (ten used); rows of visible pairs cleared
 };
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
-// Zeroes grad2d's rows of the pairs with pair_count != 0 (the rows raster_bwd adds to).
-void launch_clear_grad2d(float* grad2d, const uint32_t* pair_count, long long n_pairs, hipStream_t s);
+// The backward's clears in one launch: grad2d's rows of the pairs with pair_count != 0 (the
+// rows raster_bwd adds to), and up to kBwdClearRegions float buffers (zero_n[r] floats each;
+// 0 for none).
+constexpr int kBwdClearRegions = 4;
+struct BwdClearArgs {
+    float* grad2d;
+    const uint32_t* pair_count;
+    long long n_pairs;
+    float* zero[kBwdClearRegions];
+    long long zero_n[kBwdClearRegions];
+};
+void launch_bwd_clear(const BwdClearArgs& a, hipStream_t s);
 int raster_blocks(const ViewTable& vt);
 // Raster work list: strips of kWorkStrip consecutive tiles go round-robin to the eight XCDs
 // (workgroup g runs on XCD g % 8); each XCD takes its strips' tiles longest list first.

@@ -487,40 +487,48 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     if (MERGE) flush(prev_n, sq[buf ^ 1]);
 }
 
-// Zeroes the adjoint rows of the pairs some tile lists (the only rows the backward adds to
-// and the projection backward reads).  A thread takes four consecutive pairs: one 16-byte
-// load of their counts, then the stores of the visible ones' 64-byte rows, so no store waits
-// on more than one load.
+// The backward's clears in one launch.  Thread g zeroes the adjoint rows of the pairs
+// 4 g .. 4 g + 3 that some tile lists (the only rows the raster backward adds to and the
+// projection backward reads): one 16-byte load of their counts, then the 64-byte row stores
+// of the visible ones, so no store waits on more than one load; then, striding over the grid,
+// the dense float buffers (LiDAR depth adjoints, unused loss partials).
 static_assert(kGrad2dStride == 16, "four float4 stores per row");
 
-__global__ __launch_bounds__(256) void clear_grad2d_kernel(float* __restrict__ grad2d,
-                                                          const uint32_t* __restrict__ pair_count, long long n) {
-    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;  // pairs 4 g .. 4 g + 3
+__global__ __launch_bounds__(256) void bwd_clear_kernel(BwdClearArgs a) {
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long q0 = 4 * g;
-    if (q0 >= n) return;
-    uint32_t c[4];
-    if (q0 + 4 <= n) {
-        const uint4 v = reinterpret_cast<const uint4*>(pair_count)[g];  // pair_count is 16-byte aligned
-        c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
-    } else {
+    if (q0 < a.n_pairs) {
+        uint32_t c[4];
+        if (q0 + 4 <= a.n_pairs) {
+            const uint4 v = reinterpret_cast<const uint4*>(a.pair_count)[g];  // 16-byte aligned
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] = q0 + j < n ? pair_count[q0 + j] : 0u;
+            for (int j = 0; j < 4; ++j) c[j] = q0 + j < a.n_pairs ? a.pair_count[q0 + j] : 0u;
+        }
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!c[j]) continue;
+            float4* row = reinterpret_cast<float4*>(a.grad2d + (q0 + j) * kGrad2dStride);
+#pragma unroll
+            for (int k = 0; k < kGrad2dStride / 4; ++k) row[k] = z;
+        }
     }
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (!c[j]) continue;
-        float4* row = reinterpret_cast<float4*>(grad2d + (q0 + j) * kGrad2dStride);
-#pragma unroll
-        for (int k = 0; k < kGrad2dStride / 4; ++k) row[k] = z;
-    }
+    const long long stride = (long long)gridDim.x * 256;
+    for (int r = 0; r < kBwdClearRegions; ++r)
+        for (long long i = g; i < a.zero_n[r]; i += stride) a.zero[r][i] = 0.f;
 }
 
-void launch_clear_grad2d(float* grad2d, const uint32_t* pair_count, long long n_pairs, hipStream_t s) {
-    if (n_pairs <= 0) return;
-    const long long groups = (n_pairs + 3) / 4;
-    hipLaunchKernelGGL(clear_grad2d_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, grad2d,
-                       pair_count, n_pairs);
+void launch_bwd_clear(const BwdClearArgs& a, hipStream_t s) {
+    long long most = (a.n_pairs + 3) / 4;
+    for (int r = 0; r < kBwdClearRegions; ++r) {
+        const long long t = (a.zero_n[r] + 3) / 4;  // about four floats per thread
+        most = t > most ? t : most;
+    }
+    if (most <= 0) return;
+    const long long grid = (most + 255) / 256;
+    hipLaunchKernelGGL(bwd_clear_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
 }
 
 int raster_blocks(const ViewTable& vt) {
