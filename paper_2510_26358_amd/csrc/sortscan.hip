@@ -380,28 +380,38 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __shared__ uint32_t ttot[256];                            // digit count of the tile
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
     __shared__ uint32_t wtot[kSortWaves];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    // the digit offsets, the live count and then the first tile's items are loaded before the
+    // prologue's barriers, so their round trips overlap instead of following one another
+    const uint32_t my_rowtot = rowtot[t];
+    const uint32_t my_hist = hist[(long long)t * grid + blockIdx.x];
     const long long n = live_count(n_max, n_dev);
     long long start, end;
     chunk_of_block(n, grid, start, end);
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    {
-        uint32_t total;
-        const uint32_t base = sort_block_scan(rowtot[t], wtot, total);
-        run[t] = base + hist[(long long)t * grid + blockIdx.x];
-        if (drop && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
-    }
-    const uint32_t mask = (1u << dbits) - 1u;
-    uint32_t* const cw = wcnt[w];
-    for (long long base = start; base < end; base += kSortTile) {
+    uint32_t kv[kSortItems], vv[kSortItems];
+    auto load_tile = [&](long long base) {
         const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
-        uint32_t kv[kSortItems], vv[kSortItems], dig[kSortItems], rank[kSortItems];
-        bool on[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const int l = w * WS + k * 64 + lane;
             kv[k] = l < nt ? keys_in[base + l] : 0u;
             vv[k] = l < nt ? (vals_in ? vals_in[base + l] : (uint32_t)(base + l)) : 0u;  // index if no values
         }
+    };
+    if (start < end) load_tile(start);
+    {
+        uint32_t total;
+        const uint32_t base = sort_block_scan(my_rowtot, wtot, total);
+        run[t] = base + my_hist;
+        if (drop && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
+    }
+    const uint32_t mask = (1u << dbits) - 1u;
+    uint32_t* const cw = wcnt[w];
+    for (long long base = start; base < end; base += kSortTile) {
+        const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
+        uint32_t dig[kSortItems], rank[kSortItems];
+        bool on[kSortItems];
+        if (base != start) load_tile(base);
 #pragma unroll
         for (int x = 0; x < kSortWaves; ++x) wcnt[x][t] = 0;
         __syncthreads();
