@@ -504,3 +504,46 @@ def test_map_lifecycle_edge_cases(ras):
         _compare(gm, om, r_gpu, r_ora, counts, ev)
     finally:
         gm.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_map_random_sequences_with_small_staging(ras, seed):
+    """Seeded random plans of insertion calls (random sizes, or a revisit: a sample of the
+    points inserted so far) and lifecycle passes (random action mixes, densification-heavy, so
+    key groups grow) with 4 to 16 staging rows and a small resident bound, so reloads and
+    offloads go through the staging in chunks, either, both or neither in one call; the oracle
+    is compared after every step."""
+    from paper_2510_26358_amd.voxel_map import VoxelMap
+    rng = np.random.default_rng(700 + seed)
+    max_points = int(rng.choice([4, 8, 16]))
+    tau = int(rng.integers(6, 24))
+    deg = int(rng.integers(0, 2))
+    voxel = float(rng.choice([0.5, 1.0]))
+    vp = VoxelMapParams(voxel=voxel, tau=tau, sh_degree=deg, s_init=0.005, o_init=0.2)
+    om = OracleMap(vp)
+    gm = VoxelMap(ras, voxel=voxel, sh_degree=deg, tau=tau, max_ids=8192, max_points=max_points, s_init=0.005,
+                  o_init=0.2)
+    approx, seen, chunked = set(), [], [0, 0]
+    try:
+        for t in range(14):
+            if t > 0 and rng.random() < 0.35:
+                approx = _lifecycle_step(gm, om, ras, rng, rng.dirichlet([1.5, 0.7, 1.5, 1.5]), approx)
+                continue
+            if seen and rng.random() < 0.4:
+                allp = np.concatenate(seen)
+                pts = allp[rng.choice(len(allp), min(len(allp), max_points), replace=False)]
+                cols = np.full((len(pts), 3), 0.25, np.float32)
+            else:
+                n = int(rng.integers(0, max_points + 1))
+                pts, cols = _frame(rng, t, n, spread=1.5, step=0.5)
+                if n:
+                    seen.append(pts)
+            r_ora = om.insert(pts, cols, t)
+            r_gpu, counts, ev = gm.insert(torch.from_numpy(pts).cuda(), torch.from_numpy(cols).cuda(), t,
+                                          evicted=True)
+            chunked[0] += counts["n_reloaded"] > max_points
+            chunked[1] += counts["n_evicted"] > max_points
+            _compare(gm, om, r_gpu, r_ora, counts, ev, approx)
+        print("seed", seed, "max_points", max_points, "tau", tau, "chunked reload / offload calls", chunked)
+    finally:
+        gm.close()
