@@ -335,7 +335,8 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
         if name == "project_bwd":
             by = 4 * F * n_gauss * 2 + 52 * int(v) + 4 * Q
         elif name == "project_fwd":
-            by = 4 * F * n_gauss + 56 * int(v) + 4 * Q
+            # with each visible pair's 64-byte adjoint row zeroed for the backward
+            by = 4 * F * n_gauss + 56 * int(v) + 4 * Q + 64 * int(v)
         elif name == "adam":
             by = 7 * 4 * F * n_gauss
         else:
@@ -351,17 +352,21 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
     (HBM-bound stages) or FLOP (raster) per launch, as listed in the design doc; plus the whole
     step's algorithmic bytes over its time (the HBM fraction of the step).  With the fused
     backward + Adam the projection backward also carries Adam's bytes, less the SH gradient's
-    write and re-read and the second read of the SH coefficients."""
+    write and re-read and the second read of the SH coefficients.  The backward's accumulators
+    are zeroed in the forward (the adjoint rows by the projection, the dense depth adjoint by
+    the raster forward); a separate clear stage runs only for a backward that cannot rely on
+    that."""
     F = 11 + 3 * sh_k
     byts = {
-        "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V,
+        "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V + 64 * V,
         "binning": 8 * Q + 84 * V + 44 * K,
         "lidar_adjoint": 16 * n_targets,
         "project_bwd": 2 * 4 * F * N + 56 * V + 24 * N,
-        "clear": 4 * Q + 64 * V + 4 * P,
-        "raster_fwd": 28 * P,
+        "raster_fwd": 28 * P + 4 * P,
         "raster_bwd": 44 * P,
     }
+    if stage_ms.get("clear", 0) > 0:
+        byts["clear"] = 4 * Q + 64 * V + 4 * P
     if "adam" in stage_ms:
         byts["adam"] = 7 * 4 * F * N
     elif fused_adam:

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define AGS_ABI_VERSION 4
+#define AGS_ABI_VERSION 5
 #define AGS_MAX_VIEWS 32
 
 enum {
@@ -191,7 +191,9 @@ typedef struct ags_loss {
 
 /* Buffer sizes and the layout of the `saved` buffer (byte offsets), for a batch shape. */
 typedef struct ags_sizes {
-    size_t saved_bytes;      /* state the forward leaves for the backward */
+    size_t saved_bytes;      /* state the forward leaves for the backward, including the
+                                backward's accumulators (per-pair 2D adjoint rows, dense
+                                depth adjoints), which the forward leaves zeroed */
     size_t fwd_ws_bytes;     /* forward scratch */
     size_t bwd_ws_bytes;     /* backward scratch */
     int64_t n_pairs, n_pixels, n_tiles;
@@ -263,12 +265,16 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
  * shared splat set of Sec. III-B).  Exactly one of `up` (upstream gradients) or `loss` (fused
  * loss; then `loss_out`, device float[1] or NULL, receives the loss value) is non-NULL.
  * `fwd` holds the outputs of the matching forward (read in loss mode).  saved: from that
- * forward (transmittance is recomputed from it, no per-pixel blend lists are kept).  ws:
- * device, bwd_ws_bytes.  Gradients per ags_grads.  Errors: INVALID_ARG, WORKSPACE,
- * NOT_SUPPORTED, HIP. */
+ * forward (transmittance is recomputed from it, no per-pixel blend lists are kept); the
+ * backward accumulates into the adjoint buffers it holds, which that forward left zeroed.
+ * When the call directly follows, on this context and in the same stream-capture state (both
+ * outside any capture, or in one capture), the forward that filled `saved`, it relies on that
+ * zeroing; otherwise (a second backward of one forward, say) it clears them first.  (So a captured graph holding a backward but not its forward must not be replayed
+ * twice after one forward.)  ws: device, bwd_ws_bytes.  Gradients per ags_grads.  Errors:
+ * INVALID_ARG, WORKSPACE, NOT_SUPPORTED, HIP. */
 int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
-                   const void* saved, const ags_upstream* up, const ags_loss* loss,
+                   void* saved, const ags_upstream* up, const ags_loss* loss,
                    ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Binning stage alone (for tests and tuning): from projected records (float[n_pairs][12],
@@ -301,7 +307,7 @@ int ags_adam_step(ags_ctx* ctx, const ags_adam* hp, ags_gaussians* params,
  * must be 0.  The result equals the two calls in sequence. */
 int ags_render_bwd_adam(ags_ctx* ctx, const ags_views* views, ags_gaussians* params,
                         const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
-                        const void* saved, const ags_upstream* up, const ags_loss* loss,
+                        void* saved, const ags_upstream* up, const ags_loss* loss,
                         ags_grads* grads, float* loss_out, const ags_adam* hp, ags_gaussians* m,
                         ags_gaussians* v, const int32_t* step, void* ws, size_t ws_bytes,
                         void* stream);

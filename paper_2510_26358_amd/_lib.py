@@ -115,7 +115,7 @@ class Adam(C.Structure):
                 ("eps", C.c_float)]
 
 
-ABI_VERSION = 4  # include/agsplat.h AGS_ABI_VERSION
+ABI_VERSION = 5  # include/agsplat.h AGS_ABI_VERSION
 
 _lib = None
 

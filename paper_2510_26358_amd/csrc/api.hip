@@ -32,6 +32,14 @@ struct ags_ctx {
     std::vector<hipEvent_t> pool;
     double total_ms[ST_COUNT];
     long long launches[ST_COUNT];
+    // What the last forward call on this context left zeroed in its `saved`
+    // buffer for the backward: the visible pairs' adjoint rows (kClearRows), the dense depth
+    // adjoint (kClearDepth) and second-moment adjoint (kClearDepth2); recorded with the
+    // stream capture it was enqueued in (0: none).  A backward of the same buffer in the same
+    // capture state skips those clears and resets the record, since it dirties them.
+    const void* clean_saved;
+    unsigned clean_bits;
+    unsigned long long clean_capture;
 };
 
 namespace {
@@ -48,12 +56,13 @@ struct Layout {
     int tile_bits;
     int depth_grid, tile_grid;
     // saved
-    size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_work, s_t_final, s_last, s_total;
+    size_t s_counters, s_records, s_pair_count, s_tile_pairs, s_ranges, s_work, s_t_final, s_last, s_grad2d,
+        s_ddepth, s_ddepth2, s_total;
     // fwd ws
     size_t f_pair_z, f_dkeys0, f_dkeys1, f_dvals0, f_dvals1, f_emit_off, f_block_first, f_tkeys0, f_tkeys1,
         f_tvals1, f_hist, f_rowtot, f_block_sums, f_total;
     // bwd ws
-    size_t b_grad2d, b_ddepth, b_ddepth2, b_dssim, b_partials, b_pose_part, b_vis, b_total;
+    size_t b_dssim, b_partials, b_pose_part, b_vis, b_total;
     long long n_partials, n_ssim;
 };
 
@@ -133,6 +142,12 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     L.s_work = o; o = align_up(o + (size_t)(tiles > 0 ? tiles + 8 * (kWorkStrip + 1) : 1) * 4);
     L.s_t_final = o; o = align_up(o + (size_t)pix * 4);
     L.s_last = o; o = align_up(o + (size_t)pix * 4);
+    // the backward's accumulators, zeroed by the forward: per-pair 2D adjoint rows (the
+    // visible pairs' rows, by the projection) and the dense depth and second-moment adjoints
+    // (by the raster forward)
+    L.s_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
+    L.s_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
+    L.s_ddepth2 = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
     L.s_total = o;
     o = 0;
     const int gmax = L.depth_grid > L.tile_grid ? L.depth_grid : L.tile_grid;
@@ -154,9 +169,6 @@ int build_layout(const ags_config* cfg, const ags_views* views, int n, long long
     o = 0;
     L.n_ssim = ssim_blocks(vt);
     L.n_partials = tiles + lidar_blocks(0) + L.n_ssim;  // raster, LiDAR, then D-SSIM blocks
-    L.b_grad2d = o; o = align_up(o + (size_t)Qs * kGrad2dStride * 4);
-    L.b_ddepth = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
-    L.b_ddepth2 = o; o = align_up(o + (size_t)(pix > 0 ? pix : 1) * 4);
     L.b_dssim = o; o = align_up(o + (size_t)(pix > 0 ? 3 * pix : 1) * 4);
     L.b_partials = o; o = align_up(o + (size_t)L.n_partials * 4);
     L.b_pose_part = o; o = align_up(o + (size_t)2 * (project_bwd_blocks(n) > 0 ? project_bwd_blocks(n) : 1) *
@@ -239,6 +251,30 @@ BinArgs bin_args(const Layout& L, void* saved, void* ws) {
 }
 
 int run_binning(BinArgs a, hipStream_t s) { return launch_binning(a, s); }
+
+constexpr unsigned kClearRows = 1u, kClearDepth = 2u, kClearDepth2 = 4u;
+
+// The stream capture `s` is recording into (0: none); false if that cannot be told.  Called
+// before a call's first launch, so the error a failed query leaves can be taken back without
+// hiding one of the call's own.
+bool capture_of(hipStream_t s, unsigned long long& id) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long cid = 0;
+    if (hipStreamGetCaptureInfo(s, &st, &cid) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    id = st == hipStreamCaptureStatusActive ? cid : 0ull;
+    return true;
+}
+
+// Records what a forward call just enqueued left zeroed in `saved` (capture state as queried
+// before the call's launches).
+void mark_clean(ags_ctx* ctx, const void* saved, unsigned bits, bool known, unsigned long long id) {
+    ctx->clean_saved = known ? saved : nullptr;
+    ctx->clean_bits = known ? bits : 0u;
+    ctx->clean_capture = id;
+}
 
 }  // namespace
 
@@ -401,6 +437,9 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
     const Settings st = settings_of(ctx->cfg);
+    unsigned long long cid = 0;
+    const bool cid_known = capture_of(s, cid);
+    ctx->clean_saved = nullptr;
     {
         Scope sc(ctx, ST_PROJECT, s);
         ProjectArgs pa;
@@ -417,6 +456,7 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         pa.records = at<float>(saved, L.s_records);
         pa.pair_count = at<uint32_t>(saved, L.s_pair_count);
         pa.pair_z = at<uint32_t>(ws, L.f_pair_z);
+        pa.grad2d = at<float>(saved, L.s_grad2d);
         launch_project_fwd(pa, s);
     }
     {
@@ -438,9 +478,12 @@ int ags_render_fwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
         ra.depth_var = out->depth_var;
         ra.t_final = at<float>(saved, L.s_t_final);
         ra.last = at<uint32_t>(saved, L.s_last);
+        ra.zero_px[0] = at<float>(saved, L.s_ddepth);
+        ra.zero_px[1] = out->depth_var ? at<float>(saved, L.s_ddepth2) : nullptr;
         rc = launch_raster_fwd(ra, ctx->cfg.tile, ctx->cfg.batch, ctx->cfg.px_per_thread, s);
         if (rc) return rc;
     }
+    mark_clean(ctx, saved, kClearRows | kClearDepth | (out->depth_var ? kClearDepth2 : 0u), cid_known, cid);
     return hip_status(ctx);
 }
 
@@ -456,6 +499,7 @@ int ags_bin_records(ags_ctx* ctx, const ags_views* views, int32_t n_gaussians, c
     if (ws_bytes < L.f_total) return AGS_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
+    ctx->clean_saved = nullptr;  // the backward of these records clears its accumulators itself
     Scope sc(ctx, ST_BINNING, s);
     if (L.Q > 0)
         (void)hipMemcpyAsync(at<float>(saved, L.s_records), records, (size_t)L.Q * kRecFloats * 4,
@@ -471,7 +515,7 @@ namespace {
 // The backward; with `fused` non-null the colour phase of the projection backward also
 // applies Adam to every Gaussian parameter (grads->sh is then not written and may be null).
 int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const ags_camera* cams,
-               int64_t isect_capacity, const ags_fwd_out* fwd, const void* saved, const ags_upstream* up,
+               int64_t isect_capacity, const ags_fwd_out* fwd, void* saved, const ags_upstream* up,
                const ags_loss* loss, ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream,
                const AdamArgs* fused) {
     if (!ctx || !saved || !ws || !cams || !grads) return AGS_ERR_INVALID_ARG;
@@ -509,29 +553,38 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return hip_status(ctx);
     const Settings st = settings_of(ctx->cfg);
-    float* grad2d = at<float>(ws, L.b_grad2d);
-    float* ddepth = at<float>(ws, L.b_ddepth);
-    float* ddepth2 = at<float>(ws, L.b_ddepth2);
+    float* grad2d = at<float>(saved, L.s_grad2d);
+    float* ddepth = at<float>(saved, L.s_ddepth);
+    float* ddepth2 = at<float>(saved, L.s_ddepth2);
     const bool rendered_var = loss && loss->sigma_mode == AGS_SIGMA_RENDERED;
     float* partials = at<float>(ws, L.b_partials);
     {
-        Scope sc(ctx, ST_CLEAR, s);
-        BwdClearArgs ca;
-        memset(&ca, 0, sizeof(ca));
-        ca.grad2d = grad2d;
-        ca.pair_count = at<uint32_t>(saved, L.s_pair_count);
-        ca.n_pairs = L.Q;
-        int r = 0;
-        auto zero = [&](float* p, long long n) {
-            ca.zero[r] = p;
-            ca.zero_n[r] = n;
-            ++r;
-        };
-        if (loss && n_targets > 0) zero(ddepth, L.P);
-        if (rendered_var && n_targets > 0) zero(ddepth2, L.P);
-        if (loss && n_targets == 0) zero(partials + L.n_tiles, lidar_blocks(0));
-        if (loss && !(loss->ssim_weight > 0.f)) zero(partials + L.n_tiles + lidar_blocks(0), L.n_ssim);
-        launch_bwd_clear(ca, s);
+        // the accumulators start at zero: the forward that filled `saved` zeroed them unless
+        // another backward (or a call in another capture state) came in between
+        unsigned need = kClearRows;
+        if (loss && n_targets > 0) need |= kClearDepth;
+        if (rendered_var && n_targets > 0) need |= kClearDepth2;
+        unsigned long long cid = 0;
+        if (ctx->clean_saved == saved && capture_of(s, cid) && cid == ctx->clean_capture) need &= ~ctx->clean_bits;
+        ctx->clean_saved = nullptr;  // this backward dirties them
+        if (need) {
+            Scope sc(ctx, ST_CLEAR, s);
+            BwdClearArgs ca;
+            memset(&ca, 0, sizeof(ca));
+            ca.grad2d = (need & kClearRows) ? grad2d : nullptr;
+            ca.pair_count = at<uint32_t>(saved, L.s_pair_count);
+            ca.n_pairs = (need & kClearRows) ? L.Q : 0;
+            int r = 0;
+            if (need & kClearDepth) {
+                ca.zero[r] = ddepth;
+                ca.zero_n[r++] = L.P;
+            }
+            if (need & kClearDepth2) {
+                ca.zero[r] = ddepth2;
+                ca.zero_n[r++] = L.P;
+            }
+            launch_bwd_clear(ca, s);
+        }
     }
     RasterBwdArgs ra;
     memset(&ra, 0, sizeof(ra));
@@ -639,7 +692,15 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
         else memset(&pa.adam, 0, sizeof(pa.adam));
         launch_project_bwd(pa, s);
     }
-    if (loss && loss_out) launch_sum_partials(partials, L.n_partials, loss_out, s);
+    if (loss && loss_out) {
+        // partials: the tiles', then the LiDAR blocks' and the D-SSIM blocks'; the parts of
+        // terms that are off were not written and count as zero
+        const long long lidar0 = L.n_tiles, ssim0 = L.n_tiles + lidar_blocks(0);
+        const bool no_lidar = n_targets == 0, no_ssim = !(loss->ssim_weight > 0.f);
+        const long long skip0 = no_lidar ? lidar0 : (no_ssim ? ssim0 : L.n_partials);
+        const long long skip1 = no_ssim ? L.n_partials : (no_lidar ? ssim0 : L.n_partials);
+        launch_sum_partials(partials, L.n_partials, skip0, skip1, loss_out, s);
+    }
     return hip_status(ctx);
 }
 
@@ -682,14 +743,14 @@ bool adam_shapes_ok(const ags_gaussians* p, const ags_gaussians* m, const ags_ga
 
 int ags_render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g,
                    const ags_camera* cams, int64_t isect_capacity, const ags_fwd_out* fwd,
-                   const void* saved, const ags_upstream* up, const ags_loss* loss,
+                   void* saved, const ags_upstream* up, const ags_loss* loss,
                    ags_grads* grads, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
     return render_bwd(ctx, views, g, cams, isect_capacity, fwd, saved, up, loss, grads, loss_out, ws, ws_bytes,
                       stream, nullptr);
 }
 
 int ags_render_bwd_adam(ags_ctx* ctx, const ags_views* views, ags_gaussians* params, const ags_camera* cams,
-                        int64_t isect_capacity, const ags_fwd_out* fwd, const void* saved,
+                        int64_t isect_capacity, const ags_fwd_out* fwd, void* saved,
                         const ags_upstream* up, const ags_loss* loss, ags_grads* grads, float* loss_out,
                         const ags_adam* hp, ags_gaussians* m, ags_gaussians* v, const int32_t* step, void* ws,
                         size_t ws_bytes, void* stream) {

@@ -395,6 +395,7 @@ struct ProjectArgs {
     float* records;
     uint32_t* pair_count;
     uint32_t* pair_z;
+    float* grad2d;  // [n_pairs][kGrad2dStride]: each visible pair's row is zeroed for the backward
 };
 void launch_project_fwd(const ProjectArgs& a, hipStream_t s);
 
@@ -491,6 +492,8 @@ struct RasterArgs {
     float* depth_var;  // or null: rendered depth variance per pixel
     float* t_final;
     uint32_t* last;
+    // zeroed per pixel (or null): the backward's dense depth and second-moment adjoints
+    float* zero_px[2];
 };
 // The (tile, pixels per thread, LDS batch) launch shapes compiled for both raster kernels:
 // writes up to n_max of them and returns how many there are.
@@ -523,10 +526,11 @@ struct RasterBwdArgs {
     float* grad2d;               // [n_pairs][16] (ten used); rows of visible pairs cleared
 };
 int launch_raster_bwd(const RasterBwdArgs& a, int T, int batch, int ppt, hipStream_t s);
-// The backward's clears in one launch: grad2d's rows of the pairs with pair_count != 0 (the
-// rows raster_bwd adds to), and up to kBwdClearRegions float buffers (zero_n[r] floats each;
-// 0 for none).
-constexpr int kBwdClearRegions = 4;
+// The backward's clears in one launch, for a backward whose forward did not leave them done
+// (a second backward of one forward): grad2d's rows of the pairs with pair_count != 0 (the
+// rows raster_bwd adds to; none if grad2d is null), and up to kBwdClearRegions float buffers
+// (the dense depth adjoints; zero_n[r] floats each, 0 for none).
+constexpr int kBwdClearRegions = 2;
 struct BwdClearArgs {
     float* grad2d;
     const uint32_t* pair_count;
@@ -573,7 +577,8 @@ struct LidarArgs {
 };
 int lidar_blocks(long long n_targets);
 void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s);
-void launch_sum_partials(const float* partials, long long n, float* out, hipStream_t s);
+void launch_sum_partials(const float* partials, long long n, long long skip0, long long skip1, float* out,
+                         hipStream_t s);
 
 // Adam on the Gaussian parameters: groups means, log-scales, quaternions, logits, SH
 // degree 0, SH degree >= 1 (lr[0..5]); the SH buffer holds both SH groups.

@@ -66,18 +66,21 @@ void launch_lidar_adjoint(const LidarArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(lidar_adjoint_kernel, dim3(kLidarBlocks), dim3(kLidarThreads), 0, s, a);
 }
 
-// Deterministic sum of the per-block loss partials (fixed order, one workgroup).
-__global__ __launch_bounds__(1024) void sum_partials_kernel(const float* p, long long n, float* out) {
+// Deterministic sum of the per-block loss partials (fixed order, one workgroup); the entries
+// in [skip0, skip1) belong to terms that are off, were not written, and count as zero.
+__global__ __launch_bounds__(1024) void sum_partials_kernel(const float* p, long long n, long long skip0,
+                                                            long long skip1, float* out) {
     __shared__ float sred[16];
     // eight independent sums per thread, so eight loads are in flight at a time (fixed order)
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     long long i = threadIdx.x;
+    auto at = [&](long long j) { return j >= skip0 && j < skip1 ? 0.f : p[j]; };
     for (; i + 7 * 1024 < n; i += 8 * 1024)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += p[i + u * 1024];
+        for (int u = 0; u < 8; ++u) acc[u] += at(i + u * 1024);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-        if (i + u * 1024 < n) acc[u] += p[i + u * 1024];
+        if (i + u * 1024 < n) acc[u] += at(i + u * 1024);
     float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
@@ -89,8 +92,9 @@ __global__ __launch_bounds__(1024) void sum_partials_kernel(const float* p, long
     }
 }
 
-void launch_sum_partials(const float* partials, long long n, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, out);
+void launch_sum_partials(const float* partials, long long n, long long skip0, long long skip1, float* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, skip0, skip1, out);
 }
 
 }  // namespace ags

@@ -8,7 +8,8 @@
 //   (u, v) = (fx x/z + cx, fy y/z + cy); o = sigmoid(omega);
 //   colour = max(0, SH(d) . f + 0.5) with d the unit direction from the camera centre;
 //   opacity-aware footprint half-extents ex = sqrt(2 ln(255 o) Sigma'_xx), ey likewise
-//   (the box outside which alpha < 1/255), the tile rectangle and its tile count.
+//   (the box outside which alpha < 1/255), the tile rectangle and its tile count; a kept pair's
+//   row of the backward's 2D adjoint accumulator is zeroed.
 // Culled pairs (z < z_near, det <= 0, o < alpha_min, empty rectangle) get count 0 and no
 // record.
 // The SH coefficients (48 of the 59 floats at degree 3) are read once per Gaussian that
@@ -95,6 +96,10 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
                     rec[1] = make_float4(ca * idet, o, z, ex);
                     a.records[q * kRecFloats + 8] = ey;
                     a.pair_z[q] = __float_as_uint(z);
+                    // the pair's 2D adjoint row starts the backward at zero
+                    float4* row = reinterpret_cast<float4*>(a.grad2d + q * kGrad2dStride);
+#pragma unroll
+                    for (int c = 0; c < kGrad2dStride / 4; ++c) row[c] = make_float4(0.f, 0.f, 0.f, 0.f);
                     vis |= 1u << b;
                 }
             }

@@ -281,6 +281,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         a.alpha[gp] = A[k];
         a.t_final[gp] = Tr[k];
         a.last[gp] = last[k];
+        if (a.zero_px[0]) a.zero_px[0][gp] = 0.f;
+        if (a.zero_px[1]) a.zero_px[1][gp] = 0.f;
     }
 }
 
@@ -487,11 +489,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     if (MERGE) flush(prev_n, sq[buf ^ 1]);
 }
 
-// The backward's clears in one launch.  Thread g zeroes the adjoint rows of the pairs
-// 4 g .. 4 g + 3 that some tile lists (the only rows the raster backward adds to and the
-// projection backward reads): one 16-byte load of their counts, then the 64-byte row stores
-// of the visible ones, so no store waits on more than one load; then, striding over the grid,
-// the dense float buffers (LiDAR depth adjoints, unused loss partials).
+// The backward's clears in one launch, when the forward's own zeroing of these accumulators
+// cannot be relied on (a second backward of one forward).  Thread g zeroes the adjoint rows of
+// the pairs 4 g .. 4 g + 3 that some tile lists (the only rows the raster backward adds to
+// and the projection backward reads): one 16-byte load of their counts, then the 64-byte row
+// stores of the visible ones, so no store waits on more than one load; then, striding over
+// the grid, the dense float buffers (the LiDAR depth and second-moment adjoints).
 static_assert(kGrad2dStride == 16, "four float4 stores per row");
 
 __global__ __launch_bounds__(256) void bwd_clear_kernel(BwdClearArgs a) {

@@ -37,7 +37,7 @@ def test_every_declared_function_is_exported(lib):
 
 def test_version_errors_and_defaults(lib):
     from paper_2510_26358_amd import _lib as L
-    assert lib.ags_version() == L.ABI_VERSION == 4
+    assert lib.ags_version() == L.ABI_VERSION == 5
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.ags_error_string(code)
     cfg = L.Config()

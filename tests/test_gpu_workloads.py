@@ -155,6 +155,78 @@ def test_upstream_mode_gradients(ras):
     assert ok, msg
 
 
+def _loss_backward(ras, p, cams, views, buf, out, tg):
+    grads = p.zeros_like()
+    pose = torch.zeros(views.n_views, 6, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+    return grads, pose, loss
+
+
+def _same_result(a, b):
+    """Two backward results of one forward: equal up to the order of the float atomics."""
+    for x, y in zip(list(a[0].tensors()) + [a[1], a[2]], list(b[0].tensors()) + [b[1], b[2]]):
+        tol = 1e-5 * max(1.0, float(y.abs().max()))
+        assert torch.allclose(x, y, rtol=1e-4, atol=tol), float((x - y).abs().max())
+
+
+@pytest.mark.parametrize("mode,ssim_w", [("fixed", 0.0), ("fixed", 0.2), ("rendered", 0.0)])
+def test_second_backward_of_one_forward_matches_the_first(ras, mode, ssim_w):
+    """The forward leaves the backward's accumulators (per-pair adjoint rows, dense depth
+    adjoints) zeroed and the backward right after it relies on that; a second backward of the
+    same forward, directly or after a forward of other buffers, clears them first and gives
+    the same loss and gradients (doubled adjoints would show here)."""
+    sc = random_scene(331, n=400, sh_degree=2, n_views=2, width=64, height=48, f=60.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    tg = LossTargets.from_scene(sc, views, ssim_weight=ssim_w, sigma_mode=mode)
+    assert int(tg.depth_offsets[-1]) > 0  # LiDAR targets present: the dense depth adjoint is used
+    out, buf = ras.render(p, cams, views, depth_var=mode == "rendered")
+    first = _loss_backward(ras, p, cams, views, buf, out, tg)
+    second = _loss_backward(ras, p, cams, views, buf, out, tg)
+    torch.cuda.synchronize()
+    _same_result(second, first)
+    # a forward of other buffers in between, then the first buffers' backward again
+    out_b, _ = ras.render(p, cams, views, depth_var=mode == "rendered")
+    third = _loss_backward(ras, p, cams, views, buf, out, tg)
+    torch.cuda.synchronize()
+    _same_result(third, first)
+    # and the first result is the oracle's (the forward's zeroing is what the first relied on)
+    ref = loss_and_grads(sc, RenderSettings(), ssim_w=ssim_w, sigma_mode=mode)
+    assert abs(first[2].item() - ref["loss"]) <= 1e-5 * max(1.0, abs(ref["loss"]))
+    for name, gg in zip(["means", "log_scales", "quats", "opacity_logits", "sh"], first[0].to_numpy_aos()):
+        ok, msg = grad_close(gg, ref["grads"][name], ref["amb_gauss"])
+        assert ok, (name, msg)
+
+
+def test_captured_forward_backward_replays_match_eager(ras):
+    """Forward and fused-loss backward captured in one HIP graph: every replay (with an eager
+    backward of the same buffers between replays, which must clear the accumulators the
+    replay's backward filled) matches the eager pair."""
+    sc = random_scene(341, n=500, sh_degree=3, n_views=2, width=64, height=48, f=60.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    tg = LossTargets.from_scene(sc, views)
+    out, buf = ras.render(p, cams, views)
+    eager = _loss_backward(ras, p, cams, views, buf, out, tg)
+    torch.cuda.synchronize()
+    eager = tuple(x.clone() if torch.is_tensor(x) else x for x in eager)
+    grads, pose, loss = p.zeros_like(), torch.zeros(views.n_views, 6, device="cuda"), torch.zeros(1, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ras.forward_into(p, cams, views, buf, out)
+        ras.backward_into(p, cams, views, buf, out, grads, pose, loss=tg, loss_out=loss)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _same_result((grads, pose, loss), eager)
+        between = _loss_backward(ras, p, cams, views, buf, out, tg)
+        torch.cuda.synchronize()
+        _same_result(between, eager)
+
+
 def test_autograd_function_matches_fused_loss(ras):
     from paper_2510_26358_amd.autograd import render, render_loss
     sc = random_scene(321, n=250, sh_degree=1, n_views=1, width=48, height=40, f=50.0)
