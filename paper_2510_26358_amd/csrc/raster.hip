@@ -121,13 +121,17 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 // Copy record q into LDS in the form the per-pixel loops use: the conic (a, b, c) becomes
 // log2(e) (-a/2, -b, -c/2), so the exponent in base 2, p2 = dx (A' dx + B' dy) + C' dy^2,
 // costs five operations and e^power = exp2(p2) is one instruction; the footprint extent is
-// replaced by log2(alpha_min / o) (a Gaussian whose exponent is below it cannot reach
-// alpha_min) and by the mask of wave blocks its footprint box touches.  Forward and
-// backward stage identical values, so their decisions agree; every skipped (pixel,
-// Gaussian) pair has alpha < alpha_min, so the result is the same as evaluating it.
+// replaced by the exponent floor log2(alpha_min / o) - kPreTestMargin and by the mask of wave
+// blocks its footprint box touches.  Both kernels keep a (pixel, Gaussian) pair exactly when
+// p2 <= 0 and alpha = min(alpha_max, o exp2(p2)) >= alpha_min, in float32, so their decisions
+// agree; the backward tests the exponent floor first to skip whole entries.  A kept pair has
+// o exp2(p2) >= alpha_min, so p2 >= log2(alpha_min / o) less the float32 rounding of the
+// product and of exp2 (a few 1e-7), and the computed floor is within ~1e-6 of the exact
+// log2: the 1e-4 margin keeps every kept pair above the floor, so the pre-test never
+// changes a decision; every skipped pair has alpha < alpha_min.
 // LDS layout (64 B, read at non-negative offsets from one per-lane address):
 //   [0] = (wave mask bits, r, g, b), [1] = (u, v, -a/2 log2e, -b log2e),
-//   [2] = (-c/2 log2e, o, z, log2(alpha_min/o)), [3] = (pair id, z^2, -, -).
+//   [2] = (-c/2 log2e, o, z, exponent floor), [3] = (pair id, z^2, -, -).
 struct alignas(16) SRec {
     float4 m, g0, g1;
     uint32_t q;
@@ -135,6 +139,7 @@ struct alignas(16) SRec {
     uint32_t pad[2];
 };
 
+constexpr float kPreTestMargin = 1e-4f;
 template <int T, int PPT, bool BLOCKS>
 __device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
                                              int px0, int py0, SRec& dst) {
@@ -144,7 +149,7 @@ __device__ __forceinline__ void stage_record(const float* records, uint32_t q, f
     const uint32_t m = BLOCKS ? wave_mask<T, PPT, BLOCKS>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : ~0u;
     dst.m = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
     dst.g0 = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
-    dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y));
+    dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y) - kPreTestMargin);
     dst.q = q;
     dst.z2 = r1.z * r1.z;
 }
@@ -237,8 +242,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
                 const float p2 = power_of(r0, r1, dx, dy);
                 const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
-                // r1.w = log2(alpha_min / o): below it alpha cannot reach alpha_min
-                const bool keep = p2 <= 0.f && p2 >= r1.w && alpha >= amin;
+                const bool keep = p2 <= 0.f && alpha >= amin;
                 if (keep) {
                     // stop (once per pixel) before a Gaussian that would take T below t_min
                     const bool go = Tr[k] * (1.f - alpha) >= tmin;
@@ -430,8 +434,8 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) continue;  // wave-uniform
             const float z2 = S2 ? r.z2 : 0.f;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
-            // passes (a lane passes exactly when it can keep this Gaussian, up to rounding of
-            // the threshold, and keeps are re-tested on alpha below)
+            // passes (every lane that keeps this Gaussian passes: the floor sits a margin below
+            // the exact threshold; keeps are decided on alpha below, as in the forward)
             float p2v[PPT];
             bool pass[PPT];
             bool anyp = false;
