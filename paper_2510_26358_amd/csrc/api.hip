@@ -690,16 +690,20 @@ int render_bwd(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, con
         pa.fused_adam = fused != nullptr;
         if (fused) pa.adam = *fused;
         else memset(&pa.adam, 0, sizeof(pa.adam));
-        launch_project_bwd(pa, s);
-    }
-    if (loss && loss_out) {
-        // partials: the tiles', then the LiDAR blocks' and the D-SSIM blocks'; the parts of
-        // terms that are off were not written and count as zero
-        const long long lidar0 = L.n_tiles, ssim0 = L.n_tiles + lidar_blocks(0);
-        const bool no_lidar = n_targets == 0, no_ssim = !(loss->ssim_weight > 0.f);
-        const long long skip0 = no_lidar ? lidar0 : (no_ssim ? ssim0 : L.n_partials);
-        const long long skip1 = no_ssim ? L.n_partials : (no_lidar ? ssim0 : L.n_partials);
-        launch_sum_partials(partials, L.n_partials, skip0, skip1, loss_out, s);
+        pa.loss_partials = partials;
+        pa.n_loss = L.n_partials;
+        pa.loss_skip0 = pa.loss_skip1 = 0;
+        pa.loss_out = nullptr;
+        if (loss && loss_out) {
+            // partials: the tiles', then the LiDAR blocks' and the D-SSIM blocks'; the parts
+            // of terms that are off were not written and count as zero
+            const long long lidar0 = L.n_tiles, ssim0 = L.n_tiles + lidar_blocks(0);
+            const bool no_lidar = n_targets == 0, no_ssim = !(loss->ssim_weight > 0.f);
+            pa.loss_skip0 = no_lidar ? lidar0 : (no_ssim ? ssim0 : L.n_partials);
+            pa.loss_skip1 = no_ssim ? L.n_partials : (no_lidar ? ssim0 : L.n_partials);
+            pa.loss_out = loss_out;
+        }
+        launch_project_bwd(pa, s);  // its pose reduction also sums the loss partials
     }
     return hip_status(ctx);
 }

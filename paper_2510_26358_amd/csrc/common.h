@@ -622,6 +622,12 @@ struct ProjectBwdArgs {
     // Adam to all its parameters instead of writing the SH gradient (g_sh unused)
     int fused_adam;
     AdamArgs adam;
+    // optional (loss_out non-null): the loss partials' fixed-order sum into loss_out[0], done
+    // by one more workgroup of the pose reduction's launch; entries [loss_skip0, loss_skip1)
+    // were not written and count as zero
+    const float* loss_partials;
+    long long n_loss, loss_skip0, loss_skip1;
+    float* loss_out;
 };
 int project_bwd_blocks(int n);
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);

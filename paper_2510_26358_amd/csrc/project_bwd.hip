@@ -450,11 +450,30 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a) {
 }
 
 // Sum of the per-workgroup pose partials, fixed order: one workgroup per (view, component),
-// whose partials form one contiguous row of n_blocks values.
+// whose partials form one contiguous row of n_blocks values; with loss_out, one more
+// workgroup adds up the loss partials (fixed order, the skipped range counting as zero).
 __global__ __launch_bounds__(256) void pose_reduce_kernel(const float* partials, int n_blocks, int n_views,
-                                                         float* pose, int accumulate) {
+                                                         float* pose, int accumulate, const float* lp, long long n_lp,
+                                                         long long skip0, long long skip1, float* loss_out) {
     __shared__ float sred[4];
     const int bk = blockIdx.x;  // b * 6 + k
+    if (bk == n_views * 6) {
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto at = [&](long long j) { return j >= skip0 && j < skip1 ? 0.f : lp[j]; };
+        long long i = threadIdx.x;
+        for (; i + 7 * 256 < n_lp; i += 8 * 256)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += at(i + u * 256);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i + u * 256 < n_lp) acc[u] += at(i + u * 256);
+        float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) loss_out[0] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+        return;
+    }
     const float* row = partials + (long long)bk * n_blocks;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     int g = threadIdx.x;
@@ -481,11 +500,14 @@ int project_bwd_blocks(int n) { return n > 0 ? (n + 255) / 256 : 0; }
 void launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
     const int nb = project_bwd_blocks(a.n);
     if (nb > 0) launch_project_bwd_main(a, s);
-    if (nb > 0)
-        hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6), dim3(256), 0, s, a.pose_partials, 2 * nb,
-                           a.vt.n_views, a.g_pose, a.accumulate);
-    else if (!a.accumulate)
-        launch_fill_f32(a.g_pose, 0.f, 6LL * a.vt.n_views, s);
+    if (nb > 0) {
+        hipLaunchKernelGGL(pose_reduce_kernel, dim3(a.vt.n_views * 6 + (a.loss_out ? 1 : 0)), dim3(256), 0, s,
+                           a.pose_partials, 2 * nb, a.vt.n_views, a.g_pose, a.accumulate, a.loss_partials, a.n_loss,
+                           a.loss_skip0, a.loss_skip1, a.loss_out);
+        return;
+    }
+    if (!a.accumulate) launch_fill_f32(a.g_pose, 0.f, 6LL * a.vt.n_views, s);
+    if (a.loss_out) launch_sum_partials(a.loss_partials, a.n_loss, a.loss_skip0, a.loss_skip1, a.loss_out, s);
 }
 
 void launch_project_bwd_main(const ProjectBwdArgs& a, hipStream_t s) {
