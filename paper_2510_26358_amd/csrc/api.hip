@@ -383,6 +383,7 @@ int ags_ctx_set_config(ags_ctx* ctx, const ags_config* cfg) {
     int rc = check_config(cfg);
     if (rc) return rc;
     ctx->cfg = *cfg;
+    ctx->clean_saved = nullptr;  // a saved buffer's layout follows the configuration
     return AGS_OK;
 }
 
@@ -1172,7 +1173,9 @@ int ags_tune(ags_ctx* ctx, const ags_views* views, const ags_gaussians* g, const
             found = true;
         }
     }
-    // tear down: the caller's profile totals and setting return, the pick is applied
+    // tear down: the caller's profile totals and setting return, the pick is applied; the
+    // trial buffers are gone, so no saved buffer counts as zeroed
+    ctx->clean_saved = nullptr;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     for (int k = 0; k < ST_COUNT; ++k) {
