@@ -335,8 +335,9 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
         if name == "project_bwd":
             by = 4 * F * n_gauss * 2 + 52 * int(v) + 4 * Q
         elif name == "project_fwd":
-            # with each visible pair's 64-byte adjoint row zeroed for the backward
-            by = 4 * F * n_gauss + 56 * int(v) + 4 * Q + 64 * int(v)
+            # parameters once; per visible pair its 48-byte record and its 64-byte adjoint row
+            # zeroed for the backward; per pair its tile count and depth key
+            by = 4 * F * n_gauss + 48 * int(v) + 8 * Q + 64 * int(v)
         elif name == "adam":
             by = 7 * 4 * F * n_gauss
         else:
@@ -358,7 +359,7 @@ def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fu
     that."""
     F = 11 + 3 * sh_k
     byts = {
-        "project_fwd": 4 * F * N + 48 * V + 4 * Q + 4 * V + 64 * V,
+        "project_fwd": 4 * F * N + 48 * V + 8 * Q + 64 * V,
         "binning": 8 * Q + 84 * V + 44 * K,
         "lidar_adjoint": 16 * n_targets,
         "project_bwd": 2 * 4 * F * N + 56 * V + 24 * N,
