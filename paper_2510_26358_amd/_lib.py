@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libagsplat.so")
+# AGS_LIBRARY selects another build of the same library (the host-sanitized one, for its test)
+LIB_PATH = os.environ.get("AGS_LIBRARY") or os.path.join(HERE, "libagsplat.so")
 
 AGS_OK = 0
 AGS_ERR_INVALID_ARG = -1

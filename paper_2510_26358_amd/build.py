@@ -4,6 +4,11 @@ Every translation unit is compiled to an object in parallel, then linked into on
 library next to this file.  Packed FP32 instructions are disabled for all device code
 (`-Xclang -target-feature -Xclang -packed-fp32-ops`); float atomics use the hardware
 instruction (`-munsafe-fp-atomics`, device memory is coarse-grained).
+
+`build(sanitize=True)` makes a second library, `_build_san/libagsplat_san.so`, whose host code
+carries AddressSanitizer and UndefinedBehaviorSanitizer checks (device code unchanged; each
+sanitizer flag applies to the host side only); load it with the sanitizer runtime preloaded
+(`sanitizer_runtime()`).
 """
 from __future__ import annotations
 
@@ -19,6 +24,10 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libagsplat.so")
+BUILD_SAN = os.path.join(ROOT, "_build_san")
+LIB_SAN = os.path.join(BUILD_SAN, "libagsplat_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+             "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
 ARCH = os.environ.get("AGS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "project.hip", "sortscan.hip", "bin.hip", "raster.hip", "loss.hip",
@@ -36,9 +45,9 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(BUILD_SAN if sanitize else BUILD, os.path.basename(src) + ".o")
+    cmd = [hipcc(), *CFLAGS, *(SAN_FLAGS if sanitize else []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -54,21 +63,40 @@ def _filter_warnings(text: str) -> str:
     return "".join(keep)
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every HIP translation unit and link libagsplat.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, sanitize: bool = False) -> str:
+    """Compile every HIP translation unit and link libagsplat.so (or, with sanitize, the
+    host-sanitized libagsplat_san.so); returns its path."""
+    out = LIB_SAN if sanitize else LIB
+    os.makedirs(BUILD_SAN if sanitize else BUILD, exist_ok=True)
     workers = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
+    if sanitize:
+        cmd[2:2] = [*SAN_FLAGS, "-Xarch_host", "-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {out}")
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (to preload for libagsplat_san.so)."""
+    r = subprocess.run([os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin",
+                                     "clang++"), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        found = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+        if not found:
+            raise RuntimeError("the AddressSanitizer runtime of the ROCm compiler was not found")
+        path = found[-1]
+    return path
 
 
 if __name__ == "__main__":

@@ -200,6 +200,27 @@ def test_second_backward_of_one_forward_matches_the_first(ras, mode, ssim_w):
         assert ok, (name, msg)
 
 
+def test_second_upstream_backward_of_one_forward_matches_the_first(ras):
+    """Upstream-gradient mode (the autograd path, e.g. a retained graph run backward twice):
+    the second backward of one forward clears the per-pair adjoint rows the first filled."""
+    sc = random_scene(335, n=300, sh_degree=1, n_views=2, width=56, height=40, f=50.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    out, buf = ras.render(p, cams, views)
+    g = torch.Generator(device="cuda").manual_seed(336)
+    P = views.n_pixels
+    ups = (torch.randn(3 * P, device="cuda", generator=g), torch.randn(P, device="cuda", generator=g),
+           torch.randn(P, device="cuda", generator=g))
+    res = []
+    for _ in range(2):
+        grads, pose = p.zeros_like(), torch.zeros(views.n_views, 6, device="cuda")
+        ras.backward_into(p, cams, views, buf, out, grads, pose, upstream=ups)
+        res.append((grads, pose, torch.zeros(1, device="cuda")))
+    torch.cuda.synchronize()
+    _same_result(res[1], res[0])
+
+
 def test_captured_forward_backward_replays_match_eager(ras):
     """Forward and fused-loss backward captured in one HIP graph: every replay (with an eager
     backward of the same buffers between replays, which must clear the accumulators the
