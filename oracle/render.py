@@ -32,6 +32,9 @@ Loss (Sec. III-C), summed over views b:
 Gradients: torch float64 autograd through projection and compositing with every discrete
 decision (kept sets, order, stop index, alpha clamp) frozen from the forward pass; the pose
 gradient is with respect to a left perturbation W_b <- Exp(delta_b) W_b, delta = (rho, phi).
+The L1 term's gradient is sign(C - C_gt) dC; an objective evaluated with frozen decisions
+also keeps each pixel channel's sign of C - C_gt from the forward pass, so that finite
+differences of it stay on the branch the gradient is taken on.
 """
 from __future__ import annotations
 
@@ -139,6 +142,7 @@ class Decisions:
     count: np.ndarray      # (P,) number of contributors
     ambiguous: np.ndarray  # (P,) bool: a decision lies within the FP32-vs-FP64 margin
     touched: list          # per pixel: local indices processed (contributors + stopper)
+    l1_sign: np.ndarray = None  # (P_l1, 3) sign of C - C_gt on the L1 pixels, set by the loss
 
 
 def depth_key_range(z64, z_err):
@@ -372,7 +376,12 @@ def loss_and_grads(scene, s: RenderSettings = None, masks=None, lidar=None, gt=N
             if len(l1_pix):
                 tgt = torch.tensor(np.asarray(gt[b], np.float64).reshape(3, -1).T[l1_pix])
                 diff = rgb[sel] - tgt
-                total = total + (1.0 - ssim_w) * w_l1 / (3.0 * len(l1_pix)) * diff.abs().sum()
+                if frozen is not None and dec.l1_sign is not None and dec.l1_sign.shape == tuple(diff.shape):
+                    l1 = (diff * torch.tensor(dec.l1_sign, dtype=DT)).sum()  # the frozen branch of |.|
+                else:
+                    l1 = diff.abs().sum()
+                    dec.l1_sign = np.sign(diff.detach().numpy())
+                total = total + (1.0 - ssim_w) * w_l1 / (3.0 * len(l1_pix)) * l1
                 close = (diff.detach().abs() < sign_margin).any(1).numpy()
                 amb_pix[sel.numpy()[close]] = True
                 if ssim_w > 0.0:

@@ -97,6 +97,41 @@ def test_pose_gradients_match_frozen_decision_finite_differences():
             assert abs(fd - g) <= 1e-6 * abs(g) + 1e-9 * np.abs(r["pose"]).max() + 1e-12, (b, j, fd, g)
 
 
+def test_frozen_objective_keeps_the_l1_signs_of_the_forward_pass():
+    """A target a hair away from the rendered colour (1e-9 beyond it, well inside what a pose
+    step of 1e-6 moves it) puts a kink of |C - C_gt| inside the finite-difference interval:
+    with the signs of the forward pass kept, the difference quotient equals the gradient
+    sign(C - C_gt) dC/d delta; evaluated with fresh signs it would not."""
+    sc = random_scene(23, n_views=1)
+    s = RenderSettings()
+    r0 = render(sc, s)[0]
+    cam = sc.cameras[0]
+    gt = np.asarray(sc.gt_rgb[0], np.float64).copy()
+    # the pixel with the largest colour: its red channel's target sits 1e-9 above the render
+    p = int(np.argmax(r0["rgb"][:, 0]))
+    gt.reshape(3, -1)[0, p] = r0["rgb"][p, 0] + 1e-9
+    r = loss_and_grads(sc, s, gt=[gt], lam=0.0)
+    assert r["decisions"][0].l1_sign is not None
+    h = 1e-6
+    for j in range(6):
+        d = np.zeros((1, 6))
+        d[0, j] = h
+        lp = frozen_objective(sc, r["decisions"], s, gt=[gt], lam=0.0, deltas=d)
+        lm = frozen_objective(sc, r["decisions"], s, gt=[gt], lam=0.0, deltas=-d)
+        fd = (lp - lm) / (2 * h)
+        g = r["pose"][0, j]
+        assert abs(fd - g) <= 1e-6 * abs(g) + 1e-9 * np.abs(r["pose"]).max() + 1e-12, (j, fd, g)
+    # the kink is real: with the signs recomputed at +-h the quotient moves off the gradient
+    off = 0.0
+    for j in range(6):
+        d = np.zeros((1, 6))
+        d[0, j] = h
+        lp = loss_and_grads(sc, s, gt=[gt], lam=0.0, deltas=d)["loss"]
+        lm = loss_and_grads(sc, s, gt=[gt], lam=0.0, deltas=-d)["loss"]
+        off = max(off, abs((lp - lm) / (2 * h) - r["pose"][0, j]))
+    assert off > 1e-6 * np.abs(r["pose"]).max()
+
+
 def test_upstream_mode_gradients_match_finite_differences():
     sc = random_scene(31, n=40)
     rng = np.random.default_rng(32)
