@@ -256,6 +256,8 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
 //     contiguous 512-item slice of the tile, 64 items at a time, against running per-wave
 //     digit counts (ballots inside the 64; 4 KB of counts, so six workgroups fit a CU);
 //     a scan across waves and digits then places the slices.
+// A dropping first pass packs each tile's kept items, in order, into LDS first and ranks
+// only those (a fifth of the tile for the depth sort's pass over every pair).
 // Item order inside a digit is preserved, so the passes compose into a stable sort.
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
@@ -368,11 +370,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_rowscan_kernel(uint32_t* h
     if (threadIdx.x == 0) rowtot[blockIdx.x] = total;
 }
 
+template <bool DROP>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
     long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
-    const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out, bool drop,
+    const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out,
     uint32_t drop_key, uint32_t* n_live) {
+    constexpr bool drop = DROP;
     constexpr int WS = kSortTile / kSortWaves;                // items per wave slice (512)
     __shared__ uint32_t run[256];                             // global cursor per digit
     __shared__ uint32_t wcnt[kSortWaves][256];                // slice counts, then slice bases
@@ -380,6 +384,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __shared__ uint32_t ttot[256];                            // digit count of the tile
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
     __shared__ uint32_t wtot[kSortWaves];
+    __shared__ uint32_t wkept_s[kSortWaves];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     // the digit offsets, the live count and then the first tile's items are loaded before the
     // prologue's barriers, so their round trips overlap instead of following one another
@@ -412,6 +417,47 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         uint32_t dig[kSortItems], rank[kSortItems];
         bool on[kSortItems];
         if (base != start) load_tile(base);
+        // with DROP the tile's kept items are first packed in item order (wave slice, k,
+        // lane) into LDS and read back as a dense tile of `per` items per thread, so the
+        // ranking below runs over the kept items only
+        int per = kSortItems;
+        int ntk = nt;
+        if (DROP) {
+            uint32_t wk = 0, pw[kSortItems];
+            bool keep[kSortItems];
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {
+                keep[k] = w * WS + k * 64 + lane < nt && kv[k] != drop_key;
+                const unsigned long long b = __ballot(keep[k]);
+                pw[k] = wk + lanes_below(b);
+                wk += (uint32_t)__popcll(b);
+            }
+            if (lane == 0) wkept_s[w] = wk;
+            __syncthreads();
+            uint32_t woff = 0, nk = 0;
+#pragma unroll
+            for (int x = 0; x < kSortWaves; ++x) {
+                const uint32_t c = wkept_s[x];
+                woff += x < w ? c : 0u;
+                nk += c;
+            }
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k)
+                if (keep[k]) {
+                    skey[woff + pw[k]] = kv[k];
+                    sval[woff + pw[k]] = vv[k];
+                }
+            __syncthreads();
+            ntk = (int)nk;
+            per = (ntk + kSortThreads - 1) / kSortThreads;
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {
+                const int j = w * 64 * per + k * 64 + lane;
+                const bool in = k < per && j < ntk;
+                kv[k] = in ? skey[j] : 0u;
+                vv[k] = in ? sval[j] : 0u;
+            }
+        }
 #pragma unroll
         for (int x = 0; x < kSortWaves; ++x) wcnt[x][t] = 0;
         __syncthreads();
@@ -420,7 +466,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         // operations of one wave complete in issue order)
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            on[k] = w * WS + k * 64 + lane < nt && !(drop && kv[k] == drop_key);
+            on[k] = DROP ? (k < per && w * 64 * per + k * 64 + lane < ntk) : w * WS + k * 64 + lane < nt;
+            if (DROP && k >= per) {  // wave-uniform: past the dense tile
+                rank[k] = 0u;
+                dig[k] = 0u;
+                continue;
+            }
             dig[k] = (kv[k] >> shift) & mask;
             const unsigned long long m = match_digit(dig[k], dbits, __ballot(on[k]));
             const uint32_t below = lanes_below(m);
@@ -493,10 +544,16 @@ int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, con
         hipLaunchKernelGGL(radix_count_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, n_max, nd, shift, db,
                            tmp.hist, grid, drop, drop_key);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3(256), dim3(kSortThreads), 0, s, tmp.hist, tmp.rowtot, grid);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(grid), dim3(kSortThreads), 0, s, kin, vin, keys[out],
-                           vals[out], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
-                           p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr, drop,
-                           drop_key, n_live);
+        if (drop)
+            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
+                               keys[out], vals[out], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
+                               p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr,
+                               drop_key, n_live);
+        else
+            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3(grid), dim3(kSortThreads), 0, s, kin, vin,
+                               keys[out], vals[out], n_max, nd, shift, db, tmp.hist, tmp.rowtot, grid,
+                               p == passes - 1 ? gather_src : nullptr, p == passes - 1 ? gather_out : nullptr,
+                               drop_key, n_live);
         in = out;
     }
     return in;
