@@ -256,8 +256,10 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
 //     contiguous 512-item slice of the tile, 64 items at a time, against running per-wave
 //     digit counts (ballots inside the 64; 4 KB of counts, so six workgroups fit a CU);
 //     a scan across waves and digits then places the slices.
-// A dropping first pass packs each tile's kept items, in order, into LDS first and ranks
-// only those (a fifth of the tile for the depth sort's pass over every pair).
+// A dropping first pass packs the kept items of successive tiles, in order, into an LDS
+// buffer and ranks and writes the buffer whenever the next tile's would not fit, so it ranks
+// kept items only (a fifth of the items in the depth sort's pass over every pair), several
+// tiles' worth at a time.
 // Item order inside a digit is preserved, so the passes compose into a stable sort.
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
@@ -376,15 +378,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     long long n_max, const uint32_t* n_dev, int shift, int dbits, const uint32_t* hist,
     const uint32_t* rowtot, int grid, const uint32_t* gather_src, uint32_t* gather_out,
     uint32_t drop_key, uint32_t* n_live) {
-    constexpr bool drop = DROP;
     constexpr int WS = kSortTile / kSortWaves;                // items per wave slice (512)
     __shared__ uint32_t run[256];                             // global cursor per digit
     __shared__ uint32_t wcnt[kSortWaves][256];                // slice counts, then slice bases
     __shared__ uint32_t tstart[256];                          // digit start inside the tile
     __shared__ uint32_t ttot[256];                            // digit count of the tile
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
+    __shared__ uint32_t bkey[DROP ? kSortTile : 1], bval[DROP ? kSortTile : 1];  // kept items, in order
     __shared__ uint32_t wtot[kSortWaves];
-    __shared__ uint32_t wkept_s[kSortWaves];
+    __shared__ uint32_t wkept[kSortWaves];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     // the digit offsets, the live count and then the first tile's items are loaded before the
     // prologue's barriers, so their round trips overlap instead of following one another
@@ -408,56 +410,16 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         uint32_t total;
         const uint32_t base = sort_block_scan(my_rowtot, wtot, total);
         run[t] = base + my_hist;
-        if (drop && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
+        if (DROP && n_live && blockIdx.x == 0 && t == 0) *n_live = total;  // items kept
     }
     const uint32_t mask = (1u << dbits) - 1u;
     uint32_t* const cw = wcnt[w];
-    for (long long base = start; base < end; base += kSortTile) {
-        const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
+    // Ranks `cnt` items held `per` to a thread (item k * 64 + lane of wave w's slice of 64 per
+    // items is (rk[k], rv[k])), regroups them by digit in LDS and writes each digit's run to
+    // its global cursor, which then advances.
+    auto rank_write = [&](const uint32_t* rk, const uint32_t* rv, int per, int cnt) {
         uint32_t dig[kSortItems], rank[kSortItems];
         bool on[kSortItems];
-        if (base != start) load_tile(base);
-        // with DROP the tile's kept items are first packed in item order (wave slice, k,
-        // lane) into LDS and read back as a dense tile of `per` items per thread, so the
-        // ranking below runs over the kept items only
-        int per = kSortItems;
-        int ntk = nt;
-        if (DROP) {
-            uint32_t wk = 0, pw[kSortItems];
-            bool keep[kSortItems];
-#pragma unroll
-            for (int k = 0; k < kSortItems; ++k) {
-                keep[k] = w * WS + k * 64 + lane < nt && kv[k] != drop_key;
-                const unsigned long long b = __ballot(keep[k]);
-                pw[k] = wk + lanes_below(b);
-                wk += (uint32_t)__popcll(b);
-            }
-            if (lane == 0) wkept_s[w] = wk;
-            __syncthreads();
-            uint32_t woff = 0, nk = 0;
-#pragma unroll
-            for (int x = 0; x < kSortWaves; ++x) {
-                const uint32_t c = wkept_s[x];
-                woff += x < w ? c : 0u;
-                nk += c;
-            }
-#pragma unroll
-            for (int k = 0; k < kSortItems; ++k)
-                if (keep[k]) {
-                    skey[woff + pw[k]] = kv[k];
-                    sval[woff + pw[k]] = vv[k];
-                }
-            __syncthreads();
-            ntk = (int)nk;
-            per = (ntk + kSortThreads - 1) / kSortThreads;
-#pragma unroll
-            for (int k = 0; k < kSortItems; ++k) {
-                const int j = w * 64 * per + k * 64 + lane;
-                const bool in = k < per && j < ntk;
-                kv[k] = in ? skey[j] : 0u;
-                vv[k] = in ? sval[j] : 0u;
-            }
-        }
 #pragma unroll
         for (int x = 0; x < kSortWaves; ++x) wcnt[x][t] = 0;
         __syncthreads();
@@ -466,13 +428,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         // operations of one wave complete in issue order)
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            on[k] = DROP ? (k < per && w * 64 * per + k * 64 + lane < ntk) : w * WS + k * 64 + lane < nt;
-            if (DROP && k >= per) {  // wave-uniform: past the dense tile
-                rank[k] = 0u;
-                dig[k] = 0u;
-                continue;
-            }
-            dig[k] = (kv[k] >> shift) & mask;
+            on[k] = k < per && w * 64 * per + k * 64 + lane < cnt;
+            dig[k] = (rk[k] >> shift) & mask;
+            rank[k] = 0u;
+            if (k >= per) continue;  // wave-uniform
             const unsigned long long m = match_digit(dig[k], dbits, __ballot(on[k]));
             const uint32_t below = lanes_below(m);
             const uint32_t prev = on[k] ? cw[dig[k]] : 0u;
@@ -490,7 +449,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
             wcnt[x][t] = r;
             r += c;
         }
-        uint32_t total;  // items of the tile taking part (all, or those not dropped)
+        uint32_t total;  // == cnt
         const uint32_t ds = sort_block_scan(r, wtot, total);
         tstart[t] = ds;
         ttot[t] = r;
@@ -499,8 +458,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         for (int k = 0; k < kSortItems; ++k) {
             if (on[k]) {
                 const uint32_t pos = tstart[dig[k]] + cw[dig[k]] + rank[k];
-                skey[pos] = kv[k];
-                sval[pos] = vv[k];
+                skey[pos] = rk[k];
+                sval[pos] = rv[k];
             }
         }
         __syncthreads();
@@ -519,7 +478,64 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         }
         __syncthreads();
         run[t] += ttot[t];
+    };
+    if (!DROP) {
+        for (long long base = start; base < end; base += kSortTile) {
+            if (base != start) load_tile(base);
+            rank_write(kv, vv, kSortItems, end - base < kSortTile ? (int)(end - base) : kSortTile);
+        }
+        return;
     }
+    // Dropping pass: the kept items of successive tiles are packed, in item order (wave slice,
+    // k, lane), into the LDS buffer, and the buffer is ranked and written out whenever the
+    // next tile's kept items would not fit (and at the end), so the ranking runs over kept
+    // items only, and over several tiles at once when most items are dropped.
+    int buffered = 0;  // workgroup-uniform
+    uint32_t bk[kSortItems], bv[kSortItems];
+    auto flush = [&]() {
+        const int per = (buffered + kSortThreads - 1) / kSortThreads;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const int j = w * 64 * per + k * 64 + lane;
+            const bool in = k < per && j < buffered;
+            bk[k] = in ? bkey[j] : 0u;
+            bv[k] = in ? bval[j] : 0u;
+        }
+        rank_write(bk, bv, per, buffered);
+        buffered = 0;
+    };
+    for (long long base = start; base < end; base += kSortTile) {
+        const int nt = end - base < kSortTile ? (int)(end - base) : kSortTile;
+        if (base != start) load_tile(base);
+        uint32_t wk = 0, pw[kSortItems];
+        bool keep[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            keep[k] = w * WS + k * 64 + lane < nt && kv[k] != drop_key;
+            const unsigned long long b = __ballot(keep[k]);
+            pw[k] = wk + lanes_below(b);
+            wk += (uint32_t)__popcll(b);
+        }
+        if (lane == 0) wkept[w] = wk;
+        __syncthreads();
+        uint32_t woff = 0, nk = 0;
+#pragma unroll
+        for (int x = 0; x < kSortWaves; ++x) {
+            const uint32_t c = wkept[x];
+            woff += x < w ? c : 0u;
+            nk += c;
+        }
+        if (buffered + (int)nk > kSortTile) flush();  // its barriers also order the wkept reads
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k)
+            if (keep[k]) {
+                bkey[buffered + woff + pw[k]] = kv[k];
+                bval[buffered + woff + pw[k]] = vv[k];
+            }
+        buffered += (int)nk;
+        __syncthreads();
+    }
+    if (buffered > 0) flush();
 }
 
 int launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], long long n_max, const uint32_t* n_dev,
