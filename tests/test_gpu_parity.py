@@ -87,10 +87,10 @@ def test_projection_records_match_oracle(ras):
         base += n
 
 
-def _synthetic_records(rng, n_views, n, sizes, T, margin=30):
+def _synthetic_records(rng, n_views, n, sizes, T, margin=30, keep_frac=0.75):
     """Seeded records: centre (up to `margin` px outside the view), conic of a random
     positive-definite screen covariance, opacity, quantised depth (exact ties) and the
-    half-widths of the alpha = 1/255 level."""
+    half-widths of the alpha = 1/255 level; a share `keep_frac` of the pairs is valid."""
     recs, valid, ref_in = [], [], []
     for b in range(n_views):
         W, H = sizes[b]
@@ -107,7 +107,7 @@ def _synthetic_records(rng, n_views, n, sizes, T, margin=30):
         ex = np.sqrt(tau * cxx).astype(np.float32)
         ey = np.sqrt(tau * cyy).astype(np.float32)
         z = (np.round(rng.uniform(0.5, 4.0, n) * 16) / 16).astype(np.float32)  # exact ties
-        ok = rng.uniform(size=n) > 0.25
+        ok = rng.uniform(size=n) < keep_frac
         r = np.zeros((n, 12), np.float32)
         r[:, 0], r[:, 1], r[:, 2], r[:, 3], r[:, 4] = u, v, ca, cb, cc
         r[:, 5], r[:, 6], r[:, 7], r[:, 8] = o.astype(np.float32), z, ex, ey
@@ -188,6 +188,34 @@ def test_binning_bit_exact_with_long_tile_lists():
     sv = saved_arrays(buf, views)
     assert sv["K"] == cap and sv["n_listed"] == len(keys)
     assert np.array_equal(sv["tile_pairs"], vals.astype(np.int64))
+    assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
+    _check_work_list(sv["work"], sv["ranges"])
+
+
+@pytest.mark.parametrize("keep_frac", [0.2, 0.6, 0.97])
+def test_binning_bit_exact_with_several_sort_tiles_per_workgroup(keep_frac):
+    """120,000 pairs in one 320 x 240 view: each radix workgroup of the depth sort owns four
+    2,048-item tiles, so its dropping first pass packs the kept pairs of several tiles before
+    ranking them (a fifth valid: one ranking round for all four; 60 %: rounds across tile
+    boundaries; 97 %: about one per tile), and the tile sort's workgroups own several tiles
+    too; lists, keys and ranges bit for bit against the reference."""
+    from paper_2510_26358_amd.rasterizer import Rasterizer, ViewSpec
+    r = Rasterizer(0, tile=16, batch=256, px_per_thread=1)
+    rng = np.random.default_rng(1200 + int(100 * keep_frac))
+    n, sizes = 120_000, [(320, 240)]
+    recs, valid, ref_in = _synthetic_records(rng, 1, n, sizes, 16, keep_frac=keep_frac)
+    views = ViewSpec([320], [240], [0], [n])
+    keys, vals, ranges, counts, base = bin_reference(ref_in, [(320, 240, 0)], 16)
+    cap = int(sum(int(c.sum()) for c in counts))
+    buf = r.buffers(views, n, 0, cap)
+    r.bin_records(views, n, torch.from_numpy(recs).cuda(), torch.from_numpy(valid.astype(np.uint8)).cuda(), buf)
+    torch.cuda.synchronize()
+    sv = saved_arrays(buf, views)
+    assert sv["K"] == cap and not sv["overflow"] and sv["n_listed"] == len(keys)
+    assert np.array_equal(sv["pair_count"], np.concatenate(counts))
+    assert np.array_equal(sv["tile_pairs"], vals.astype(np.int64))
+    zb = recs[:, 6].view(np.uint32).astype(np.uint64)[sv["tile_pairs"]]
+    assert np.array_equal((sv["tile_keys"].astype(np.uint64) << np.uint64(32)) | zb, keys)
     assert np.array_equal(sv["ranges"], ranges.astype(np.int64))
     _check_work_list(sv["work"], sv["ranges"])
 
