@@ -221,6 +221,38 @@ def test_second_upstream_backward_of_one_forward_matches_the_first(ras):
     _same_result(res[1], res[0])
 
 
+def test_stage_profile_shows_the_clear_only_for_a_second_backward(ras):
+    """The context's stage timers (ags_profile_*): a forward and its fused-loss backward launch
+    every stage of the step once and no clear (the forward zeroed the accumulators); a second
+    backward of the same forward launches the clear once; reset empties the totals."""
+    sc = random_scene(351, n=300, sh_degree=1, n_views=2, width=48, height=40, f=50.0)
+    views = ViewSpec.from_scene(sc)
+    p = SplatParams.from_scene(sc)
+    cams = cameras_tensor(sc.cameras)
+    tg = LossTargets.from_scene(sc, views)
+    out, buf = ras.render(p, cams, views)
+    torch.cuda.synchronize()
+    ras.profile_reset()
+    ras.profile(True)
+    try:
+        ras.forward_into(p, cams, views, buf, out)
+        _loss_backward(ras, p, cams, views, buf, out, tg)
+        torch.cuda.synchronize()
+        first = ras.profile_read()
+        _loss_backward(ras, p, cams, views, buf, out, tg)
+        torch.cuda.synchronize()
+        second = ras.profile_read()
+        ras.profile_reset()
+        after_reset = ras.profile_read()
+    finally:
+        ras.profile(False)
+    for st in ("project_fwd", "binning", "raster_fwd", "lidar_adjoint", "raster_bwd", "project_bwd"):
+        assert first[st][1] == 1 and first[st][0] > 0.0, (st, first[st])
+        assert second[st][1] == (1 if st in ("project_fwd", "binning", "raster_fwd") else 2), (st, second[st])
+    assert first["clear"][1] == 0 and second["clear"][1] == 1
+    assert all(c == 0 for _, c in after_reset.values())
+
+
 def test_captured_forward_backward_replays_match_eager(ras):
     """Forward and fused-loss backward captured in one HIP graph: every replay (with an eager
     backward of the same buffers between replays, which must clear the accumulators the
