@@ -382,6 +382,7 @@ __device__ __forceinline__ float wave_transpose_sum10(const float (&v)[10]) {
     }
     w1 += dpp_mov<0xB1>(w1);  // quad_perm [1, 0, 3, 2]: lane ^ 1
     w1 += dpp_mov<0x4E>(w1);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+    asm volatile("" : "+v"(w1));  // the last step stays one DPP add, ahead of the caller's branch
     return w1;
 }
 

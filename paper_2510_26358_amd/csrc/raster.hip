@@ -7,7 +7,9 @@
 //   power = -1/2 (a dx^2 + c dy^2) - b dx dy, (dx, dy) = (u, v) - pixel centre
 //   alpha = min(alpha_max, o e^power), skipped when power > 0 or alpha < alpha_min
 //   T' = T (1 - alpha); stop (excluding this Gaussian) when T' < t_min
-//   C += alpha T rgb; D += alpha T z; A += alpha T; T = T'
+//   C += alpha T rgb; D += alpha T z; T = T'
+// and the accumulated alpha A = sum alpha T is written as 1 - T_final (the same sum, not
+// accumulated in the loop).
 // A workgroup stops fetching batches once every pixel has stopped, and a wave whose lanes
 // have all stopped skips the rest of a batch.  The forward keeps 8 bytes per pixel
 // (final T and the list position of the last contributor) so the backward recomputes
@@ -244,9 +246,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                 const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
                 const bool keep = p2 <= 0.f && alpha >= amin;
                 if (keep) {
-                    // stop (once per pixel) before a Gaussian that would take T below t_min
-                    const bool go = Tr[k] * (1.f - alpha) >= tmin;
-                    cx[k] += go ? 0.f : kStopped;  // +inf marks the pixel stopped
+                    // stop (once per pixel) before a Gaussian that would take T below t_min;
+                    // the tested T (1 - alpha), one rounding, is the next T
+                    const float Tn = __builtin_fmaf(-alpha, Tr[k], Tr[k]);
+                    const bool go = Tn >= tmin;
+                    cx[k] = go ? cx[k] : kStopped;  // +inf marks the pixel stopped
+                    in_vgpr(cx[k]);                 // one select here, not moves in both branches
                     if (go) {
                         const float4 rc = r.m;
                         const float w = alpha * Tr[k];
@@ -254,13 +259,13 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                         C1[k] += w * rc.z;
                         C2[k] += w * rc.w;
                         D[k] += w * r1.z;
-                        A[k] += w;
                         if (S2) {
+                            A[k] += w;
                             const float dz = r1.z - Mn[k];
                             Mn[k] += dz * (w * __builtin_amdgcn_rcpf(A[k]));
                             Sc[k] += w * dz * (r1.z - Mn[k]);
                         }
-                        Tr[k] = __builtin_fmaf(-alpha, Tr[k], Tr[k]);  // T (1 - alpha), one rounding
+                        Tr[k] = Tn;
                         last[k] = e - start + 1;
                     }
                 }
@@ -282,7 +287,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         rgb[2 * plane + p] = C2[k] + Tr[k] * a.st.bg2;
         a.depth[gp] = D[k];
         if (S2) a.depth_var[gp] = Sc[k] + A[k] * Tr[k] * Mn[k] * Mn[k];
-        a.alpha[gp] = A[k];
+        a.alpha[gp] = 1.f - Tr[k];
         a.t_final[gp] = Tr[k];
         a.last[gp] = last[k];
         if (a.zero_px[0]) a.zero_px[0][gp] = 0.f;
