@@ -230,12 +230,9 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         const char* sbase = reinterpret_cast<const char*>(srec);
         uint32_t off = 0;  // byte offset of record e - bs in LDS
         in_vgpr(off);
-        for (uint32_t e = bs; e < bend; ++e, off += sizeof(SRec)) {
-            bool live = false;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) live |= cx[k] != kStopped;
-            if (__ballot(live) == 0ull) break;  // wave-uniform: every pixel has stopped
-            const SRec& r = *reinterpret_cast<const SRec*>(sbase + off);
+        // entries in pairs: the second record is read at an immediate offset from the first's
+        // LDS address, so the address advances once per two entries
+        auto entry = [&](const SRec& r, uint32_t e) {
             const float4 r0 = r.g0, r1 = r.g1;
             use_record(r0, r1);
 #pragma unroll
@@ -270,6 +267,18 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                     }
                 }
             }
+        };
+        auto wave_live = [&]() {
+            bool live = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) live |= cx[k] != kStopped;
+            return __ballot(live) != 0ull;  // wave-uniform: false once every pixel has stopped
+        };
+        for (uint32_t e = bs; e < bend; e += 2, off += 2 * sizeof(SRec)) {
+            if (!wave_live()) break;
+            entry(*reinterpret_cast<const SRec*>(sbase + off), e);
+            if (e + 1 == bend || !wave_live()) break;
+            entry(*reinterpret_cast<const SRec*>(sbase + off + sizeof(SRec)), e + 1);
         }
         __syncthreads();
     }
