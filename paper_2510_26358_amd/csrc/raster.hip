@@ -230,7 +230,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         const char* sbase = reinterpret_cast<const char*>(srec);
         uint32_t off = 0;  // byte offset of record e - bs in LDS
         in_vgpr(off);
-        // entries in groups of four: the later records are read at immediate offsets from the
+        // entries in groups of eight: the later records are read at immediate offsets from the
         // first's LDS address, so the address advances once per group, and the wave's early
         // exit is tested once per group (entries past a wave's stop keep nothing: a stopped
         // pixel's exponent is -inf or NaN)
@@ -276,15 +276,14 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
             for (int k = 0; k < PPT; ++k) live |= cx[k] != kStopped;
             return __ballot(live) != 0ull;  // wave-uniform: false once every pixel has stopped
         };
-        for (uint32_t e = bs; e < bend; e += 4, off += 4 * sizeof(SRec)) {
+        for (uint32_t e = bs; e < bend; e += 8, off += 8 * sizeof(SRec)) {
             if (!wave_live()) break;
             entry(*reinterpret_cast<const SRec*>(sbase + off), e);
-            if (e + 1 == bend) break;
-            entry(*reinterpret_cast<const SRec*>(sbase + off + sizeof(SRec)), e + 1);
-            if (e + 2 == bend) break;
-            entry(*reinterpret_cast<const SRec*>(sbase + off + 2 * sizeof(SRec)), e + 2);
-            if (e + 3 == bend) break;
-            entry(*reinterpret_cast<const SRec*>(sbase + off + 3 * sizeof(SRec)), e + 3);
+#pragma unroll
+            for (int g = 1; g < 8; ++g) {
+                if (e + g == bend) break;
+                entry(*reinterpret_cast<const SRec*>(sbase + off + g * sizeof(SRec)), e + g);
+            }
         }
         __syncthreads();
     }
