@@ -444,13 +444,12 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         prev_n = hi - lo;
         __syncthreads();
         const int jtop = min(hi, wl);  // wave-uniform
-        int e = jtop - 1 - lo;         // LDS slot, advanced in a vector register
-        in_vgpr(e);
-        for (int j = jtop - 1; j >= lo; --j, --e) {
-            const SRec& r = srec[e];
+        // entries in groups of four, back to front: the group's records are read at immediate
+        // offsets from the LDS address of its lowest entry, which moves once per group
+        auto entry = [&](const SRec& r, int j, int e) {
             const float4 rm = r.m, r0 = r.g0, r1 = r.g1;
             use_record(rm, r0, r1);
-            if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) continue;  // wave-uniform
+            if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) return;  // wave-uniform
             const float z2 = S2 ? r.z2 : 0.f;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
             // passes (every lane that keeps this Gaussian passes: the floor sits a margin below
@@ -464,7 +463,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
                 pass[k] = (uint32_t)j < last[k] && p2v[k] <= 0.f && p2v[k] >= r1.w;
                 anyp |= pass[k];
             }
-            if (__ballot(anyp) == 0ull) continue;  // wave-uniform
+            if (__ballot(anyp) == 0ull) return;  // wave-uniform
             float g[10];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -506,7 +505,17 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             } else {
                 if (red_lane) atomicAdd(a.grad2d + (long long)r.q * kGrad2dStride + red_val, tot);
             }
+        };
+        const char* sbase = reinterpret_cast<const char*>(srec);
+        int j = jtop - 1;
+        int ofs = (j - 3 - lo) * (int)sizeof(SRec);  // byte offset of the group's lowest entry
+        in_vgpr(ofs);
+        for (; j >= lo + 3; j -= 4, ofs -= 4 * (int)sizeof(SRec)) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                entry(*reinterpret_cast<const SRec*>(sbase + ofs + (3 - g) * (int)sizeof(SRec)), j - g, j - g - lo);
         }
+        for (; j >= lo; --j) entry(srec[j - lo], j, j - lo);
         __syncthreads();
     }
     if (MERGE) flush(prev_n, sq[buf ^ 1]);
