@@ -132,8 +132,11 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 // log2: the 1e-4 margin keeps every kept pair above the floor, so the pre-test never
 // changes a decision; every skipped pair has alpha < alpha_min.
 // LDS layout (64 B, read at non-negative offsets from one per-lane address):
-//   [0] = (wave mask bits, r, g, b), [1] = (u, v, -a/2 log2e, -b log2e),
-//   [2] = (-c/2 log2e, o, z, exponent floor), [3] = (pair id, z^2, -, -).
+//   [0] = (wave mask bits, r, g, b) in the backward, (z, r, g, b) in the forward,
+//   [1] = (u, v, -a/2 log2e, -b log2e), [2] = (-c/2 log2e, o, z, exponent floor),
+//   [3] = (pair id, z^2, -, -).
+// The forward reads 24 bytes of an entry ([1] and the first half of [2]) before its keep
+// test and [0] only for a pixel that takes the Gaussian.
 struct alignas(16) SRec {
     float4 m, g0, g1;
     uint32_t q;
@@ -149,7 +152,7 @@ __device__ __forceinline__ void stage_record(const float* records, uint32_t q, f
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
     constexpr float kLog2e = 1.4426950408889634f;
     const uint32_t m = BLOCKS ? wave_mask<T, PPT, BLOCKS>(r0.x, r0.y, r1.w, r2.x, W, H, px0, py0) : ~0u;
-    dst.m = make_float4(__uint_as_float(m), r2.y, r2.z, r2.w);
+    dst.m = make_float4(BLOCKS ? __uint_as_float(m) : r1.z, r2.y, r2.z, r2.w);
     dst.g0 = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
     dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y) - kPreTestMargin);
     dst.q = q;
@@ -235,13 +238,14 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
         // exit is tested once per group (entries past a wave's stop keep nothing: a stopped
         // pixel's exponent is -inf or NaN)
         auto entry = [&](const SRec& r, uint32_t e) {
-            const float4 r0 = r.g0, r1 = r.g1;
-            use_record(r0, r1);
+            const float4 r0 = r.g0;
+            const float2 r1 = *reinterpret_cast<const float2*>(&r.g1);  // (C', o)
+            use_record(r0, make_float4(r1.x, r1.y, 0.f, 0.f));
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 // one predicate, one branch: the exp is cheap next to divergent control
                 const float dx = r0.x - cx[k], dy = r0.y - cy[k];
-                const float p2 = power_of(r0, r1, dx, dy);
+                const float p2 = dx * (r0.z * dx + r0.w * dy) + r1.x * dy * dy;
                 const float alpha = fminf(amax, r1.y * __builtin_amdgcn_exp2f(p2));
                 const bool keep = p2 <= 0.f && alpha >= amin;
                 if (keep) {
@@ -252,17 +256,17 @@ __global__ __launch_bounds__(T* T / PPT) void raster_fwd_kernel(RasterArgs a) {
                     cx[k] = go ? cx[k] : kStopped;  // +inf marks the pixel stopped
                     in_vgpr(cx[k]);                 // one select here, not moves in both branches
                     if (go) {
-                        const float4 rc = r.m;
+                        const float4 rc = r.m;  // (z, r, g, b)
                         const float w = alpha * Tr[k];
                         C0[k] += w * rc.y;
                         C1[k] += w * rc.z;
                         C2[k] += w * rc.w;
-                        D[k] += w * r1.z;
+                        D[k] += w * rc.x;
                         if (S2) {
                             A[k] += w;
-                            const float dz = r1.z - Mn[k];
+                            const float dz = rc.x - Mn[k];
                             Mn[k] += dz * (w * __builtin_amdgcn_rcpf(A[k]));
-                            Sc[k] += w * dz * (r1.z - Mn[k]);
+                            Sc[k] += w * dz * (rc.x - Mn[k]);
                         }
                         Tr[k] = Tn;
                         last[k] = e - start + 1;
