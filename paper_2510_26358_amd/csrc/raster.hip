@@ -134,20 +134,20 @@ __device__ __forceinline__ uint32_t wave_mask(float u, float v, float ex, float 
 // LDS layout (64 B, read at non-negative offsets from one per-lane address):
 //   [0] = (wave mask bits, r, g, b) in the backward, (z, r, g, b) in the forward,
 //   [1] = (u, v, -a/2 log2e, -b log2e), [2] = (-c/2 log2e, o, z, exponent floor),
-//   [3] = (pair id, z^2, -, -).
+//   [3] = (pair id, z^2, address of the pair's 2D adjoint row (backward)).
 // The forward reads 24 bytes of an entry ([1] and the first half of [2]) before its keep
 // test and [0] only for a pixel that takes the Gaussian.
 struct alignas(16) SRec {
     float4 m, g0, g1;
     uint32_t q;
     float z2;
-    uint32_t pad[2];
+    float* row;  // the pair's 2D adjoint row (backward)
 };
 
 constexpr float kPreTestMargin = 1e-4f;
 template <int T, int PPT, bool BLOCKS>
 __device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
-                                             int px0, int py0, SRec& dst) {
+                                             int px0, int py0, SRec& dst, float* grad2d = nullptr) {
     const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
     constexpr float kLog2e = 1.4426950408889634f;
@@ -157,6 +157,7 @@ __device__ __forceinline__ void stage_record(const float* records, uint32_t q, f
     dst.g1 = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, __log2f(amin / r1.y) - kPreTestMargin);
     dst.q = q;
     dst.z2 = r1.z * r1.z;
+    if (BLOCKS) dst.row = grad2d + (long long)q * kGrad2dStride;
 }
 
 // Makes the record's fields live at this point, so all of its LDS reads are issued together
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         if (MERGE) flush(prev_n, sq[buf ^ 1]);  // the previous batch, while this one is staged
         for (int l = tid; l < hi - lo; l += NT) {
             const uint32_t q = a.tile_pairs[start + lo + l];
-            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l]);
+            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l], a.grad2d);
             if (MERGE) sq[buf][l] = q;
         }
         prev_n = hi - lo;
@@ -452,6 +453,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
         // offsets from the LDS address of its lowest entry, which moves once per group
         auto entry = [&](const SRec& r, int j, int e) {
             const float4 rm = r.m, r0 = r.g0, r1 = r.g1;
+            float* const row = MERGE ? nullptr : r.row;
             use_record(rm, r0, r1);
             if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) return;  // wave-uniform
             const float z2 = S2 ? r.z2 : 0.f;
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
             if (MERGE) {
                 if (red_lane) atomicAdd(&sacc[e * kGrad2d + red_val], tot);
             } else {
-                if (red_lane) atomicAdd(a.grad2d + (long long)r.q * kGrad2dStride + red_val, tot);
+                if (red_lane) atomicAdd(row + red_val, tot);
             }
         };
         const char* sbase = reinterpret_cast<const char*>(srec);
