@@ -126,9 +126,10 @@ def project(p, cam, delta, s: RenderSettings, sh_degree: int):
     Y = real_sh(sh_degree, d)                       # (n, K)
     raw = torch.einsum("nk,nkc->nc", Y, p["sh"][g0:g1]) + 0.5
     rgb = torch.clamp(raw, min=0.0)
-    # footprint bounding half-extents (for the binning reference and diagnostics)
+    # footprint bounding half-extents (for the binning reference and diagnostics): the box of
+    # the alpha = alpha_min level, o exp(-q/2) = alpha_min at q = 2 ln(o / alpha_min)
     with torch.no_grad():
-        lnterm = torch.where(valid, 2.0 * torch.log(255.0 * o.clamp_min(1e-30)), zero)
+        lnterm = torch.where(valid, 2.0 * torch.log(o.clamp_min(1e-30) / s.alpha_min), zero)
         ext = torch.stack([torch.sqrt(lnterm.clamp_min(0) * a), torch.sqrt(lnterm.clamp_min(0) * c)], -1)
     return {"u": u, "v": v, "conic": conic, "o": o, "rgb": rgb, "z": z, "valid": valid,
             "cov2d": S2, "ext": ext, "g0": g0, "z_err": z_err}

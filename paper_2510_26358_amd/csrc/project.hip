@@ -7,8 +7,8 @@
 //   Sigma' = J R_b Sigma R_b^T J^T + blur I; conic = Sigma'^{-1};
 //   (u, v) = (fx x/z + cx, fy y/z + cy); o = sigmoid(omega);
 //   colour = max(0, SH(d) . f + 0.5) with d the unit direction from the camera centre;
-//   opacity-aware footprint half-extents ex = sqrt(2 ln(255 o) Sigma'_xx), ey likewise
-//   (the box outside which alpha < 1/255), the tile rectangle and its tile count; a kept pair's
+//   opacity-aware footprint half-extents ex = sqrt(2 ln(o / alpha_min) Sigma'_xx), ey likewise
+//   (the box outside which alpha < alpha_min), the tile rectangle and its tile count; a kept pair's
 //   row of the backward's 2D adjoint accumulator is zeroed.
 // Culled pairs (z < z_near, det <= 0, o < alpha_min, empty rectangle) get count 0 and no
 // record.
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectArgs a) {
     const float S11 = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
     const float S12 = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
     const float S22 = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-    const float lnterm = 2.f * __logf(255.f * o);
+    const float lnterm = 2.f * __logf(o / a.st.alpha_min);
 
     uint32_t vis = 0;  // views that keep this Gaussian (at most 32)
     for (int b = 0; b < vt.n_views; ++b) {

@@ -304,6 +304,30 @@ def test_loss_and_gradients_tiny_l1(ras):
     assert ok, msg
 
 
+@pytest.mark.parametrize("alpha_min", [1e-3, 2e-2])
+def test_forward_and_gradients_with_another_alpha_cutoff(alpha_min):
+    """The configured alpha_min sets both the keep test and the footprint box the tile lists
+    come from: with a cutoff below the default 1/255 the boxes grow (no contributing pair is
+    left out of the lists), above it they shrink."""
+    from paper_2510_26358_amd.rasterizer import Rasterizer
+    r = Rasterizer(0, alpha_min=alpha_min)
+    s = RenderSettings(alpha_min=alpha_min)
+    sc = scenes.tiny_scene()
+    gpu, _ = run_forward(sc, r)
+    _compare_forward(gpu, render(sc, s), sc)
+    g = run_loss_backward(sc, r)
+    ref = loss_and_grads(sc, s)
+    print("loss", g["loss"], ref["loss"], "excluded gaussians", ref["amb_gauss"].sum())
+    assert abs(g["loss"] - ref["loss"]) <= 1e-5 * max(1, abs(ref["loss"]))
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ok, msg = grad_close(g["grads"][name], ref["grads"][name], ref["amb_gauss"])
+        print(name, msg)
+        assert ok, (name, msg)
+    ok, msg = grad_close(g["pose"], ref["pose"])
+    print("pose", msg)
+    assert ok, msg
+
+
 @pytest.mark.parametrize("seed,n_views", [(201, 1), (202, 2)])
 def test_loss_and_gradients_sh3_lidar(ras, seed, n_views):
     sc = random_scene(seed, n=400, sh_degree=3, n_views=n_views, width=64, height=48, f=60.0)

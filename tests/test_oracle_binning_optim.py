@@ -4,6 +4,7 @@ refinement of splats and poses, Sec. III-C)."""
 import math
 
 import numpy as np
+import pytest
 import scipy.linalg
 import torch
 
@@ -144,12 +145,14 @@ def test_float32_tile_rule_agrees_with_its_float64_statement():
     assert kept and (got - amb) == kept
 
 
-def test_every_contributing_pixel_lies_in_its_gaussians_tiles():
+@pytest.mark.parametrize("alpha_min", [1.0 / 255.0, 1e-3, 2e-2])
+def test_every_contributing_pixel_lies_in_its_gaussians_tiles(alpha_min):
     """The opacity-aware bounding box, and the ellipse test on its tiles, must cover every
-    pixel where the brute-force compositing keeps the Gaussian (alpha >= 1/255), for each
-    tile size."""
+    pixel where the brute-force compositing keeps the Gaussian (alpha >= alpha_min), for each
+    tile size and for cutoffs below and above the default 1/255 (the box is the alpha_min
+    level of the configured cutoff)."""
     sc = tiny_scene()
-    s = RenderSettings()
+    s = RenderSettings(alpha_min=alpha_min)
     out = render(sc, s)[0]
     pr = out["proj"]
     dec = out["dec"]
