@@ -59,7 +59,8 @@ enum {
 
 /* Rendering settings.  The paper defers these to "standard 3DGS"; the defaults of
  * ags_config_default() are: alpha_min 1/255 (a Gaussian whose alpha is below it is
- * skipped), alpha_max 0.99 (alpha clamp), t_min 1e-4 (compositing stops before the
+ * skipped; the footprint box each Gaussian is binned by is the level of this cutoff),
+ * alpha_max 0.99 (alpha clamp), t_min 1e-4 (compositing stops before the
  * transmittance would drop below it; that Gaussian is excluded), blur 0.3 px^2 added to
  * the diagonal of Sigma', z_near 0.2 (Gaussians closer are culled), fov_clamp 1.3 (x/z
  * and y/z clamped to +-1.3 half-FOV tangents inside J only), bg = 0, tile 16, batch 256,
@@ -134,7 +135,8 @@ typedef struct ags_grads {
 } ags_grads;
 
 /* Forward outputs (device float32): rgb [3 * P], depth [P] (expected depth: sum of
- * w_i z_i, unnormalised, z the camera-frame depth of the mean), alpha [P]; P = total pixels. */
+ * w_i z_i, unnormalised, z the camera-frame depth of the mean), alpha [P] (the accumulated
+ * sum of w_i, written as 1 - the final transmittance); P = total pixels. */
 typedef struct ags_fwd_out {
     float* rgb;
     float* depth;
