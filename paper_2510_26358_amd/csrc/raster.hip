@@ -146,8 +146,8 @@ struct alignas(16) SRec {
 
 constexpr float kPreTestMargin = 1e-4f;
 template <int T, int PPT, bool BLOCKS>
-__device__ __forceinline__ void stage_record(const float* records, uint32_t q, float amin, int W, int H,
-                                             int px0, int py0, SRec& dst, float* grad2d = nullptr) {
+__device__ __forceinline__ uint32_t stage_record(const float* records, uint32_t q, float amin, int W, int H,
+                                                 int px0, int py0, SRec& dst, float* grad2d = nullptr) {
     const float4* r = reinterpret_cast<const float4*>(records + (long long)q * kRecFloats);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2];
     constexpr float kLog2e = 1.4426950408889634f;
@@ -158,6 +158,7 @@ __device__ __forceinline__ void stage_record(const float* records, uint32_t q, f
     dst.q = q;
     dst.z2 = r1.z * r1.z;
     if (BLOCKS) dst.row = grad2d + (long long)q * kGrad2dStride;
+    return m;
 }
 
 // Makes the record's fields live at this point, so all of its LDS reads are issued together
@@ -326,6 +327,11 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     __shared__ uint32_t sq[2][MERGE ? M : 1];        // the pairs of this batch and the previous
     __shared__ uint32_t smax;
     __shared__ float sred[NT / 64];
+    // per wave, one bit per LDS slot of the batch: the record's footprint box meets the wave's
+    // block (read into scalar registers once per batch, so an entry's skip test costs no
+    // vector instruction and waits on no LDS read)
+    constexpr int kWords = (M + 63) / 64;
+    __shared__ unsigned long long smask[NT / 64][kWords];
     const uint32_t wt = a.work[blockIdx.x];
     if (wt == kNoTile) return;  // padding of a shorter XCD list (whole workgroup)
     const int tile = (int)wt;
@@ -418,7 +424,6 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     const int wl = (int)__builtin_amdgcn_readfirstlane(wlast);
 
     const float amax = __builtin_canonicalizef(a.st.alpha_max);
-    const uint32_t wbit = 1u << __builtin_amdgcn_readfirstlane(wave);
     // lane L ends the reduction holding slot (L >> 2) & 15; value v of the ten sums sits in
     // slot kSlot[v % 5] + 8 (v / 5), see wave_transpose_sum10
     const int slot = (lane >> 2) & 15, sl = slot & 7;
@@ -441,21 +446,40 @@ __global__ __launch_bounds__(T* T / PPT) void raster_bwd_kernel(RasterBwdArgs a)
     for (int hi = (int)maxlast; hi > 0; hi -= M, buf ^= 1) {
         const int lo = hi - M > 0 ? hi - M : 0;
         if (MERGE) flush(prev_n, sq[buf ^ 1]);  // the previous batch, while this one is staged
-        for (int l = tid; l < hi - lo; l += NT) {
-            const uint32_t q = a.tile_pairs[start + lo + l];
-            stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l], a.grad2d);
-            if (MERGE) sq[buf][l] = q;
+        for (int base = 0; base < hi - lo; base += NT) {  // workgroup-uniform trip count
+            const int l = base + tid;
+            uint32_t m = 0;
+            if (l < hi - lo) {
+                const uint32_t q = a.tile_pairs[start + lo + l];
+                m = stage_record<T, PPT, true>(a.records, q, amin, tc.W, tc.H, tc.px0, tc.py0, srec[l], a.grad2d);
+                if (MERGE) sq[buf][l] = q;
+            }
+            const int l0 = base + 64 * wave;  // this wave's first slot
+            if (l0 < M) {
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) {
+                    const unsigned long long bits = __ballot((m >> w) & 1u);
+                    if (lane == 0) smask[w][l0 >> 6] = bits;
+                }
+            }
         }
         prev_n = hi - lo;
         __syncthreads();
+        unsigned long long mw[kWords];
+#pragma unroll
+        for (int x = 0; x < kWords; ++x) {
+            const unsigned long long v = smask[wave][x];
+            mw[x] = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+        }
         const int jtop = min(hi, wl);  // wave-uniform
         // entries in groups of four, back to front: the group's records are read at immediate
         // offsets from the LDS address of its lowest entry, which moves once per group
         auto entry = [&](const SRec& r, int j, int e) {
+            if (!((mw[e >> 6] >> (e & 63)) & 1ull)) return;  // wave-uniform
             const float4 rm = r.m, r0 = r.g0, r1 = r.g1;
             float* const row = MERGE ? nullptr : r.row;
             use_record(rm, r0, r1);
-            if (!(__builtin_amdgcn_readfirstlane(__float_as_uint(rm.x)) & wbit)) return;  // wave-uniform
             const float z2 = S2 ? r.z2 : 0.f;
             // wave-level pre-test on the exponent alone; the adjoint runs only if some lane
             // passes (every lane that keeps this Gaussian passes: the floor sits a margin below
