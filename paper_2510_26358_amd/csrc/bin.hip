@@ -121,7 +121,12 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
         const uint32_t r = (uint32_t)(k - (long long)s_off[lo]);
         const uint32_t wp = s_wp[lo], org = s_org[lo], wh = s_wh[lo];
         const uint32_t w = wp & 0xFFFFu;
-        const uint32_t row = r / w, col = r - row * w;
+        // r / w through the float reciprocal (r < 2^24, so the estimate is off by at most one),
+        // then corrected exactly
+        uint32_t row = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)w));
+        row -= row * w > r ? 1u : 0u;
+        row += (row + 1u) * w <= r ? 1u : 0u;
+        const uint32_t col = r - row * w;
         const int tx = (int)(org & 0xFFFFu) + (int)col;
         const int ty = (int)(org >> 16) + (int)row;
         const float4 e = s_ell[lo];

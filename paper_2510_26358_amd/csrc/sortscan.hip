@@ -146,51 +146,31 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(
     }
 }
 
-// Scan of the tile counts in depth order (value i = counts[order[i]], i < *n_dev) that also
-// publishes the intersection total: counters[CNT_K] = K, counters[CNT_OVERFLOW] = K >
-// capacity, counters[CNT_KEFF] = min(K, capacity).
-__global__ __launch_bounds__(kScanThreads) void emit_blocksums_kernel(uint32_t* block_sums, long long nb,
-                                                                      uint32_t* counters, long long capacity) {
-    __shared__ uint32_t wave_tot[kScanThreads / 64];
-    uint32_t carry = 0;
-    for (long long base = 0; base < nb; base += kScanTile) {
-        uint32_t v[kScanItems];
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            long long i = base + (long long)threadIdx.x * kScanItems + k;
-            v[k] = i < nb ? block_sums[i] : 0u;
-            s += v[k];
-        }
-        uint32_t tot;
-        uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
-        uint32_t run = carry + incl - s;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            long long i = base + (long long)threadIdx.x * kScanItems + k;
-            if (i < nb) block_sums[i] = run;
-            run += v[k];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        const bool over = (long long)carry > capacity;
-        counters[CNT_K] = carry;
-        counters[CNT_OVERFLOW] = over ? 1u : 0u;
-        counters[CNT_KEFF] = over ? (uint32_t)capacity : carry;
-    }
-}
-
-// Apply phase: out[i] = offset of item i; for every multiple m of kEmitSlots inside item
-// i's range [out[i], out[i] + value) with m < capacity, block_first[m / kEmitSlots] = i (the
-// item owning the first slot of that emission workgroup; every value is >= 1).
+// Scan of the tile counts in depth order (value i = counts[order[i]], i < *n_dev), after
+// scan_reduce_kernel's per-block totals: out[i] = offset of item i; for every multiple m of
+// kEmitSlots inside item i's range [out[i], out[i] + value) with m < capacity,
+// block_first[m / kEmitSlots] = i (the item owning the first slot of that emission
+// workgroup; every value is >= 1); and the intersection total, written by the last block:
+// counters[CNT_K] = K, counters[CNT_OVERFLOW] = K > capacity, counters[CNT_KEFF] =
+// min(K, capacity).
 __global__ __launch_bounds__(kScanThreads) void emit_apply_kernel(
     const uint32_t* counts, const uint32_t* order, uint32_t* out, long long n_max, const uint32_t* n_dev,
-    const uint32_t* block_sums, long long capacity, uint32_t* block_first) {
+    const uint32_t* block_sums, long long capacity, uint32_t* block_first, uint32_t* counters) {
     __shared__ uint32_t wave_tot[kScanThreads / 64];
     const long long n = live_count(n_max, n_dev);
     const long long base = (long long)blockIdx.x * kScanTile;
+    if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        counters[CNT_K] = 0u;
+        counters[CNT_OVERFLOW] = 0u;
+        counters[CNT_KEFF] = 0u;
+    }
     if (base >= n) return;  // uniform per block
+    // the block's offset: the earlier blocks' totals (at most a few hundred), summed here
+    // instead of by a separate scan launch
+    uint32_t pre = 0;
+    for (long long b = threadIdx.x; b < (long long)blockIdx.x; b += kScanThreads) pre += block_sums[b];
+    uint32_t offset;
+    block_inclusive_scan(pre, wave_tot, offset);
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
@@ -201,7 +181,14 @@ __global__ __launch_bounds__(kScanThreads) void emit_apply_kernel(
     }
     uint32_t tot;
     uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
-    uint32_t run = block_sums[blockIdx.x] + incl - s;
+    uint32_t run = offset + incl - s;
+    if (base + kScanTile >= n && threadIdx.x == 0) {  // the last block holds the grand total
+        const uint32_t total = offset + tot;
+        const bool over = (long long)total > capacity;
+        counters[CNT_K] = total;
+        counters[CNT_OVERFLOW] = over ? 1u : 0u;
+        counters[CNT_KEFF] = over ? (uint32_t)capacity : total;
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         long long i = base + (long long)threadIdx.x * kScanItems + k;
@@ -223,10 +210,8 @@ void launch_emit_scan(const uint32_t* counts, const uint32_t* order, uint32_t* o
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, order, false,
                        n_max, n_dev, tmp.block_sums);
-    hipLaunchKernelGGL(emit_blocksums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp.block_sums, nb, counters,
-                       capacity);
     hipLaunchKernelGGL(emit_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, order, out, n_max,
-                       n_dev, tmp.block_sums, capacity, block_first);
+                       n_dev, tmp.block_sums, capacity, block_first, counters);
 }
 
 void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32_t* out,
