@@ -121,8 +121,10 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(ViewTable vt, const 
         const uint32_t r = (uint32_t)(k - (long long)s_off[lo]);
         const uint32_t wp = s_wp[lo], org = s_org[lo], wh = s_wh[lo];
         const uint32_t w = wp & 0xFFFFu;
-        // r / w through the float reciprocal (r < 2^24, so the estimate is off by at most one),
-        // then corrected exactly
+        // r / w through the float reciprocal: the quotient is at most the rectangle's tile rows
+        // (views are under 65,536 pixels a side, so under 2^13 rows), which keeps the float
+        // estimate within a hundredth of it, so truncation is off by at most one; the two
+        // steps below correct that exactly
         uint32_t row = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)w));
         row -= row * w > r ? 1u : 0u;
         row += (row + 1u) * w <= r ? 1u : 0u;
