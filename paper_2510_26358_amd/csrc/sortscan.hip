@@ -92,41 +92,22 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block sums in place; grand total to *total.
-__global__ __launch_bounds__(kScanThreads) void scan_blocksums_kernel(uint32_t* block_sums,
-                                                                      long long nb, uint32_t* total) {
-    __shared__ uint32_t wave_tot[kScanThreads / 64];
-    uint32_t carry = 0;
-    for (long long base = 0; base < nb; base += kScanTile) {
-        uint32_t v[kScanItems];
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            long long i = base + (long long)threadIdx.x * kScanItems + k;
-            v[k] = i < nb ? block_sums[i] : 0u;
-            s += v[k];
-        }
-        uint32_t tot;
-        uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
-        uint32_t run = carry + incl - s;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            long long i = base + (long long)threadIdx.x * kScanItems + k;
-            if (i < nb) block_sums[i] = run;
-            run += v[k];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
+// Apply phase after scan_reduce_kernel's per-block totals: each block adds up the totals of
+// the blocks before it (instead of a separate one-workgroup scan of them), writes the
+// exclusive scan of its items to out (when non-null), and the last block writes the grand
+// total to *total (when non-null).
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(
     const uint32_t* src, const uint32_t* idx, bool flags, uint32_t* out, long long n_max,
-    const uint32_t* n_dev, const uint32_t* block_sums) {
+    const uint32_t* n_dev, const uint32_t* block_sums, uint32_t* total) {
     __shared__ uint32_t wave_tot[kScanThreads / 64];
     const long long n = live_count(n_max, n_dev);
     const long long base = (long long)blockIdx.x * kScanTile;
+    if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0u;
     if (base >= n) return;  // uniform per block
+    uint32_t pre = 0;
+    for (long long b = threadIdx.x; b < (long long)blockIdx.x; b += kScanThreads) pre += block_sums[b];
+    uint32_t offset;
+    block_inclusive_scan(pre, wave_tot, offset);
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
@@ -137,7 +118,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(
     }
     uint32_t tot;
     uint32_t incl = block_inclusive_scan(s, wave_tot, tot);
-    uint32_t run = block_sums[blockIdx.x] + incl - s;
+    if (total && base + kScanTile >= n && threadIdx.x == 0) *total = offset + tot;
+    if (!out) return;
+    uint32_t run = offset + incl - s;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         long long i = base + (long long)threadIdx.x * kScanItems + k;
@@ -221,11 +204,9 @@ void launch_scan(const uint32_t* src, const uint32_t* idx, bool as_flags, uint32
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, idx,
                        as_flags, n_max, n_dev, tmp.block_sums);
-    hipLaunchKernelGGL(scan_blocksums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp.block_sums,
-                       nb, total);
-    if (out)
+    if (out || total)
         hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src,
-                           idx, as_flags, out, n_max, n_dev, tmp.block_sums);
+                           idx, as_flags, out, n_max, n_dev, tmp.block_sums, total);
 }
 
 // ------------------------------------------------------------------------- radix sort
