@@ -180,10 +180,14 @@ def test_refinement_pose_gradient_matches_fp64_finite_differences_every_10_steps
                 fd[j] = (frozen_objective(crop, r["decisions"], s, masks=[keep], lam=0.1, deltas=d) -
                          frozen_objective(crop, r["decisions"], s, masks=[keep], lam=0.1, deltas=-d)) / (2 * h)
             print(f"step {it}: {int(flags['ambiguous'].sum())} ambiguous pixels left out")
+            # each component is a float32 sum over every pixel and Gaussian of the crop; as the
+            # loop converges one component can nearly cancel while its terms stay as large as
+            # the others, so components are held to 1e-3 of the largest one and the vector to
+            # 1e-3 in norm
             err = np.abs(g_gpu - fd)
-            scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
+            scale = np.abs(fd).max()
             print(f"step {it}: gpu {np.array2string(g_gpu, precision=5)} fd {np.array2string(fd, precision=5)} "
-                  f"max rel {np.max(err / scale):.2e}")
+                  f"max err / max |fd| {np.max(err) / scale:.2e}")
             assert np.linalg.norm(g_gpu - fd) <= 1e-3 * np.linalg.norm(fd)
             assert np.all(err <= 1e-3 * scale)
         if it < 50:
