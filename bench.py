@@ -734,8 +734,8 @@ def main():
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
-              f"design in DESIGN.md, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); sharding the path across "
+              f"GPUs is described, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
