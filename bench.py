@@ -8,7 +8,7 @@ the rendered state has means jittered by 1 cm and poses perturbed; LiDAR depth t
 LiDAR adjoint, raster backward with the fused L1 prologue, projection/pose backward -- all
 views in one launch per stage.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this build uses one GPU.
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: the measurement is of one GPU.
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+bwd Mpixel/s, batched multi-view vs per-view loop, at oracle tolerance"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32 peak (packed, 2-wide FP32 instructions)
-# Attainable without packed FP32 (disabled for all device code in this build): a wave64
+# Attainable without packed FP32 (the library compiles all device code without it): a wave64
 # FP32 instruction occupies a 16-lane SIMD for 4 cycles, so 256 CU x 4 SIMD x 16 lanes x
 # 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s; reported beside the published peak.
 FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12

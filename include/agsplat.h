@@ -54,7 +54,7 @@ enum {
     AGS_ERR_WORKSPACE = -2,     /* a buffer is smaller than ags_buffer_sizes requires */
     AGS_ERR_CAPACITY = -3,      /* intersection capacity known on the host to be too small */
     AGS_ERR_HIP = -4,           /* a HIP runtime call failed (see ags_last_hip_error) */
-    AGS_ERR_NOT_SUPPORTED = -5  /* valid request this build does not implement */
+    AGS_ERR_NOT_SUPPORTED = -5  /* valid request the library does not implement */
 };
 
 /* Rendering settings.  The paper defers these to "standard 3DGS"; the defaults of
