@@ -33,7 +33,7 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X published vector FP32 peak (packed, 2-wide F
 # 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s; reported beside the published peak.
 FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRIALS = 5  # timing: median over this many trials of `steps` replays each
-# Algorithmic FLOP per (pixel, Gaussian) pair evaluated (scope table): forward ~20 + 1 exp,
+# Algorithmic FLOP per (pixel, Gaussian) pair evaluated: forward ~20 + 1 exp,
 # backward ~60 + 1 exp; the exp is counted as one FLOP.
 FLOP_PER_PAIR = {"raster_fwd": 21, "raster_bwd": 61}
 # Algorithmic FLOP of the D-SSIM term per pixel and colour channel (no halo recomputation):
@@ -310,7 +310,8 @@ def measured_traffic(stage, workload, launch=None):
 
 def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload, launch=None):
     """Roofline of the slowest stage, from the library's per-stage HIP events over a timed
-    pass (events on the launch stream).  Algorithmic work per launch is stated in the design doc."""
+    pass (events on the launch stream); the algorithmic work of one launch is the work unit (one
+    (pixel, Gaussian) pair of the raster kernels) times its FLOP."""
     import torch
     stages = {k: v for k, v in prof.items() if v[1] > 0}
     name = max(stages, key=lambda k: stages[k][0])
@@ -350,7 +351,7 @@ def dominant_roofline(prof, views, buf, sizes, n_steps, n_gauss, sh_k, workload,
 
 def stage_rooflines(stage_ms, evals, P, N, sh_k, Q, V, K, n_targets, step_ms, fused_adam=False):
     """Every stage against its bound from the per-stage HIP-event times: algorithmic bytes
-    (HBM-bound stages) or FLOP (raster) per launch, as listed in the design doc; plus the whole
+    (HBM-bound stages) or FLOP (raster) per launch, from the sizes below; plus the whole
     step's algorithmic bytes over its time (the HBM fraction of the step).  With the fused
     backward + Adam the projection backward also carries Adam's bytes, less the SH gradient's
     write and re-read and the second read of the SH coefficients.  The backward's accumulators

@@ -22,7 +22,7 @@ What it computes, and where the paper defines it (AgriGS-SLAM, arXiv 2510.26358)
     names no optimiser; this follows the refinement workload's stated setup).
 
 Readings where the paper is silent (cutoffs, tile size, pixel centres, background, SH
-convention, normalisations) are listed in the design doc and fixed in `RenderSettings`.
+convention, normalisations) are fixed in `RenderSettings`.
 
 Parity status: every function here is pinned by the `-m "not gpu"` tests in
 `tests/test_oracle_*.py` (closed forms, invariants, library special cases, Monte Carlo,

@@ -3,7 +3,7 @@ densification (split / duplicate) and opacity reset, Sec. III-B "Gaussian Splats
 Operations".
 
 The paper fixes tau_opa = 0.01 and the size bounds 5e-5 < s < 0.3 and leaves gamma_g, kappa,
-s_init, tau_reset and the split rule unstated; the readings (recorded in the design doc):
+s_init, tau_reset and the split rule unstated; the readings taken here:
   * size s_j = the largest of the three scales, exp(max log-scale);
   * densification statistic g_j = (sum over views seeing j of |dL/d(u, v)|, pixel units) /
     (number of those views), accumulated by the backward;

@@ -1,6 +1,6 @@
 """Rendering constants the paper leaves unstated (it defers to "standard 3DGS").
 
-Each value is a reading, recorded in the design doc; the oracle and the kernels receive the same
+Each value is a reading of the paper; the oracle and the kernels receive the same
 numbers at run time, so a different reading changes inputs, not code.
 """
 from dataclasses import dataclass, field

@@ -2,8 +2,8 @@
 photometric loss (oracle; tests only).
 
 The photometric loss of Sec. III-C is L_3DGS = (1 - lambda) L1 + lambda L_D-SSIM, the loss of
-standard 3DGS.  The paper gives neither lambda nor the SSIM constants; the readings (recorded
-in the design doc) are the usual ones:
+standard 3DGS.  The paper gives neither lambda nor the SSIM constants; the readings taken
+here are the usual ones:
     L_D-SSIM = 1 - SSIM, SSIM the mean over pixels and colour channels of the SSIM map
     s = ((2 mu_x mu_y + C1)(2 sigma_xy + C2)) / ((mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2)),
 with local statistics weighted by an 11 x 11 Gaussian window (sigma 1.5, normalised to sum 1),

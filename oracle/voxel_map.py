@@ -5,7 +5,7 @@ to host memory above a threshold tau, reload when a key is met again).
 A plain, slow, dictionary-based statement of what one insertion call, and the map's side of
 one lifecycle pass (Sec. III-B "Gaussian Splats Lifecycle Operations"), compute.  The paper
 leaves v, P1..P3, tau, the initial splat, the order of the resident set and how pruned and
-densified splats relate to the voxel keys unstated; the readings (recorded in the design doc):
+densified splats relate to the voxel keys unstated; the readings taken here:
   * key: c = floor(p / v) per axis with the division and the floor in float32 (the points'
     precision), k = (c_x P1 + c_y P2 + c_z P3) mod 2^64.  Two voxels whose keys collide are
     merged, as key matching implies.  The key 2^64 - 1 is reserved and replaced by 2^64 - 2.
